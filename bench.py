@@ -1,0 +1,167 @@
+"""Benchmark: double-double GEMM C := AB at n = 4096 on one MI355X.
+
+One step = one DD product C := AB of two 4096 x 4096 double-double matrices
+(hi/lo planes, synthetic: hi ~ U[-1,1], lo inside hi's half-ulp), inputs and
+output resident in HBM.  The algorithm (block kernel, or Winograd's Strassen
+of depth 1 or 2 over it) is chosen by timing each once after warm-up, then
+exactly --steps products of the chosen algorithm are timed.
+
+Printed (one JSON line): DD Gflop/s = 2 n^3 / t (Strassen counted by the
+same conventional 2 n^3), the roofline of the dominant kernel (the grouped
+multiply-add launch, FP64 VALU issue bound, measured with HIP events on the
+library's stream), and the CPU oracle's rate on a bounded row slab.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 VALU operations per DD multiply-add in the block kernel: 10 in the
+# accumulation step plus an exact 6-op TwoSum every 8 steps.
+DD_OPS_PER_MADD = 10.0 + 6.0 / 8.0
+# MI355X FP64 VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+FP64_ISSUE_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--n", type=int, default=4096)
+    p.add_argument("--algo", default="auto", help="auto | block | strassen1 | strassen2")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="target CPU time of the oracle sample")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a plain 1 GiB device copy (PMC traffic calibration)")
+    return p.parse_args()
+
+
+def cpu_baseline(n: int, target_s: float):
+    """The oracle's step-by-step DD simple algorithm (Eq. 1) on a slab of r
+    rows of A against the full B, all host threads; rate scaled to the
+    metric's unit (DD Gflop/s, 2 r n n / t)."""
+    from oracle import cref
+    from paper_1710_01839_amd import inputs
+    A = inputs.dd_uniform(n, n, 20)
+    B = inputs.dd_uniform(n, n, 21)
+    threads = cref.max_threads()
+    rows = max(1, threads // 2)
+    while True:
+        As = tuple(a[:rows].copy() for a in A)
+        t0 = time.perf_counter()
+        cref.gemm_simple(As, B, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.3 * target_s or rows >= n:
+            break
+        rows = min(n, int(rows * max(2.0, 0.6 * target_s / max(dt, 1e-3))))
+    return {"value": 2.0 * rows * n * n / dt / 1e9, "unit": "DD Gflop/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"rows 0..{rows - 1} of A ({rows}x{n}) times the full {n}x{n} B, DD simple "
+                      f"algorithm (Eq. 1) step by step, {dt:.1f} s on {threads} threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this product is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1710_01839_amd import build as hipbuild
+    if not os.path.exists(hipbuild.OUT):
+        hipbuild.build()
+    from paper_1710_01839_amd import inputs, mpgemm as M
+
+    n = args.n
+    ctx = M.Context(0)
+    A = M.to_device(inputs.dd_uniform(n, n, 20))
+    B = M.to_device(inputs.dd_uniform(n, n, 21))
+    C = M.empty_like_limbs(n, n, 2)
+
+    cands = {"block": ("block", None), "strassen1": ("strassen", {"depth": 1}),
+             "strassen2": ("strassen", {"depth": 2})}
+
+    def step(key):
+        algo, tile = cands[key]
+        M.mpgemm_dd(ctx, A, B, C, algo=algo, tile=tile)
+
+    # warm-up (also the algorithm choice when --algo auto)
+    times = {}
+    keys = list(cands) if args.algo == "auto" else [args.algo]
+    for key in keys:
+        for _ in range(max(1, args.warmup)):
+            step(key)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(key)
+        torch.cuda.synchronize()
+        times[key] = time.perf_counter() - t0
+    key = min(times, key=times.get)
+
+    if args.calibrate_copy:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    ctx.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(key)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gemm_ms, gemm_n = ctx.prof_read(M.MPG_KCLASS_GEMM)
+    aux_ms, aux_n = ctx.prof_read(M.MPG_KCLASS_AUX)
+    ctx.prof_enable(False)
+
+    ms_per_step = elapsed / args.steps * 1e3
+    value = 2.0 * n ** 3 * args.steps / elapsed / 1e9
+    depth = cands[key][1]["depth"] if cands[key][1] else 0
+    madds_per_launch = (7 / 8) ** depth * n ** 3
+    launch_ms = gemm_ms / max(gemm_n, 1)
+    achieved = madds_per_launch * DD_OPS_PER_MADD / (launch_ms * 1e-3) / 1e12
+    rec = {
+        "metric": "DD GEMM Gflop/s at n=4096 (% FP64 peak)",
+        "value": round(value, 1),
+        "unit": "DD Gflop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"double-double square GEMM C=AB, n={n}, hi~U[-1,1], lo in hi's half-ulp",
+                   "n": n, "algo": cands[key][0], "strassen_depth": depth,
+                   "tile": M.variants(2)[0], "candidates_ms": {k: round(v * 1e3, 3) for k, v in times.items()}},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_ISSUE_PEAK_TOPS,
+                     "unit": "TOP/s (FP64 VALU lane-ops)", "frac": round(achieved / FP64_ISSUE_PEAK_TOPS, 4),
+                     "traffic": None,
+                     "kernel": "grouped DD block multiply-add launch",
+                     "launch_ms": round(launch_ms, 4), "launches": gemm_n,
+                     "ops_per_launch": madds_per_launch * DD_OPS_PER_MADD,
+                     "aux_ms_per_step": round(aux_ms / args.steps, 4)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

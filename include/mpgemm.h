@@ -1,0 +1,143 @@
+/*
+ * mpgemm.h -- C ABI of the MI355X (gfx950) multiple-precision dense matrix
+ * multiplication library libmpgemm.so.
+ *
+ * The library computes C := AB (Section 2 of Kouya, "Tuning Technique for
+ * Multiple Precision Dense Matrix Multiplication using Prediction of
+ * Computational Time", arXiv:1710.01839), A m x l, B l x n, C m x n, in
+ * double-double (DD, two FP64 limbs) or quad-double (QD, four limbs)
+ * arithmetic, by the simple algorithm (Eq. 1), the block algorithm (Eq. 2)
+ * or Strassen's recursion (Eq. 3, Winograd's variant of it), and chooses
+ * among them with the tuning procedure of Section 3.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major limb planes: a DD matrix is two separate FP64
+ *     arrays (hi, lo), a QD matrix four; element (i, j) of a plane with
+ *     leading dimension ld is at offset i*ld + j.  lda >= l, ldb >= n,
+ *     ldc >= n.  Inputs must be canonical (each limb at most half an ulp of
+ *     the limb before it) and finite with magnitude below 2^900.
+ *   - All matrix pointers are DEVICE pointers owned by the caller.  The
+ *     library owns only its workspace (cached in the context) and the
+ *     objects it creates.
+ *   - Calls are asynchronous on the context's stream (mpg_set_stream); C is
+ *     valid once that stream has completed the call.
+ *   - C := AB overwrites C.  m == 0 or n == 0 is a no-op; l == 0 sets C = 0.
+ *   - C must not overlap A or B (MPG_ERR_ALIAS).
+ *   - Every call returns an mpg_status.  Argument errors are detected before
+ *     anything is launched.  A HIP failure returns MPG_ERR_HIP and
+ *     mpg_last_error() holds the HIP error name.
+ *   - One context must not be used by two host threads at once.
+ */
+#ifndef MPGEMM_H
+#define MPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpg_ctx mpg_ctx;
+
+typedef enum {
+  MPG_OK = 0,
+  MPG_ERR_ARG = -1,         /* invalid argument (null pointer, bad size or ld) */
+  MPG_ERR_UNSUPPORTED = -2, /* a tile / algorithm combination that is not built */
+  MPG_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  MPG_ERR_NOMEM = -4,       /* workspace allocation failed */
+  MPG_ERR_ALIAS = -5,       /* C overlaps A or B */
+  MPG_ERR_STATE = -6        /* object in the wrong state (e.g. MLP not trained) */
+} mpg_status;
+
+typedef enum {
+  MPG_AUTO = 0,     /* use the context's tuning table, else a default */
+  MPG_SIMPLE = 1,   /* Eq. (1): one thread per c_ij, k in order */
+  MPG_BLOCK = 2,    /* Eq. (2): LDS-staged tiles, register-blocked accumulators */
+  MPG_STRASSEN = 3, /* Eq. (3), Winograd's form, `depth` levels over MPG_BLOCK */
+  MPG_OZAKI = 4     /* split-precision INT8 product (mpgemm_ozaki_dd only) */
+} mpg_algo;
+
+/* Tile / algorithm parameters.  Zero fields mean "library default".
+ * (bm, bn, bk, tm, tn) must name one of the built block-kernel variants
+ * (mpg_num_variants / mpg_variant), otherwise MPG_ERR_UNSUPPORTED.  The
+ * paper's block size n_min corresponds to the C tile (bm x bn) and its
+ * K-step bk. */
+typedef struct {
+  int bm, bn, bk; /* C tile of one workgroup and K step staged in LDS */
+  int tm, tn;     /* per-thread register block */
+  int depth;      /* Strassen recursion depth (MPG_STRASSEN), 1..3 */
+  int slices;     /* Ozaki slice count (MPG_OZAKI) */
+} mpg_tile;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  The stream defaults to the
+ * null stream.  *ctx receives the new context. */
+int mpg_create(mpg_ctx** ctx, int device);
+/* Free the context, its workspace and cached objects (synchronises its
+ * stream first).  NULL is accepted. */
+int mpg_destroy(mpg_ctx* ctx);
+/* Set the stream (a hipStream_t passed as void*) used by later calls. */
+int mpg_set_stream(mpg_ctx* ctx, void* hip_stream);
+/* Static text of a status code. */
+const char* mpg_status_string(int status);
+/* Detail of the last error on this context ("" if none). */
+const char* mpg_last_error(const mpg_ctx* ctx);
+
+/* ---- block-kernel variants -------------------------------------------- */
+
+/* Number of built block-kernel tile variants (DD: precision 2, QD: 4). */
+int mpg_num_variants(int precision);
+/* Fill *tile with variant `index` of the given precision. */
+int mpg_variant(int precision, int index, mpg_tile* tile);
+
+/* ---- DD GEMM ---------------------------------------------------------- */
+
+/* C := A B in double-double.  A = A_hi + A_lo (m x l), B = B_hi + B_lo
+ * (l x n), C = C_hi + C_lo (m x n).  algo MPG_SIMPLE, MPG_BLOCK or
+ * MPG_STRASSEN (tile->depth levels of Winograd's recursion over the block
+ * kernel, odd or non-tile dimensions zero-padded in workspace), or MPG_AUTO.
+ * tile may be NULL.  Error: componentwise |C - AB|_ij <= 8 l 2^-104
+ * (|A||B|)_ij for SIMPLE and BLOCK; STRASSEN obeys a normwise bound that
+ * grows with depth.  SIMPLE and BLOCK give bitwise identical results. */
+int mpgemm_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
+              const double* A_hi, const double* A_lo, int64_t lda,
+              const double* B_hi, const double* B_lo, int64_t ldb,
+              double* C_hi, double* C_lo, int64_t ldc,
+              mpg_algo algo, const mpg_tile* tile);
+
+/* ---- QD GEMM ---------------------------------------------------------- */
+
+/* C := A B in quad-double.  A, B and C are arrays of four limb-plane
+ * pointers (leading limb first), each plane row-major with the given
+ * leading dimension.  algo MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN or MPG_AUTO
+ * as for mpgemm_dd.  Error: componentwise |C - AB|_ij <= 8 l 2^-208
+ * (|A||B|)_ij for SIMPLE and BLOCK (bitwise identical to each other). */
+int mpgemm_qd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
+              const double* const A[4], int64_t lda,
+              const double* const B[4], int64_t ldb,
+              double* const C[4], int64_t ldc,
+              mpg_algo algo, const mpg_tile* tile);
+
+/* ---- kernel timing (HIP events on the context stream) ------------------ */
+
+/* Kernel classes timed when profiling is on. */
+typedef enum {
+  MPG_KCLASS_GEMM = 0,    /* the multiply-add kernel of a call (simple/block/grouped) */
+  MPG_KCLASS_AUX = 1,     /* O(n^2) kernels: Strassen operands/assembly, slicing, scans */
+  MPG_KCLASS_COUNT = 2
+} mpg_kclass;
+
+/* Turn event timing of every launch on (1) or off (0); turning it on clears
+ * the counters. */
+int mpg_prof_enable(mpg_ctx* ctx, int on);
+/* Synchronise the recorded events and return total milliseconds and number
+ * of launches of kernel class `kclass` since profiling was enabled. */
+int mpg_prof_read(mpg_ctx* ctx, int kclass, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPGEMM_H */

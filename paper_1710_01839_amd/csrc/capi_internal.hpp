@@ -1,0 +1,67 @@
+// Host-side internals shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <functional>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mpgemm.h"
+#include "internal.hpp"
+
+struct mpg_mlp_state;  // mlp_host.cpp
+
+struct mpg_ctx {
+  int device = 0;
+  int num_cu = 256;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+
+  // workspace (grow-only, freed with the context)
+  void* ws = nullptr;
+  size_t ws_size = 0;
+  bool alloc_hook_fail = false;  // test seam: make the next allocations fail
+
+  // kernel timing
+  bool prof = false;
+  struct Rec {
+    int kclass;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> prof_recs;
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms[MPG_KCLASS_COUNT] = {0.0, 0.0};
+  int64_t prof_n[MPG_KCLASS_COUNT] = {0, 0};
+
+  // tuning table: (precision, m, n, l) -> (algo, tile)
+  std::map<std::tuple<int, int64_t, int64_t, int64_t>, std::pair<int, mpg_tile>> table;
+
+  // learned time model (owned)
+  mpg_mlp_state* mlp = nullptr;
+};
+
+int mpg_fail(mpg_ctx* c, int status, const char* fmt, ...);
+int mpg_hip_fail(mpg_ctx* c, hipError_t e, const char* where);
+int mpg_device_guard(mpg_ctx* c);
+int mpg_workspace(mpg_ctx* c, size_t bytes, void** out);
+int mpg_launch(mpg_ctx* c, int kclass, const std::function<hipError_t()>& fn, const char* what);
+size_t mpg_span_bytes(int64_t rows, int64_t cols, int64_t ld);
+int mpg_check_gemm_args(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
+                        const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
+                        double* const* C, int64_t ldc);
+int mpg_resolve_variant(mpg_ctx* c, int precision, const mpg_tile* t, int* variant);
+int mpg_strassen(mpg_ctx* c, int limbs, int depth, int variant, int64_t m, int64_t n, int64_t l,
+                 const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
+                 double* const* C, int64_t ldc);
+int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
+                    const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
+                    double* const* C, int64_t ldc, mpg_algo algo, const mpg_tile* tile);
+
+// tuning table (tuner.cpp)
+bool mpg_table_lookup(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l, int* algo,
+                      mpg_tile* tile);
+// cached objects owned by the context (MLP state)
+void mpg_destroy_cached(mpg_ctx* c);

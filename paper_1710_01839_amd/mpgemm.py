@@ -1,0 +1,215 @@
+"""Thin ctypes binding of libmpgemm.so (include/mpgemm.h).
+
+Argument marshalling only: torch tensors (float64, CUDA/HIP device, row-major
+with unit column stride) are turned into device pointers, sizes and leading
+dimensions, the calls run on torch's current stream, and every non-zero
+status raises MpgemmError.  All arithmetic happens in the HIP library; if it
+is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpgemm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MPG_OK, MPG_ERR_ARG, MPG_ERR_UNSUPPORTED, MPG_ERR_HIP, MPG_ERR_NOMEM, MPG_ERR_ALIAS, MPG_ERR_STATE = \
+    0, -1, -2, -3, -4, -5, -6
+MPG_AUTO, MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN, MPG_OZAKI = 0, 1, 2, 3, 4
+MPG_KCLASS_GEMM, MPG_KCLASS_AUX = 0, 1
+ALGOS = {"auto": MPG_AUTO, "simple": MPG_SIMPLE, "block": MPG_BLOCK,
+         "strassen": MPG_STRASSEN, "ozaki": MPG_OZAKI}
+
+
+class mpg_tile(ctypes.Structure):
+    _fields_ = [("bm", ctypes.c_int), ("bn", ctypes.c_int), ("bk", ctypes.c_int),
+                ("tm", ctypes.c_int), ("tn", ctypes.c_int), ("depth", ctypes.c_int),
+                ("slices", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MpgemmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_ci = ctypes.c_int
+_pp = ctypes.POINTER(ctypes.c_void_p)
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("mpg_create", [ctypes.POINTER(_vp), _ci])
+_sig("mpg_destroy", [_vp])
+_sig("mpg_set_stream", [_vp, _vp])
+_sig("mpg_status_string", [_ci], ctypes.c_char_p)
+_sig("mpg_last_error", [_vp], ctypes.c_char_p)
+_sig("mpg_num_variants", [_ci])
+_sig("mpg_variant", [_ci, _ci, ctypes.POINTER(mpg_tile)])
+_sig("mpgemm_dd", [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _ci,
+                   ctypes.POINTER(mpg_tile)])
+_sig("mpgemm_qd", [_vp, _i64, _i64, _i64, _pp, _i64, _pp, _i64, _pp, _i64, _ci,
+                   ctypes.POINTER(mpg_tile)])
+_sig("mpg_prof_enable", [_vp, _ci])
+_sig("mpg_prof_read", [_vp, _ci, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
+
+
+def lib():
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return _lib.mpg_status_string(status).decode()
+
+
+class Context:
+    """Owns an mpg_ctx on one device; every call uses torch's current stream."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        h = _vp()
+        st = _lib.mpg_create(ctypes.byref(h), device)
+        if st != MPG_OK:
+            raise MpgemmError(st, "mpg_create: " + status_string(st))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _lib.mpg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int, what: str):
+        if st != MPG_OK:
+            detail = _lib.mpg_last_error(self.handle).decode()
+            raise MpgemmError(st, f"{what}: {status_string(st)}: {detail}")
+
+    def bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.mpg_set_stream(self.handle, _vp(s))
+
+    # --- kernel timing -------------------------------------------------
+    def prof_enable(self, on: bool = True):
+        self.check(_lib.mpg_prof_enable(self.handle, int(on)), "mpg_prof_enable")
+
+    def prof_read(self, kclass: int = MPG_KCLASS_GEMM):
+        ms = ctypes.c_double()
+        n = _i64()
+        self.check(_lib.mpg_prof_read(self.handle, kclass, ctypes.byref(ms), ctypes.byref(n)),
+                   "mpg_prof_read")
+        return ms.value, n.value
+
+
+def make_tile(tile=None) -> mpg_tile | None:
+    if tile is None:
+        return None
+    if isinstance(tile, mpg_tile):
+        return tile
+    t = mpg_tile()
+    for k, v in dict(tile).items():
+        setattr(t, k, int(v))
+    return t
+
+
+def variants(precision: int = 2):
+    out = []
+    for i in range(_lib.mpg_num_variants(precision)):
+        t = mpg_tile()
+        _lib.mpg_variant(precision, i, ctypes.byref(t))
+        out.append(t.as_dict())
+    return out
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp(0)
+
+
+def _mat(t: torch.Tensor, name: str):
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise MpgemmError(MPG_ERR_ARG, f"{name} must be a float64 device tensor")
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise MpgemmError(MPG_ERR_ARG, f"{name} must be 2-D with unit column stride")
+    return t.shape[0], t.shape[1], max(t.stride(0), 1)
+
+
+def mpgemm_dd(ctx: Context, A, B, C, algo="block", tile=None):
+    """C := A B in double-double.  A, B, C: (hi, lo) tuples of tensors."""
+    m, l, lda = _mat(A[0], "A_hi")
+    l2, n, ldb = _mat(B[0], "B_hi")
+    m2, n2, ldc = _mat(C[0], "C_hi")
+    if l2 != l or m2 != m or n2 != n:
+        raise MpgemmError(MPG_ERR_ARG, f"shape mismatch {tuple(A[0].shape)} {tuple(B[0].shape)} "
+                                       f"{tuple(C[0].shape)}")
+    for t, nm in ((A[1], "A_lo"), (B[1], "B_lo"), (C[1], "C_lo")):
+        _mat(t, nm)
+    t = make_tile(tile)
+    ctx.bind_stream()
+    st = _lib.mpgemm_dd(ctx.handle, m, n, l, _ptr(A[0]), _ptr(A[1]), lda, _ptr(B[0]), _ptr(B[1]),
+                        ldb, _ptr(C[0]), _ptr(C[1]), ldc, ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
+                        ctypes.byref(t) if t is not None else None)
+    ctx.check(st, "mpgemm_dd")
+    return C
+
+
+def _limb_array(ts):
+    arr = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in ts])
+    return ctypes.cast(arr, _pp), arr
+
+
+def mpgemm_qd(ctx: Context, A, B, C, algo="block", tile=None):
+    """C := A B in quad-double.  A, B, C: 4-tuples of limb tensors."""
+    m, l, lda = _mat(A[0], "A[0]")
+    l2, n, ldb = _mat(B[0], "B[0]")
+    m2, n2, ldc = _mat(C[0], "C[0]")
+    if l2 != l or m2 != m or n2 != n:
+        raise MpgemmError(MPG_ERR_ARG, "shape mismatch")
+    for q in range(4):
+        _mat(A[q], f"A[{q}]"); _mat(B[q], f"B[{q}]"); _mat(C[q], f"C[{q}]")
+    pa, ka = _limb_array(A)
+    pb, kb = _limb_array(B)
+    pc, kc = _limb_array(C)
+    t = make_tile(tile)
+    ctx.bind_stream()
+    st = _lib.mpgemm_qd(ctx.handle, m, n, l, pa, lda, pb, ldb, pc, ldc,
+                        ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
+                        ctypes.byref(t) if t is not None else None)
+    ctx.check(st, "mpgemm_qd")
+    return C
+
+
+def empty_like_limbs(m: int, n: int, limbs: int, device="cuda"):
+    return tuple(torch.empty((m, n), dtype=torch.float64, device=device) for _ in range(limbs))
+
+
+def to_device(planes, device="cuda"):
+    return tuple(torch.as_tensor(p).to(device=device, dtype=torch.float64).contiguous() for p in planes)
+
+
+def to_host(planes):
+    return tuple(p.detach().cpu().numpy() for p in planes)
