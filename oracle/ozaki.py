@@ -1,0 +1,150 @@
+"""Split-precision (Ozaki-scheme) product, written out plainly.
+
+TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark CPU baseline).
+
+The method (Ozaki, Ogita, Oishi and Rump's error-free splitting, in the
+INT8 form of Ootomo, Ozaki and Yokota) reaches double-double accuracy from
+products of small integers:
+
+1. row scale e_i: the smallest integer with max_k |a_ik| < 2^e_i (0 for a
+   zero row); column scale f_j of B likewise;
+2. x = a_ik 2^-e_i lies in (-1, 1); its digits are taken by truncation,
+   y_0 = x, y_s = 128 y_{s-1} - D_s with D_s = trunc(128 y_{s-1}) in
+   [-127, 127] -- every step exact in binary64 -- so
+   a_ik = 2^e_i (sum_s D_s 2^-7s + 2^-7S y_S);
+3. for each kept pair of digit planes (s, t) the integer product
+   D_A^(s) D_B^(t) is exact; pairs on one diagonal g = s + t share the
+   weight 2^(e_i + f_j - 7g);
+4. C_ij = sum_g 2^(e_i + f_j - 7g) G_g[i, j].
+
+Pairs kept: all S^2 ('all') or the triangle s + t <= S + 1 ('triangle').
+This module forms the digit planes exactly, the diagonal sums with int64
+matrix products and the combination exactly in Python integers, then rounds
+to double-double (nearest, limb by limb).
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+from oracle import exact
+
+
+def row_exponents(A: np.ndarray) -> np.ndarray:
+    M = np.abs(A).max(axis=1) if A.shape[1] else np.zeros(A.shape[0])
+    _, E = np.frexp(M)              # M = f 2^E with 0.5 <= f < 1, so M < 2^E
+    return np.where(M > 0, E, 0).astype(np.int64)
+
+
+def col_exponents(B: np.ndarray) -> np.ndarray:
+    return row_exponents(np.ascontiguousarray(B.T))
+
+
+def split_rows(X: np.ndarray, e: np.ndarray, S: int):
+    """Digit planes (S arrays of int8, same shape as X) of X scaled by 2^-e_i
+    per row, and the scaled remainder y_S."""
+    y = np.ldexp(X, -e[:, None])
+    digits = []
+    for _ in range(S):
+        y = y * 128.0
+        d = np.trunc(y)
+        y = y - d
+        digits.append(d.astype(np.int8))
+    return digits, y
+
+
+def split_cols(X: np.ndarray, f: np.ndarray, S: int):
+    d, y = split_rows(np.ascontiguousarray(X.T), f, S)
+    return [np.ascontiguousarray(x.T) for x in d], np.ascontiguousarray(y.T)
+
+
+def slices_needed_rows(X: np.ndarray, e: np.ndarray) -> int:
+    """Smallest S for which split_rows reproduces every entry exactly:
+    ceil((e_i - exponent of the lowest set bit of x) / 7), maximised."""
+    M, E = exact._mant_exp(X)
+    nz = M != 0
+    if not nz.any():
+        return 0
+    Mabs = np.abs(M[nz])
+    tz = np.zeros(Mabs.shape, dtype=np.int64)
+    for b in range(53):
+        tz += ((Mabs >> b) & 1 == 0) & (tz == b)
+    low = E[nz] + tz                           # x = odd * 2^low
+    eb = np.broadcast_to(e[:, None], X.shape)[nz]
+    bits = eb - low
+    return int(max(0, np.ceil(bits.max() / 7)))
+
+
+def slices_exact(A: np.ndarray, B: np.ndarray) -> int:
+    return max(slices_needed_rows(A, row_exponents(A)),
+               slices_needed_rows(np.ascontiguousarray(B.T), col_exponents(B)))
+
+
+def pairs(S: int, mode: str = "all"):
+    """Kept (s, t), 1-based."""
+    out = []
+    for s in range(1, S + 1):
+        for t in range(1, S + 1):
+            if mode == "all" or s + t <= S + 1:
+                out.append((s, t))
+    return out
+
+
+def group_sums(DA, DB, S: int, mode: str = "all"):
+    """{g: sum over kept pairs with s + t = g of D_A^(s) D_B^(t)} (int64)."""
+    G = {}
+    for s, t in pairs(S, mode):
+        P = DA[s - 1].astype(np.int64) @ DB[t - 1].astype(np.int64)
+        G[s + t] = G.get(s + t, 0) + P
+    return G
+
+
+def combine_exact(G, e: np.ndarray, f: np.ndarray):
+    """Exact C_ij = sum_g 2^(e_i + f_j - 7 g) G_g[i, j], returned as an
+    object array of integers N and the exponent E0 with C = N 2^E0, where
+    the common exponent is per entry: E0_ij = e_i + f_j - 7 gmax."""
+    gmax = max(G)
+    N = None
+    for g, Gg in G.items():
+        term = Gg.astype(object) * (1 << (7 * (gmax - g)))
+        N = term if N is None else N + term
+    E0 = (e[:, None] + f[None, :] - 7 * gmax).astype(np.int64)
+    return N, E0
+
+
+def to_fraction(N, E0, idx) -> Fraction:
+    k = int(E0[idx])
+    return Fraction(int(N[idx])) * (Fraction(2) ** k)
+
+
+def ozaki_dd(A: np.ndarray, B: np.ndarray, S: int, mode: str = "all"):
+    """The split-precision product rounded to double-double, plus the exact
+    pieces (N, E0) of the value before rounding."""
+    e, f = row_exponents(A), col_exponents(B)
+    DA, _ = split_rows(A, e, S)
+    DB, _ = split_cols(B, f, S)
+    G = group_sums(DA, DB, S, mode)
+    N, E0 = combine_exact(G, e, f)
+    hi = np.zeros(N.shape)
+    lo = np.zeros(N.shape)
+    for idx in np.ndindex(N.shape):
+        h, l_ = exact.round_to_limbs(to_fraction(N, E0, idx), 2)
+        hi[idx], lo[idx] = h, l_
+    return (hi, lo), (N, E0)
+
+
+def apriori_bound(A: np.ndarray, B: np.ndarray, S: int, mode: str = "all"):
+    """Per-entry bound on |C_S - AB|_ij from the truncated slices: every
+    remainder is below 2^(e - 7S) in magnitude, so with all pairs
+    |C_S - AB| <= l 2^(e_i + f_j) 2^-7S (2 + 2^-7S); with the triangle the
+    dropped pairs add l 2^(e_i + f_j) sum_{g > S+1} #pairs_g 127^2 2^-7g."""
+    l = A.shape[1]
+    e, f = row_exponents(A), col_exponents(B)
+    base = l * np.ldexp(1.0, (e[:, None] + f[None, :]).astype(np.int64))
+    b = 2.0 ** (-7 * S) * (2 + 2.0 ** (-7 * S))
+    if mode == "triangle":
+        for g in range(S + 2, 2 * S + 1):
+            cnt = sum(1 for s in range(1, S + 1) if 1 <= g - s <= S)
+            b += cnt * 127 * 127 * 2.0 ** (-7 * g)
+    return base * b

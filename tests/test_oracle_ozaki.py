@@ -1,0 +1,83 @@
+"""Pins of the split-precision oracle: exact reconstruction of the digit
+planes, digit range and sign, exact integer special cases, agreement with
+the exact product when nothing is truncated, and the a-priori truncation
+bound."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import exact, ozaki
+from paper_1710_01839_amd import inputs
+
+
+def test_exponents():
+    A = np.array([[0.5, -0.25], [0.0, 0.0], [3.0, 1.0], [-1.0, 0.75]])
+    assert list(ozaki.row_exponents(A)) == [0, 0, 2, 1]      # max < 2^e, zero row -> 0
+
+
+def test_split_reconstructs_and_digits_in_range():
+    A = inputs.fp64_wide(20, 30, 0)
+    e = ozaki.row_exponents(A)
+    S = ozaki.slices_needed_rows(A, e)
+    assert 10 <= S <= 30
+    D, y = ozaki.split_rows(A, e, S)
+    assert np.all(y == 0.0)
+    for i in range(20):
+        for k in range(30):
+            v = sum(Fraction(int(D[s][i, k]), 128 ** (s + 1)) for s in range(S))
+            assert v * Fraction(2) ** int(e[i]) == Fraction(float(A[i, k]))
+            for s in range(S):
+                d = int(D[s][i, k])
+                assert -127 <= d <= 127
+                assert d == 0 or (d > 0) == (A[i, k] > 0)
+    # one slice fewer leaves a remainder somewhere
+    D2, y2 = ozaki.split_rows(A, e, S - 1)
+    assert np.any(y2 != 0.0)
+
+
+def test_single_slice_integer_product_exact():
+    """Integer entries in [-127, 127] with every row / column maximum >= 64:
+    one slice holds them exactly, so the result is exactly AB."""
+    g = np.random.default_rng(3)
+    A = g.integers(-127, 128, size=(9, 40)).astype(float)
+    B = g.integers(-127, 128, size=(40, 7)).astype(float)
+    A[:, 0] = 127.0
+    B[0, :] = -100.0
+    (hi, lo), (N, E0) = ozaki.ozaki_dd(A, B, 1)
+    want = A.astype(np.int64) @ B.astype(np.int64)
+    for idx in np.ndindex(want.shape):
+        assert ozaki.to_fraction(N, E0, idx) == int(want[idx])
+    assert np.array_equal(hi, want.astype(float))
+
+
+def test_exact_slices_give_exact_product():
+    A = inputs.fp64_wide(6, 25, 1)
+    B = inputs.fp64_wide(25, 5, 2)
+    S = ozaki.slices_exact(A, B)
+    (hi, lo), (N, E0) = ozaki.ozaki_dd(A, B, S, "all")
+    Ci, s = exact.matmul_exact((A,), (B,))
+    for idx in np.ndindex(hi.shape):
+        assert ozaki.to_fraction(N, E0, idx) == Fraction(int(Ci[idx]), 2 ** s)
+
+
+@pytest.mark.parametrize("mode", ["all", "triangle"])
+@pytest.mark.parametrize("S", [3, 6, 10])
+def test_truncated_within_apriori_bound(S, mode):
+    A = inputs.fp64_wide(8, 50, 3)
+    B = inputs.fp64_wide(50, 6, 4)
+    (hi, lo), (N, E0) = ozaki.ozaki_dd(A, B, S, mode)
+    Ci, s = exact.matmul_exact((A,), (B,))
+    bound = ozaki.apriori_bound(A, B, S, mode)
+    worst = 0.0
+    for idx in np.ndindex(hi.shape):
+        err = abs(ozaki.to_fraction(N, E0, idx) - Fraction(int(Ci[idx]), 2 ** s))
+        assert err <= Fraction(float(bound[idx]))
+        worst = max(worst, float(err) / bound[idx])
+    assert worst > 0          # truncation does lose something at these S
+
+
+def test_pair_sets():
+    assert len(ozaki.pairs(5, "all")) == 25
+    assert len(ozaki.pairs(5, "triangle")) == 15
+    assert all(s + t <= 6 for s, t in ozaki.pairs(5, "triangle"))
