@@ -120,6 +120,49 @@ int mpgemm_qd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
               double* const C[4], int64_t ldc,
               mpg_algo algo, const mpg_tile* tile);
 
+/* ---- split-precision (Ozaki) DD product on INT8 MFMA ------------------ */
+
+/* C := A B to double-double accuracy from FP64 inputs A (m x l) and B
+ * (l x n) through INT8 matrix cores (error-free splitting of Ozaki, Ogita,
+ * Oishi and Rump; INT8 form of Ootomo, Ozaki and Yokota).  Each row of A is
+ * scaled by 2^-e_i and each column of B by 2^-f_j into (-1, 1) (e_i the
+ * smallest integer with max_k |a_ik| < 2^e_i) and cut by truncation into
+ * `slices` digit planes of 7 bits (INT8 values in [-127, 127], exact); the
+ * products of digit planes s and t are exact INT32 sums, grouped by
+ * diagonal g = s + t, scaled by 2^(e_i + f_j - 7g) and added in
+ * double-double.
+ *   slices     1..40, or 0 = as many as make every digit expansion exact
+ *              (found by a device scan; synchronises the stream).  With the
+ *              exact count and pairs_mode 0 the only rounding is the
+ *              double-double recombination, so the result meets the DD bound
+ *              8 l 2^-104 (|A||B|)_ij.
+ *   pairs_mode 0: all slices^2 digit-plane pairs; 1: only s + t <= slices + 1.
+ * With fewer slices the truncation error is at most
+ * l 2^(e_i + f_j) 2^(-7 slices)(2 + 2^(-7 slices)) per entry (pairs_mode 0).
+ * Requires l <= 33280 (INT32 headroom).  C_hi/C_lo must not overlap A, B. */
+int mpgemm_ozaki_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
+                    const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double* C_hi, double* C_lo, int64_t ldc, int slices, int pairs_mode);
+
+/* The slice count that makes the digit planes of A's rows and B's columns
+ * exact (the count slices = 0 would use).  Synchronises the stream. */
+int mpg_ozaki_slices_exact(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
+                           const double* A, int64_t lda, const double* B, int64_t ldb,
+                           int* slices);
+
+/* The splitting step alone.  side 0: rows of X (rows x cols) get exponents
+ * exps[rows] and digit planes out[s][r][k]; side 1: columns of X get
+ * exps[cols] and planes out[s][c][k] (transposed, K contiguous).  Lines are
+ * padded to a multiple of 64 and K to a multiple of 64 with zero digits:
+ * ld_out >= round64(K) (a multiple of 8) and plane >= round64(lines) *
+ * ld_out bytes.  out and exps are device buffers owned by the caller. */
+int mpg_ozaki_split(mpg_ctx* ctx, int side, int64_t rows, int64_t cols,
+                    const double* X, int64_t ldx, int slices,
+                    int8_t* out, int64_t ld_out, int64_t plane, int32_t* exps);
+
+/* Slice count used by the context's last mpgemm_ozaki_dd call. */
+int mpg_ozaki_last_slices(const mpg_ctx* ctx);
+
 /* ---- kernel timing (HIP events on the context stream) ------------------ */
 
 /* Kernel classes timed when profiling is on. */

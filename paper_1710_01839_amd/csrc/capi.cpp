@@ -45,28 +45,28 @@ int mpg_device_guard(mpg_ctx* c) {
   return MPG_OK;
 }
 
-int mpg_workspace(mpg_ctx* c, size_t bytes, void** out) {
+int mpg_workspace(mpg_ctx* c, int slot, size_t bytes, void** out) {
   if (bytes == 0) {
     *out = nullptr;
     return MPG_OK;
   }
-  if (bytes > c->ws_size) {
-    if (c->ws) {
+  if (bytes > c->ws_size[slot]) {
+    if (c->ws[slot]) {
       hipError_t e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) return mpg_hip_fail(c, e, "hipStreamSynchronize (workspace)");
-      (void)hipFree(c->ws);
-      c->ws = nullptr;
-      c->ws_size = 0;
+      (void)hipFree(c->ws[slot]);
+      c->ws[slot] = nullptr;
+      c->ws_size[slot] = 0;
     }
     void* p = nullptr;
     if (c->alloc_hook_fail || hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
       return mpg_fail(c, MPG_ERR_NOMEM, "workspace allocation of %zu bytes failed", bytes);
     }
-    c->ws = p;
-    c->ws_size = bytes;
+    c->ws[slot] = p;
+    c->ws_size[slot] = bytes;
   }
-  *out = c->ws;
+  *out = c->ws[slot];
   return MPG_OK;
 }
 
@@ -208,7 +208,8 @@ extern "C" int mpg_destroy(mpg_ctx* c) {
   (void)mpg_device_guard(c);
   (void)hipStreamSynchronize(c->stream);
   mpg_destroy_cached(c);
-  if (c->ws) (void)hipFree(c->ws);
+  for (int s = 0; s < mpg_ctx::kSlots; ++s)
+    if (c->ws[s]) (void)hipFree(c->ws[s]);
   for (auto& r : c->prof_recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -316,7 +317,7 @@ int mpg_strassen(mpg_ctx* c, int limbs, int depth, int variant, int64_t m, int64
     elems += (size_t)(v.cnt * v.mr * v.nc);
   }
   void* ws = nullptr;
-  int st = mpg_workspace(c, elems * limbs * sizeof(double), &ws);
+  int st = mpg_workspace(c, 0, elems * limbs * sizeof(double), &ws);
   if (st != MPG_OK) return st;
   double* base = (double*)ws;
   auto plane = [&](size_t off, int q_) { return base + (size_t)q_ * elems + off; };

@@ -20,9 +20,11 @@ struct mpg_ctx {
   hipStream_t stream = nullptr;
   std::string last_error;
 
-  // workspace (grow-only, freed with the context)
-  void* ws = nullptr;
-  size_t ws_size = 0;
+  // workspace slots (grow-only, freed with the context): 0 = large operand
+  // workspace (Strassen blocks, digit planes), 1 = small (exponents, counters)
+  static constexpr int kSlots = 2;
+  void* ws[kSlots] = {nullptr, nullptr};
+  size_t ws_size[kSlots] = {0, 0};
   bool alloc_hook_fail = false;  // test seam: make the next allocations fail
 
   // kernel timing
@@ -39,6 +41,9 @@ struct mpg_ctx {
   // tuning table: (precision, m, n, l) -> (algo, tile)
   std::map<std::tuple<int, int64_t, int64_t, int64_t>, std::pair<int, mpg_tile>> table;
 
+  // slice count used by the last split-precision product
+  int last_slices = 0;
+
   // learned time model (owned)
   mpg_mlp_state* mlp = nullptr;
 };
@@ -46,7 +51,7 @@ struct mpg_ctx {
 int mpg_fail(mpg_ctx* c, int status, const char* fmt, ...);
 int mpg_hip_fail(mpg_ctx* c, hipError_t e, const char* where);
 int mpg_device_guard(mpg_ctx* c);
-int mpg_workspace(mpg_ctx* c, size_t bytes, void** out);
+int mpg_workspace(mpg_ctx* c, int slot, size_t bytes, void** out);
 int mpg_launch(mpg_ctx* c, int kclass, const std::function<hipError_t()>& fn, const char* what);
 size_t mpg_span_bytes(int64_t rows, int64_t cols, int64_t ld);
 int mpg_check_gemm_args(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,

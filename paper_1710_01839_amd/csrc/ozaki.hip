@@ -1,0 +1,398 @@
+// Split-precision double-double product on INT8 MFMA (gfx950).
+//
+// FP64 inputs are scaled per row of A (2^-e_i) and per column of B
+// (2^-f_j) into (-1, 1) and cut by truncation into S exact 7-bit digit
+// planes (INT8, values in [-127, 127]).  Products of digit planes run on
+// v_mfma_i32_16x16x64_i8 with exact INT32 sums; the sums of one diagonal
+// g = s + t of the (s, t) pair grid share the weight 2^(e_i + f_j - 7g) and
+// are added, scaled exactly, into double-double accumulators.
+#include <climits>
+
+#include "mp_arith.hpp"
+#include "ozaki_internal.hpp"
+
+namespace mpg {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------
+// exponent scans
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fill_int_kernel(int* p, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = v;
+}
+
+// e_i = max over the row of frexp's exponent (max |x| < 2^e_i); rows of X
+// (R x K, leading dimension ld) when by_col == 0, columns when by_col == 1.
+// Each thread folds a strided set of elements, then one atomic max per
+// thread (max is order independent: deterministic).
+__global__ __launch_bounds__(256) void exp_scan_kernel(const double* X, int64_t R, int64_t K,
+                                                       int64_t ld, int by_col, int* e) {
+  if (!by_col) {
+    // one workgroup per row
+    const int64_t i = blockIdx.x;
+    if (i >= R) return;
+    int best = INT_MIN;
+    for (int64_t k = threadIdx.x; k < K; k += 256) {
+      const double x = X[i * ld + k];
+      if (x != 0.0) best = max(best, ilogb(x) + 1);
+    }
+    if (best != INT_MIN) atomicMax(&e[i], best);
+  } else {
+    // threads over columns, rows split over gridDim.y
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= K) return;
+    const int64_t chunk = (R + gridDim.y - 1) / gridDim.y;
+    const int64_t r0 = blockIdx.y * chunk, r1 = min(R, r0 + chunk);
+    int best = INT_MIN;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double x = X[r * ld + j];
+      if (x != 0.0) best = max(best, ilogb(x) + 1);
+    }
+    if (best != INT_MIN) atomicMax(&e[j], best);
+  }
+}
+
+__global__ __launch_bounds__(256) void exp_finish_kernel(int* e, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n && e[i] == INT_MIN) e[i] = 0;
+}
+
+// Digits needed to hold x 2^-e exactly: ceil((e - low) / 7), low the
+// exponent of x's lowest set bit.
+__device__ __forceinline__ int digits_needed(double x, int e) {
+  if (x == 0.0) return 0;
+  const int top = ilogb(x);                            // x = 1.f * 2^top
+  const unsigned long long bits = __double_as_longlong(x);
+  const unsigned long long mant = (bits & 0x000FFFFFFFFFFFFFull) | 0x0010000000000000ull;
+  const int low = top - 52 + __builtin_ctzll(mant);
+  const int need = e - low;
+  return need <= 0 ? 0 : (need + 6) / 7;
+}
+
+__global__ __launch_bounds__(256) void need_scan_kernel(const double* X, int64_t R, int64_t K,
+                                                        int64_t ld, int by_col, const int* e,
+                                                        int* out) {
+  int best = 0;
+  const int64_t total = R * K;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * 256) {
+    const int64_t r = idx / K, k = idx % K;
+    const double x = X[r * ld + k];
+    best = max(best, digits_needed(x, by_col ? e[k] : e[r]));
+  }
+  atomicMax(out, best);
+}
+
+// ---------------------------------------------------------------------
+// digit slicing
+// ---------------------------------------------------------------------
+// Rows of X (R x K) -> planes out[s][r][k] (r < Rp, k < Kp, zero padded).
+// Each thread handles 8 consecutive k of one row and writes 8 bytes per
+// plane.
+__global__ __launch_bounds__(256) void split_rows_kernel(const double* X, int64_t R, int64_t K,
+                                                         int64_t ld, const int* e, int S,
+                                                         int8_t* out, int64_t ld_out,
+                                                         int64_t plane, int64_t Rp, int64_t Kp) {
+  const int64_t per_row = Kp / 8;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= Rp * per_row) return;
+  const int64_t r = idx / per_row, k0 = (idx % per_row) * 8;
+  double y[8];
+  const int er = r < R ? e[r] : 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t k = k0 + q;
+    const double x = (r < R && k < K) ? X[r * ld + k] : 0.0;
+    y[q] = ldexp(x, -er);
+  }
+  for (int s = 0; s < S; ++s) {
+    unsigned long long word = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      y[q] = y[q] * 128.0;
+      const double d = trunc(y[q]);
+      y[q] = y[q] - d;
+      word |= (unsigned long long)(uint8_t)(int8_t)(int)d << (8 * q);
+    }
+    *reinterpret_cast<unsigned long long*>(out + s * plane + r * ld_out + k0) = word;
+  }
+}
+
+// Columns of X (K x C, row-major) -> planes out[s][c][k] (transposed, c < Cp,
+// k < Kp, zero padded).  A 32 (k) x 64 (c) tile is read coalesced along c
+// (each thread keeps 8 remainders in registers); for each digit plane the
+// digits pass through LDS and are written back as 8-byte runs along k.
+constexpr int kColTileK = 32;
+constexpr int kMaxSlices = 40;
+__global__ __launch_bounds__(256) void split_cols_kernel(const double* X, int64_t K, int64_t C,
+                                                         int64_t ld, const int* f, int S,
+                                                         int8_t* out, int64_t ld_out,
+                                                         int64_t plane, int64_t Cp, int64_t Kp) {
+  __shared__ int8_t dig[64][kColTileK + 8];
+  const int64_t c0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * kColTileK;
+  const int tc = threadIdx.x % 64, tk = threadIdx.x / 64;  // 64 columns x 4
+  const int64_t c = c0 + tc;
+  const int fc = c < C ? f[c] : 0;
+  double y[kColTileK / 4];
+#pragma unroll
+  for (int q = 0; q < kColTileK / 4; ++q) {
+    const int64_t k = k0 + tk + 4 * q;
+    const double x = (c < C && k < K) ? X[k * ld + c] : 0.0;
+    y[q] = ldexp(x, -fc);
+  }
+  const int wc = threadIdx.x / 4, wk = (threadIdx.x % 4) * 8;
+  const int64_t cc = c0 + wc;
+  for (int s = 0; s < S; ++s) {
+#pragma unroll
+    for (int q = 0; q < kColTileK / 4; ++q) {
+      y[q] = y[q] * 128.0;
+      const double d = trunc(y[q]);
+      y[q] = y[q] - d;
+      dig[tc][tk + 4 * q] = (int8_t)(int)d;
+    }
+    __syncthreads();
+    unsigned long long word = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) word |= (unsigned long long)(uint8_t)dig[wc][wk + q] << (8 * q);
+    if (cc < Cp)
+      *reinterpret_cast<unsigned long long*>(out + s * plane + cc * ld_out + k0 + wk) = word;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------
+// INT8 MFMA product with diagonal grouping.
+//
+// Workgroup: 256 threads, C tile 64 x 64; wave w owns the 32 x 32 sub-tile
+// (32 (w / 2), 32 (w % 2)) as 2 x 2 blocks of 16 x 16 MFMA outputs.  The
+// (s, t) pair grid is walked in SB x SB blocks, from the smallest weights
+// to the largest; for one block the K loop stages SB digit planes of A and
+// SB of B (64 rows x 64 k bytes each, rows padded to 80 bytes so the
+// 16-byte fragment reads of 8 lanes hit distinct banks) in LDS,
+// double-buffered, and every kept pair adds into the INT32 accumulator of
+// its diagonal (2 SB - 1 live diagonals).  At the end of the block each
+// diagonal sum is converted to FP64 (exact), scaled by 2^(e_i + f_j - 7g)
+// (exact) and added to the entry's double-double accumulator.
+//
+// MFMA operand layout (16 x 16 x 64, i8): lane l supplies row (l % 16) of
+// A and column (l % 16) of B with the 16 bytes k = 16 (l / 16) .. +15 of
+// the 64-wide K step (any fixed k order is exact as long as A and B use the
+// same one); lane l receives D[4 (l / 16) + i][l % 16], i = 0..3.
+// ---------------------------------------------------------------------
+constexpr int kOzTile = 64;
+constexpr int kOzK = 64;
+constexpr int kOzRow = 80;  // padded LDS row in bytes
+
+template <int SB>
+__global__ __launch_bounds__(256, 1) void ozaki_mfma_kernel(OzakiGemmArgs a) {
+  __shared__ __attribute__((aligned(16))) int8_t sA[2][SB][kOzTile * kOzRow];
+  __shared__ __attribute__((aligned(16))) int8_t sB[2][SB][kOzTile * kOzRow];
+
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wr = wave / 2, wc = wave % 2;
+  const int tiles_n = (int)((a.n + kOzTile - 1) / kOzTile);
+  const int64_t m0 = (int64_t)(blockIdx.x / tiles_n) * kOzTile;
+  const int64_t n0 = (int64_t)(blockIdx.x % tiles_n) * kOzTile;
+
+  // per-lane output coordinates and their scale exponents
+  int erow[2][4], fcol[2];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = m0 + 32 * wr + 16 * rb + 4 * (lane / 16) + i;
+      erow[rb][i] = r < a.m ? a.e[r] : 0;
+    }
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int64_t c = n0 + 32 * wc + 16 * cb + lane % 16;
+    fcol[cb] = c < a.n ? a.f[c] : 0;
+  }
+
+  double hi[2][2][4], lo[2][2][4];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hi[rb][cb][i] = lo[rb][cb][i] = 0.0;
+
+  // staging: thread -> (row = tid / 4, 16-byte chunk = tid % 4) of a 64 x 64 tile
+  const int ld_row = tid / 4, ld_chunk = (tid % 4) * 16;
+  const int nblk = (a.S + SB - 1) / SB;
+  const int numK = (int)(a.l_pad / kOzK);
+
+  // blocks of the pair grid in order of decreasing s0 + t0 (smallest weights first)
+  for (int diag = 2 * (nblk - 1); diag >= 0; --diag) {
+    for (int bs = 0; bs < nblk; ++bs) {
+      const int bt = diag - bs;
+      if (bt < 0 || bt >= nblk) continue;
+      const int s0 = bs * SB, t0 = bt * SB;  // 0-based first slice of the block
+      // any kept pair in this block?  (1-based s + t <= S + 1 for the triangle)
+      if (a.triangle && (s0 + 1) + (t0 + 1) > a.S + 1) continue;
+      const int ns = min(SB, a.S - s0), nt = min(SB, a.S - t0);
+
+      v4i acc[2 * SB - 1][2][2];
+#pragma unroll
+      for (int g = 0; g < 2 * SB - 1; ++g)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) acc[g][rb][cb] = v4i{0, 0, 0, 0};
+
+      uint4 ra[SB], rb_[SB];
+      auto load = [&](int kt) {
+        const int64_t k = (int64_t)kt * kOzK + ld_chunk;
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+          const int sq = q < ns ? s0 + q : s0;   // clamp: a valid plane, never used
+          const int tq = q < nt ? t0 + q : t0;
+          ra[q] = *reinterpret_cast<const uint4*>(a.A + sq * a.planeA + (m0 + ld_row) * a.l_pad + k);
+          rb_[q] = *reinterpret_cast<const uint4*>(a.B + tq * a.planeB + (n0 + ld_row) * a.l_pad + k);
+        }
+      };
+      auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+          *reinterpret_cast<uint4*>(&sA[buf][q][ld_row * kOzRow + ld_chunk]) = ra[q];
+          *reinterpret_cast<uint4*>(&sB[buf][q][ld_row * kOzRow + ld_chunk]) = rb_[q];
+        }
+      };
+
+      load(0);
+      store(0);
+      __syncthreads();
+      for (int kt = 0; kt < numK; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < numK) load(kt + 1);
+        v4i fa[SB][2], fb[SB][2];
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int ra_row = 32 * wr + 16 * h + lane % 16;
+            const int rb_row = 32 * wc + 16 * h + lane % 16;
+            fa[q][h] = *reinterpret_cast<const v4i*>(&sA[cur][q][ra_row * kOzRow + 16 * (lane / 16)]);
+            fb[q][h] = *reinterpret_cast<const v4i*>(&sB[cur][q][rb_row * kOzRow + 16 * (lane / 16)]);
+          }
+#pragma unroll
+        for (int ds = 0; ds < SB; ++ds)
+#pragma unroll
+          for (int dt = 0; dt < SB; ++dt) {
+            const bool keep = ds < ns && dt < nt &&
+                              (!a.triangle || (s0 + ds + 1) + (t0 + dt + 1) <= a.S + 1);
+            if (keep) {
+#pragma unroll
+              for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                  acc[ds + dt][rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                      fa[ds][rb], fb[dt][cb], acc[ds + dt][rb][cb], 0, 0, 0);
+            }
+          }
+        if (kt + 1 < numK) store(cur ^ 1);
+        __syncthreads();
+      }
+
+      // flush the diagonals, smallest weight (largest g) first
+#pragma unroll
+      for (int gl = 2 * SB - 2; gl >= 0; --gl) {
+        const int g = (s0 + 1) + (t0 + 1) + gl;  // 1-based s + t
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int v = acc[gl][rb][cb][i];
+              if (v == 0) continue;
+              const double x = ldexp((double)v, erow[rb][i] + fcol[cb] - 7 * g);
+              double s, err;
+              two_sum(hi[rb][cb][i], x, s, err);
+              hi[rb][cb][i] = s;
+              lo[rb][cb][i] = lo[rb][cb][i] + err;
+            }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = m0 + 32 * wr + 16 * rb + 4 * (lane / 16) + i;
+        const int64_t c = n0 + 32 * wc + 16 * cb + lane % 16;
+        if (r < a.m && c < a.n) {
+          double h = hi[rb][cb][i], l = lo[rb][cb][i];
+          dd_renorm(h, l);
+          a.C_hi[r * a.ldc + c] = h;
+          a.C_lo[r * a.ldc + c] = l;
+        }
+      }
+}
+
+}  // namespace
+
+int ozaki_max_slices() { return kMaxSlices; }
+int ozaki_block_slices() { return 4; }
+
+hipError_t launch_ozaki_exponents(const double* X, int64_t R, int64_t K, int64_t ld, int by_col,
+                                  int* e, hipStream_t s) {
+  const int64_t n = by_col ? K : R;
+  if (n <= 0) return hipSuccess;
+  const unsigned fb = (unsigned)std::min<int64_t>((n + 255) / 256, 65535);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(fb), dim3(256), 0, s, e, n, INT_MIN);
+  if (R > 0 && K > 0) {
+    if (!by_col) {
+      hipLaunchKernelGGL(exp_scan_kernel, dim3((unsigned)R), dim3(256), 0, s, X, R, K, ld, 0, e);
+    } else {
+      const unsigned gy = (unsigned)std::min<int64_t>(std::max<int64_t>(R / 64, 1), 256);
+      hipLaunchKernelGGL(exp_scan_kernel, dim3((unsigned)((K + 255) / 256), gy), dim3(256), 0, s,
+                         X, R, K, ld, 1, e);
+    }
+  }
+  hipLaunchKernelGGL(exp_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, e, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ozaki_need(const double* X, int64_t R, int64_t K, int64_t ld, int by_col,
+                             const int* e, int* out, hipStream_t s) {
+  if (R <= 0 || K <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((R * K + 255) / 256, 8192);
+  hipLaunchKernelGGL(need_scan_kernel, dim3(blocks), dim3(256), 0, s, X, R, K, ld, by_col, e, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ozaki_split_rows(const double* X, int64_t R, int64_t K, int64_t ld, const int* e,
+                                   int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Rp,
+                                   int64_t Kp, hipStream_t s) {
+  const int64_t work = Rp * (Kp / 8);
+  if (work <= 0 || S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, X, R,
+                     K, ld, e, S, out, ld_out, plane, Rp, Kp);
+  return hipGetLastError();
+}
+
+hipError_t launch_ozaki_split_cols(const double* X, int64_t K, int64_t C, int64_t ld, const int* f,
+                                   int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Cp,
+                                   int64_t Kp, hipStream_t s) {
+  if (Cp <= 0 || Kp <= 0 || S <= 0) return hipSuccess;
+  if (S > kMaxSlices) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_cols_kernel, dim3((unsigned)(Cp / 64), (unsigned)(Kp / kColTileK)),
+                     dim3(256), 0, s, X, K, C, ld, f, S, out, ld_out, plane, Cp, Kp);
+  return hipGetLastError();
+}
+
+hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
+  const int64_t tiles = ((a.m + kOzTile - 1) / kOzTile) * ((a.n + kOzTile - 1) / kOzTile);
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ozaki_mfma_kernel<4>, dim3((unsigned)tiles), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace mpg

@@ -1,0 +1,180 @@
+// Host side of the split-precision (INT8 MFMA) double-double product.
+#include <climits>
+#include <cstring>
+
+#include "capi_internal.hpp"
+#include "ozaki_internal.hpp"
+
+using namespace mpg;
+
+namespace {
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+// Device scan for the slice count that makes the digit planes exact; the
+// result is read back (the stream is synchronised).
+int slices_exact(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda,
+                 const double* B, int64_t ldb, int* e, int* f, int* counter, int* S) {
+  int st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->stream, counter);
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    r = launch_ozaki_need(A, m, l, lda, 0, e, counter, c->stream);
+    if (r != hipSuccess) return r;
+    return launch_ozaki_need(B, l, n, ldb, 1, f, counter, c->stream);
+  }, "slice-count scan");
+  if (st != MPG_OK) return st;
+  int h = 0;
+  hipError_t r = hipMemcpyAsync(&h, counter, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+  if (r != hipSuccess) return mpg_hip_fail(c, r, "slice-count read-back");
+  *S = h;
+  return MPG_OK;
+}
+
+int check_fp64_args(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda,
+                    const double* B, int64_t ldb) {
+  if (m < 0 || n < 0 || l < 0) return mpg_fail(c, MPG_ERR_ARG, "negative dimension");
+  if (l > 0 && (m > 0 && n > 0)) {
+    if (!A || !B) return mpg_fail(c, MPG_ERR_ARG, "NULL input");
+    if (lda < l) return mpg_fail(c, MPG_ERR_ARG, "lda < l");
+    if (ldb < n) return mpg_fail(c, MPG_ERR_ARG, "ldb < n");
+  }
+  return MPG_OK;
+}
+
+// Exponents of A rows and B columns in the small workspace slot.
+int exponents(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda,
+              const double* B, int64_t ldb, int** e, int** f, int** counter) {
+  void* small = nullptr;
+  const int64_t mp = round_up(std::max<int64_t>(m, 1), 64), np = round_up(std::max<int64_t>(n, 1), 64);
+  int st = mpg_workspace(c, 1, (size_t)(mp + np + 64) * sizeof(int), &small);
+  if (st != MPG_OK) return st;
+  *e = (int*)small;
+  *f = *e + mp;
+  *counter = *f + np;
+  return mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipError_t r = launch_ozaki_exponents(A, m, l, lda, 0, *e, c->stream);
+    if (r != hipSuccess) return r;
+    return launch_ozaki_exponents(B, l, n, ldb, 1, *f, c->stream);
+  }, "exponent scan");
+}
+
+}  // namespace
+
+extern "C" int mpg_ozaki_slices_exact(mpg_ctx* c, int64_t m, int64_t n, int64_t l,
+                                      const double* A, int64_t lda, const double* B, int64_t ldb,
+                                      int* slices) {
+  if (!c || !slices) return MPG_ERR_ARG;
+  int st = check_fp64_args(c, m, n, l, A, lda, B, ldb);
+  if (st != MPG_OK) return st;
+  *slices = 0;
+  if (m == 0 || n == 0 || l == 0) return MPG_OK;
+  if ((st = mpg_device_guard(c)) != MPG_OK) return st;
+  int *e, *f, *counter;
+  if ((st = exponents(c, m, n, l, A, lda, B, ldb, &e, &f, &counter)) != MPG_OK) return st;
+  return slices_exact(c, m, n, l, A, lda, B, ldb, e, f, counter, slices);
+}
+
+extern "C" int mpg_ozaki_split(mpg_ctx* c, int side, int64_t rows, int64_t cols, const double* X,
+                               int64_t ldx, int slices, int8_t* out, int64_t ld_out,
+                               int64_t plane, int32_t* exps) {
+  if (!c) return MPG_ERR_ARG;
+  if (side != 0 && side != 1) return mpg_fail(c, MPG_ERR_ARG, "side must be 0 (rows) or 1 (columns)");
+  if (rows < 0 || cols < 0 || ldx < cols || slices < 1 || slices > ozaki_max_slices())
+    return mpg_fail(c, MPG_ERR_ARG, "bad split arguments");
+  if (rows == 0 || cols == 0) return MPG_OK;
+  if (!X || !out || !exps) return mpg_fail(c, MPG_ERR_ARG, "NULL pointer");
+  const int64_t lines = side == 0 ? rows : cols, len = side == 0 ? cols : rows;
+  const int64_t lines_p = round_up(lines, 64), len_p = round_up(len, 64);
+  if (ld_out < len_p || ld_out % 8 || plane < lines_p * ld_out)
+    return mpg_fail(c, MPG_ERR_ARG, "digit plane too small: need ld_out >= %lld (multiple of 8), "
+                    "plane >= %lld", (long long)len_p, (long long)(lines_p * ld_out));
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  return mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipError_t r = launch_ozaki_exponents(X, rows, cols, ldx, side, exps, c->stream);
+    if (r != hipSuccess) return r;
+    if (side == 0)
+      return launch_ozaki_split_rows(X, rows, cols, ldx, exps, slices, out, ld_out, plane, lines_p,
+                                     len_p, c->stream);
+    return launch_ozaki_split_cols(X, rows, cols, ldx, exps, slices, out, ld_out, plane, lines_p,
+                                   len_p, c->stream);
+  }, "digit split");
+}
+
+extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A,
+                               int64_t lda, const double* B, int64_t ldb, double* C_hi,
+                               double* C_lo, int64_t ldc, int slices, int pairs_mode) {
+  if (!c) return MPG_ERR_ARG;
+  int st = check_fp64_args(c, m, n, l, A, lda, B, ldb);
+  if (st != MPG_OK) return st;
+  if (m == 0 || n == 0) return MPG_OK;
+  if (!C_hi || !C_lo || ldc < n) return mpg_fail(c, MPG_ERR_ARG, "bad C");
+  if (pairs_mode != 0 && pairs_mode != 1) return mpg_fail(c, MPG_ERR_ARG, "pairs_mode must be 0 or 1");
+  if (slices < 0 || slices > ozaki_max_slices())
+    return mpg_fail(c, MPG_ERR_ARG, "slices must be 0 (exact) .. %d", ozaki_max_slices());
+  {
+    const size_t sa = mpg_span_bytes(m, l, lda), sb = mpg_span_bytes(l, n, ldb),
+                 sc = mpg_span_bytes(m, n, ldc);
+    auto ov = [](const void* x, size_t a, const void* y, size_t b) {
+      return x && y && a && b && (const char*)x < (const char*)y + b && (const char*)y < (const char*)x + a;
+    };
+    if (ov(C_hi, sc, A, sa) || ov(C_hi, sc, B, sb) || ov(C_lo, sc, A, sa) || ov(C_lo, sc, B, sb) ||
+        ov(C_hi, sc, C_lo, sc))
+      return mpg_fail(c, MPG_ERR_ALIAS, "C overlaps an input or its other limb");
+  }
+  if ((st = mpg_device_guard(c)) != MPG_OK) return st;
+  if (l == 0) {
+    double* Cp[4] = {C_hi, C_lo, nullptr, nullptr};
+    return mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_zero(Cp, 2, m, n, ldc, c->stream); },
+                      "zero C");
+  }
+  const int64_t lp = round_up(l, 64), mp = round_up(m, 64), np = round_up(n, 64);
+  // INT32 headroom: at most SB pairs share a diagonal accumulator per block
+  if ((double)ozaki_block_slices() * (double)lp * 127.0 * 127.0 >= 2147483647.0)
+    return mpg_fail(c, MPG_ERR_UNSUPPORTED, "l = %lld too large for exact INT32 sums", (long long)l);
+  int *e, *f, *counter;
+  if ((st = exponents(c, m, n, l, A, lda, B, ldb, &e, &f, &counter)) != MPG_OK) return st;
+  int S = slices;
+  if (S == 0) {
+    if ((st = slices_exact(c, m, n, l, A, lda, B, ldb, e, f, counter, &S)) != MPG_OK) return st;
+    S = std::max(S, 1);
+    if (S > ozaki_max_slices())
+      return mpg_fail(c, MPG_ERR_UNSUPPORTED, "exact slicing needs %d slices (max %d)", S,
+                      ozaki_max_slices());
+  }
+  c->last_slices = S;
+  void* big = nullptr;
+  const int64_t planeA = mp * lp, planeB = np * lp;
+  if ((st = mpg_workspace(c, 0, (size_t)S * (size_t)(planeA + planeB), &big)) != MPG_OK) return st;
+  int8_t* Asl = (int8_t*)big;
+  int8_t* Bsl = Asl + (size_t)S * planeA;
+  st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipError_t r = launch_ozaki_split_rows(A, m, l, lda, e, S, Asl, lp, planeA, mp, lp, c->stream);
+    if (r != hipSuccess) return r;
+    return launch_ozaki_split_cols(B, l, n, ldb, f, S, Bsl, lp, planeB, np, lp, c->stream);
+  }, "digit split");
+  if (st != MPG_OK) return st;
+  OzakiGemmArgs g{};
+  g.m = m;
+  g.n = n;
+  g.l_pad = lp;
+  g.S = S;
+  g.triangle = pairs_mode;
+  g.A = Asl;
+  g.B = Bsl;
+  g.planeA = planeA;
+  g.planeB = planeB;
+  g.e = e;
+  g.f = f;
+  g.C_hi = C_hi;
+  g.C_lo = C_lo;
+  g.ldc = ldc;
+  return mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_ozaki_gemm(g, c->stream); },
+                    "INT8 MFMA product");
+}
+
+extern "C" int mpg_ozaki_last_slices(const mpg_ctx* c) { return c ? c->last_slices : 0; }

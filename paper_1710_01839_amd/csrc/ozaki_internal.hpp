@@ -1,0 +1,38 @@
+// Internal interface of the split-precision (INT8 MFMA) path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace mpg {
+
+struct OzakiGemmArgs {
+  int64_t m, n, l_pad;      // real output size, padded K (multiple of 64)
+  int S;                    // digit planes per operand
+  int triangle;             // 1: keep pairs with s + t <= S + 1 only
+  const int8_t* A;          // [S][m_pad][l_pad]
+  const int8_t* B;          // [S][n_pad][l_pad] (columns of B, K contiguous)
+  int64_t planeA, planeB;   // bytes per plane
+  const int* e;             // row exponents of A (m)
+  const int* f;             // column exponents of B (n)
+  double* C_hi;
+  double* C_lo;
+  int64_t ldc;
+};
+
+int ozaki_max_slices();
+int ozaki_block_slices();
+hipError_t launch_ozaki_exponents(const double* X, int64_t R, int64_t K, int64_t ld, int by_col,
+                                  int* e, hipStream_t s);
+hipError_t launch_ozaki_need(const double* X, int64_t R, int64_t K, int64_t ld, int by_col,
+                             const int* e, int* out, hipStream_t s);
+hipError_t launch_ozaki_split_rows(const double* X, int64_t R, int64_t K, int64_t ld, const int* e,
+                                   int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Rp,
+                                   int64_t Kp, hipStream_t s);
+hipError_t launch_ozaki_split_cols(const double* X, int64_t K, int64_t C, int64_t ld, const int* f,
+                                   int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Cp,
+                                   int64_t Kp, hipStream_t s);
+hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s);
+
+}  // namespace mpg

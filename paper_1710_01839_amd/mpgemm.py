@@ -69,6 +69,10 @@ _sig("mpgemm_dd", [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _
                    ctypes.POINTER(mpg_tile)])
 _sig("mpgemm_qd", [_vp, _i64, _i64, _i64, _pp, _i64, _pp, _i64, _pp, _i64, _ci,
                    ctypes.POINTER(mpg_tile)])
+_sig("mpgemm_ozaki_dd", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _ci, _ci])
+_sig("mpg_ozaki_slices_exact", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(_ci)])
+_sig("mpg_ozaki_split", [_vp, _ci, _i64, _i64, _vp, _i64, _ci, _vp, _i64, _i64, _vp])
+_sig("mpg_ozaki_last_slices", [_vp])
 _sig("mpg_prof_enable", [_vp, _ci])
 _sig("mpg_prof_read", [_vp, _ci, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
 
@@ -201,6 +205,50 @@ def mpgemm_qd(ctx: Context, A, B, C, algo="block", tile=None):
                         ctypes.byref(t) if t is not None else None)
     ctx.check(st, "mpgemm_qd")
     return C
+
+
+def mpgemm_ozaki_dd(ctx: Context, A, B, C, slices: int = 0, mode: str = "all"):
+    """C := A B to DD accuracy on INT8 MFMA.  A, B: float64 device tensors;
+    C: (hi, lo).  slices = 0 picks the exact slice count."""
+    m, l, lda = _mat(A, "A")
+    l2, n, ldb = _mat(B, "B")
+    m2, n2, ldc = _mat(C[0], "C_hi")
+    _mat(C[1], "C_lo")
+    if l2 != l or m2 != m or n2 != n:
+        raise MpgemmError(MPG_ERR_ARG, "shape mismatch")
+    ctx.bind_stream()
+    st = _lib.mpgemm_ozaki_dd(ctx.handle, m, n, l, _ptr(A), lda, _ptr(B), ldb, _ptr(C[0]),
+                              _ptr(C[1]), ldc, int(slices), 1 if mode == "triangle" else 0)
+    ctx.check(st, "mpgemm_ozaki_dd")
+    return C
+
+
+def ozaki_last_slices(ctx: Context) -> int:
+    return int(_lib.mpg_ozaki_last_slices(ctx.handle))
+
+
+def ozaki_slices_exact(ctx: Context, A, B) -> int:
+    m, l, lda = _mat(A, "A")
+    _, n, ldb = _mat(B, "B")
+    out = ctypes.c_int()
+    ctx.bind_stream()
+    ctx.check(_lib.mpg_ozaki_slices_exact(ctx.handle, m, n, l, _ptr(A), lda, _ptr(B), ldb,
+                                          ctypes.byref(out)), "mpg_ozaki_slices_exact")
+    return out.value
+
+
+def ozaki_split(ctx: Context, X, slices: int, side: int = 0):
+    """Digit planes and exponents of X's rows (side 0) or columns (side 1).
+    Returns (planes int8 [slices, lines_pad, len_pad], exps int32)."""
+    rows, cols, ldx = _mat(X, "X")
+    lines, length = (rows, cols) if side == 0 else (cols, rows)
+    lp, kp = -(-lines // 64) * 64, -(-length // 64) * 64
+    out = torch.zeros((slices, lp, kp), dtype=torch.int8, device=X.device)
+    exps = torch.zeros(lines, dtype=torch.int32, device=X.device)
+    ctx.bind_stream()
+    ctx.check(_lib.mpg_ozaki_split(ctx.handle, side, rows, cols, _ptr(X), ldx, slices, _ptr(out),
+                                   kp, lp * kp, _ptr(exps)), "mpg_ozaki_split")
+    return out, exps
 
 
 def empty_like_limbs(m: int, n: int, limbs: int, device="cuda"):

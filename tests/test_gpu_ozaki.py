@@ -1,0 +1,138 @@
+"""GPU parity of the split-precision (INT8 MFMA) path against the oracle:
+digit planes and exponents bit-exact, the integer special case exact, the
+value within the recombination tolerance of the oracle's exact truncated
+product, and the DD bound against exact AB with the exact slice count."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cref, exact, ozaki
+from paper_1710_01839_amd import inputs
+from tests.helpers import error_ratio_full, sampled_errors, sampled_pairs
+
+pytestmark = pytest.mark.gpu
+
+
+def run_oz(M, ctx, A, B, S, mode="all"):
+    m, n = A.shape[0], B.shape[1]
+    C = M.empty_like_limbs(m, n, 2)
+    M.mpgemm_ozaki_dd(ctx, torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda(), C, S, mode)
+    torch.cuda.synchronize()
+    return M.to_host(C)
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_split_planes_bit_exact(gpu, side):
+    M, ctx = gpu
+    X = inputs.fp64_wide(70, 101, 0)
+    S = 12
+    planes, exps = M.ozaki_split(ctx, torch.as_tensor(X).cuda(), S, side)
+    torch.cuda.synchronize()
+    planes, exps = planes.cpu().numpy(), exps.cpu().numpy()
+    if side == 0:
+        e = ozaki.row_exponents(X)
+        D, _ = ozaki.split_rows(X, e, S)
+        assert np.array_equal(exps, e)
+        for s in range(S):
+            assert np.array_equal(planes[s, :70, :101], D[s])
+            assert not planes[s, 70:, :].any() and not planes[s, :, 101:].any()
+    else:
+        f = ozaki.col_exponents(X)
+        D, _ = ozaki.split_cols(X, f, S)
+        assert np.array_equal(exps, f)
+        for s in range(S):
+            assert np.array_equal(planes[s, :101, :70], D[s].T)
+            assert not planes[s, 101:, :].any() and not planes[s, :, 70:].any()
+
+
+def test_slices_exact_matches_oracle(gpu):
+    M, ctx = gpu
+    A, B = inputs.fp64_wide(90, 130, 1), inputs.fp64_wide(130, 60, 2)
+    S = M.ozaki_slices_exact(ctx, torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda())
+    assert S == ozaki.slices_exact(A, B)
+
+
+def test_single_slice_integer_product_exact(gpu):
+    """Integer entries in [-127, 127], row/column maxima >= 64: one digit
+    plane holds them, the MFMA sums are exact, C == AB."""
+    M, ctx = gpu
+    g = np.random.default_rng(3)
+    m, n, l = 100, 90, 300
+    A = g.integers(-127, 128, size=(m, l)).astype(float)
+    B = g.integers(-127, 128, size=(l, n)).astype(float)
+    A[:, 5] = 127.0
+    B[7, :] = -120.0
+    C = run_oz(M, ctx, A, B, 1)
+    want = A.astype(np.int64) @ B.astype(np.int64)
+    assert np.array_equal(C[0], want.astype(float)) and not C[1].any()
+
+
+@pytest.mark.parametrize("S,mode", [(3, "all"), (7, "all"), (10, "triangle"), (13, "all")])
+def test_matches_oracle_truncated_product(gpu, S, mode):
+    M, ctx = gpu
+    m, n, l = 77, 69, 150
+    A, B = inputs.fp64_wide(m, l, 4), inputs.fp64_wide(l, n, 5)
+    C = run_oz(M, ctx, A, B, S, mode)
+    (hi, lo), (N, E0) = ozaki.ozaki_dd(A, B, S, mode)
+    G = cref.absprod_exact((A,), (B,))
+    for idx in np.ndindex(hi.shape):
+        got = Fraction(float(C[0][idx])) + Fraction(float(C[1][idx]))
+        want = ozaki.to_fraction(N, E0, idx)
+        # double-double recombination of at most a few hundred exact terms
+        assert abs(got - want) <= Fraction(float(G[idx])) * Fraction(256, 2 ** 106) + abs(want) * Fraction(1, 2 ** 104)
+
+
+def test_exact_slices_meet_dd_bound(gpu):
+    """slices = 0 (exact splitting, all pairs): equal stated accuracy with the
+    DD kernel, |C - AB| <= 8 l 2^-104 (|A||B|)."""
+    M, ctx = gpu
+    m, n, l = 128, 96, 257
+    A, B = inputs.fp64_wide(m, l, 6), inputs.fp64_wide(l, n, 7)
+    C = run_oz(M, ctx, A, B, 0)
+    assert M.ozaki_last_slices(ctx) == ozaki.slices_exact(A, B)
+    r, _ = error_ratio_full(C, (A,), (B,), -104)
+    print("ozaki exact-slices ratio", r, "S =", M.ozaki_last_slices(ctx))
+    assert r <= 8.0
+
+
+@pytest.mark.parametrize("S", [6, 10])
+def test_truncated_within_apriori_bound(gpu, S):
+    M, ctx = gpu
+    m, n, l = 64, 80, 200
+    A, B = inputs.fp64_wide(m, l, 8), inputs.fp64_wide(l, n, 9)
+    C = run_oz(M, ctx, A, B, S)
+    Ce = cref.gemm_exact((A,), (B,), out_limbs=2)
+    d = np.abs(cref.exact_diff(C, Ce))
+    assert np.all(d <= ozaki.apriori_bound(A, B, S) * (1 + 2.0 ** -40) + np.abs(Ce[0]) * 2.0 ** -100)
+
+
+def test_edge_cases(gpu):
+    M, ctx = gpu
+    # zero rows / columns, l not a multiple of 64, 1 x 1
+    A = inputs.fp64_wide(33, 65, 10)
+    B = inputs.fp64_wide(65, 17, 11)
+    A[3, :] = 0.0
+    B[:, 4] = 0.0
+    C = run_oz(M, ctx, A, B, 0)
+    r, _ = error_ratio_full(C, (A,), (B,), -104)
+    assert r <= 8.0 and not C[0][3].any() and not C[0][:, 4].any()
+    C = run_oz(M, ctx, np.array([[3.0]]), np.array([[-0.5]]), 0)
+    assert C[0][0, 0] == -1.5 and C[1][0, 0] == 0.0
+    with pytest.raises(M.MpgemmError):
+        run_oz(M, ctx, A, B, 41)
+
+
+def test_full_size_4096_exact_slices_sampled(gpu):
+    """n = 4096 (smallest size of the split-precision workload) with the
+    exact slice count: DD bound at sampled entries against Python integers."""
+    M, ctx = gpu
+    n = 4096
+    A, B = inputs.fp64_wide(n, n, 12), inputs.fp64_wide(n, n, 13)
+    C = run_oz(M, ctx, A, B, 0)
+    pairs = sampled_pairs(n, n, 32)
+    errs, mags = sampled_errors(C, (A,), (B,), pairs)
+    r = max(e / (n * 2.0 ** -104 * g) for e, g in zip(errs, mags) if g > 0)
+    print("n=4096 exact slices", M.ozaki_last_slices(ctx), "ratio", r)
+    assert r <= 8.0
