@@ -120,6 +120,39 @@ int mpgemm_qd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
               double* const C[4], int64_t ldc,
               mpg_algo algo, const mpg_tile* tile);
 
+/* ---- batches of uneven DD products ------------------------------------ */
+
+/* One problem C := A B of a batch (same conventions as mpgemm_dd). */
+typedef struct {
+  int64_t m, n, l, lda, ldb, ldc;
+  const double *A_hi, *A_lo, *B_hi, *B_lo;
+  double *C_hi, *C_lo;
+} mpg_dd_problem;
+
+typedef struct mpg_batch_plan mpg_batch_plan;
+
+/* All problems in one persistent launch: a grid of (CUs x resident
+ * workgroups) walks the tiles of every problem, laid end to end, with the
+ * block algorithm (Eq. 2) of tile variant `tile` (NULL: 32 x 32 tiles);
+ * results are bitwise those of mpgemm_dd(MPG_BLOCK) with that tile.
+ * `problems` is a host array; the descriptors are uploaded on the context
+ * stream (the call waits for the context's previous batch to finish). */
+int mpgemm_dd_batched(mpg_ctx* ctx, int count, const mpg_dd_problem* problems,
+                      const mpg_tile* tile);
+
+/* Capture that persistent launch once in a HIP graph.  The plan owns the
+ * graph and a device copy of the descriptors; `problems` is only read
+ * during the call. */
+int mpg_batch_plan_create(mpg_ctx* ctx, int count, const mpg_dd_problem* problems,
+                          const mpg_tile* tile, mpg_batch_plan** plan);
+/* Replay the graph on `stream` (a hipStream_t; NULL = the context stream). */
+int mpg_batch_plan_launch(mpg_batch_plan* plan, void* stream);
+/* Rewrite the descriptors in place (same count; shapes and pointers may
+ * change); the captured graph stays valid.  Waits for the context stream. */
+int mpg_batch_plan_update(mpg_batch_plan* plan, const mpg_dd_problem* problems);
+/* Free the plan (waits for the context stream).  NULL is accepted. */
+int mpg_batch_plan_destroy(mpg_batch_plan* plan);
+
 /* ---- split-precision (Ozaki) DD product on INT8 MFMA ------------------ */
 
 /* C := A B to double-double accuracy from FP64 inputs A (m x l) and B

@@ -1,0 +1,184 @@
+// Host side of batched uneven double-double products: descriptor
+// construction, the persistent launch, and plans that capture that launch
+// once in a HIP graph and replay it.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "batch_internal.hpp"
+#include "capi_internal.hpp"
+
+using namespace mpg;
+
+struct mpg_batch_plan {
+  mpg_ctx* ctx = nullptr;
+  int count = 0;
+  int variant = 0;
+  int grid = 0;
+  BatchProblem* d_desc = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Validate and lay out the problems: tiles of all problems end to end,
+// problems ordered by decreasing l (cost per tile) so that the strided walk
+// hands every workgroup a similar mix of long and short tiles.
+int build_desc(mpg_ctx* c, int count, const mpg_dd_problem* P, int variant,
+               std::vector<BatchProblem>& out) {
+  if (count < 0 || (count > 0 && !P)) return mpg_fail(c, MPG_ERR_ARG, "bad problem list");
+  int bm, bn;
+  batch_variant_tile(variant, &bm, &bn);
+  for (int i = 0; i < count; ++i) {
+    const double* A[4] = {P[i].A_hi, P[i].A_lo, nullptr, nullptr};
+    const double* B[4] = {P[i].B_hi, P[i].B_lo, nullptr, nullptr};
+    double* C[4] = {P[i].C_hi, P[i].C_lo, nullptr, nullptr};
+    int st = mpg_check_gemm_args(c, 2, P[i].m, P[i].n, P[i].l, A, P[i].lda, B, P[i].ldb, C, P[i].ldc);
+    if (st != MPG_OK) return mpg_fail(c, st, "problem %d: %s", i, c->last_error.c_str());
+  }
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P[a].l > P[b].l; });
+  out.assign(count + 1, BatchProblem{});
+  int64_t start = 0;
+  for (int k = 0; k < count; ++k) {
+    const mpg_dd_problem& q = P[order[k]];
+    BatchProblem& d = out[k + 1];
+    d.m = q.m;
+    d.n = q.n;
+    d.l = q.l;
+    d.lda = q.lda;
+    d.ldb = q.ldb;
+    d.ldc = q.ldc;
+    d.A[0] = q.A_hi;
+    d.A[1] = q.A_lo;
+    d.B[0] = q.B_hi;
+    d.B[1] = q.B_lo;
+    d.C[0] = q.C_hi;
+    d.C[1] = q.C_lo;
+    const int64_t tm = q.m > 0 && q.n > 0 ? (q.m + bm - 1) / bm : 0;
+    const int64_t tn = q.m > 0 && q.n > 0 ? (q.n + bn - 1) / bn : 1;
+    d.tiles_n = tn;
+    d.tile_start = start;
+    start += tm * tn;
+  }
+  out[0].tile_start = start;
+  out[0].tiles_n = count;
+  return MPG_OK;
+}
+
+int batch_variant(mpg_ctx* c, const mpg_tile* tile, int* v) {
+  if (!tile || (tile->bm == 0 && tile->bn == 0 && tile->bk == 0 && tile->tm == 0 && tile->tn == 0)) {
+    *v = 1;  // 32 x 32 tiles: most problems of a batch are small
+    return MPG_OK;
+  }
+  return mpg_resolve_variant(c, 2, tile, v);
+}
+
+int grid_for(mpg_ctx* c, int v, int64_t total) {
+  const int64_t g = (int64_t)c->num_cu * batch_blocks_per_cu(v);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, total));
+}
+
+}  // namespace
+
+extern "C" int mpgemm_dd_batched(mpg_ctx* c, int count, const mpg_dd_problem* problems,
+                                 const mpg_tile* tile) {
+  if (!c) return MPG_ERR_ARG;
+  int v, st;
+  if ((st = batch_variant(c, tile, &v)) != MPG_OK) return st;
+  std::vector<BatchProblem> desc;
+  if ((st = build_desc(c, count, problems, v, desc)) != MPG_OK) return st;
+  if (count == 0 || desc[0].tile_start == 0) return MPG_OK;
+  if ((st = mpg_device_guard(c)) != MPG_OK) return st;
+  // the previous call's descriptors may still be read by the device
+  hipError_t r = hipStreamSynchronize(c->stream);
+  if (r != hipSuccess) return mpg_hip_fail(c, r, "hipStreamSynchronize (batch descriptors)");
+  void* d = nullptr;
+  if ((st = mpg_workspace(c, 2, desc.size() * sizeof(BatchProblem), &d)) != MPG_OK) return st;
+  c->batch_host.assign((const char*)desc.data(), (const char*)(desc.data() + desc.size()));
+  r = hipMemcpyAsync(d, c->batch_host.data(), c->batch_host.size(), hipMemcpyHostToDevice, c->stream);
+  if (r != hipSuccess) return mpg_hip_fail(c, r, "descriptor upload");
+  const int grid = grid_for(c, v, desc[0].tile_start);
+  return mpg_launch(c, MPG_KCLASS_GEMM,
+                    [&] { return launch_batch_persistent(v, (const BatchProblem*)d, grid, c->stream); },
+                    "persistent batch kernel");
+}
+
+extern "C" int mpg_batch_plan_create(mpg_ctx* c, int count, const mpg_dd_problem* problems,
+                                     const mpg_tile* tile, mpg_batch_plan** plan) {
+  if (!c || !plan) return MPG_ERR_ARG;
+  *plan = nullptr;
+  int v, st;
+  if ((st = batch_variant(c, tile, &v)) != MPG_OK) return st;
+  std::vector<BatchProblem> desc;
+  if ((st = build_desc(c, count, problems, v, desc)) != MPG_OK) return st;
+  if ((st = mpg_device_guard(c)) != MPG_OK) return st;
+  mpg_batch_plan* p = new mpg_batch_plan();
+  p->ctx = c;
+  p->count = count;
+  p->variant = v;
+  // the grid is fixed at capture; size it for the largest total tile count
+  // any later update may bring (the kernel reads the count at run time)
+  p->grid = (int)((int64_t)c->num_cu * batch_blocks_per_cu(v));
+  hipError_t r = hipMalloc(&p->d_desc, desc.size() * sizeof(BatchProblem));
+  if (r == hipSuccess)
+    r = hipMemcpy(p->d_desc, desc.data(), desc.size() * sizeof(BatchProblem), hipMemcpyHostToDevice);
+  hipStream_t cs = nullptr;
+  if (r == hipSuccess) r = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (r == hipSuccess) r = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (r == hipSuccess) {
+    hipError_t lr = launch_batch_persistent(v, p->d_desc, p->grid, cs);
+    r = hipStreamEndCapture(cs, &p->graph);
+    if (lr != hipSuccess) r = lr;
+  }
+  if (r == hipSuccess) r = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (r != hipSuccess) {
+    mpg_batch_plan_destroy(p);
+    return mpg_hip_fail(c, r, "batch plan capture");
+  }
+  *plan = p;
+  return MPG_OK;
+}
+
+extern "C" int mpg_batch_plan_update(mpg_batch_plan* p, const mpg_dd_problem* problems) {
+  if (!p) return MPG_ERR_ARG;
+  mpg_ctx* c = p->ctx;
+  std::vector<BatchProblem> desc;
+  int st = build_desc(c, p->count, problems, p->variant, desc);
+  if (st != MPG_OK) return st;
+  if ((st = mpg_device_guard(c)) != MPG_OK) return st;
+  hipError_t r = hipStreamSynchronize(c->stream);
+  if (r == hipSuccess)
+    r = hipMemcpy(p->d_desc, desc.data(), desc.size() * sizeof(BatchProblem), hipMemcpyHostToDevice);
+  if (r != hipSuccess) return mpg_hip_fail(c, r, "batch plan update");
+  return MPG_OK;
+}
+
+extern "C" int mpg_batch_plan_launch(mpg_batch_plan* p, void* stream) {
+  if (!p || !p->exec) return MPG_ERR_ARG;
+  mpg_ctx* c = p->ctx;
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+  if (s == c->stream)
+    return mpg_launch(c, MPG_KCLASS_GEMM, [&] { return hipGraphLaunch(p->exec, s); },
+                      "batch graph launch");
+  hipError_t r = hipGraphLaunch(p->exec, s);
+  return r == hipSuccess ? MPG_OK : mpg_hip_fail(c, r, "batch graph launch");
+}
+
+extern "C" int mpg_batch_plan_destroy(mpg_batch_plan* p) {
+  if (!p) return MPG_OK;
+  if (p->ctx) {
+    (void)mpg_device_guard(p->ctx);
+    (void)hipStreamSynchronize(p->ctx->stream);
+  }
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->d_desc) (void)hipFree(p->d_desc);
+  delete p;
+  return MPG_OK;
+}

@@ -22,9 +22,11 @@ struct mpg_ctx {
 
   // workspace slots (grow-only, freed with the context): 0 = large operand
   // workspace (Strassen blocks, digit planes), 1 = small (exponents, counters)
-  static constexpr int kSlots = 2;
-  void* ws[kSlots] = {nullptr, nullptr};
-  size_t ws_size[kSlots] = {0, 0};
+  // 2 = batch descriptors
+  static constexpr int kSlots = 3;
+  void* ws[kSlots] = {nullptr, nullptr, nullptr};
+  size_t ws_size[kSlots] = {0, 0, 0};
+  std::string batch_host;  // host copy of the last batch descriptors (upload source)
   bool alloc_hook_fail = false;  // test seam: make the next allocations fail
 
   // kernel timing

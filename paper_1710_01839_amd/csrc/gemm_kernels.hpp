@@ -84,9 +84,20 @@ hipError_t launch_simple(const GemmBatch& g, hipStream_t s) {
 // so every c_ij sees exactly the operation sequence of the simple kernel
 // (zero padding beyond l changes no accumulator).
 // ---------------------------------------------------------------------
-template <class Arith, int BM, int BN, int BK, int TM, int TN, int MINW>
-__global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(GemmBatch g, int tiles_m,
-                                                                      int tiles_n) {
+// LDS of one block-kernel workgroup.
+template <int L, int BM, int BN, int BK>
+struct BlockSmem {
+  double A[2][L][BM * (BK + 2)];
+  double B[2][L][BK * BN];
+};
+
+// One BM x BN output tile at (m0, n0) of the product C_p := A_p B_p whose
+// limb planes start at Ap/Bp/Cp.  Called by every thread of the workgroup.
+template <class Arith, int BM, int BN, int BK, int TM, int TN>
+__device__ __forceinline__ void block_tile(BlockSmem<Arith::L, BM, BN, BK>& sm, int64_t m, int64_t n,
+                                           int64_t l, const double* const* Ap, int64_t lda,
+                                           const double* const* Bp, int64_t ldb,
+                                           double* const* Cp, int64_t ldc, int64_t m0, int64_t n0) {
   constexpr int L = Arith::L;
   constexpr int NTX = BN / TN;
   constexpr int NTY = BM / TM;
@@ -98,27 +109,9 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
   static_assert(BK % 2 == 0 && TN % 2 == 0, "tile shape");
   static_assert(Arith::kRenorm == 0 || BK % Arith::kRenorm == 0, "renormalisation period");
 
-  __shared__ double sA[2][L][BM * LDS_A];
-  __shared__ double sB[2][L][BK * BN];
-
   const int tid = threadIdx.x;
   const int tx = tid % NTX;
   const int ty = tid / NTX;
-
-  const int per_problem = tiles_m * tiles_n;
-  const int w = xcd_remap(blockIdx.x, gridDim.x);
-  const int p = w / per_problem;
-  int tm, tn;
-  tile_coords(w - p * per_problem, tiles_m, tiles_n, tm, tn);
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-
-  const double* Ap[L];
-  const double* Bp[L];
-#pragma unroll
-  for (int q = 0; q < L; ++q) {
-    Ap[q] = g.A[q] + p * g.sA;
-    Bp[q] = g.B[q] + p * g.sB;
-  }
 
   double ra[L][LA], rb[L][LB];
 
@@ -128,10 +121,10 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
       const int e = tid + r * NT;
       const int row = e / BK, col = e % BK;
       const int64_t gi = m0 + row, gk = k0 + col;
-      const bool ok = gi < g.m && gk < g.l;
+      const bool ok = gi < m && gk < l;
       // always load (from element 0 when outside), then select: no branch,
       // so the loads stay in flight during the current step's arithmetic
-      const int64_t off = ok ? gi * g.lda + gk : 0;
+      const int64_t off = ok ? gi * lda + gk : 0;
 #pragma unroll
       for (int q = 0; q < L; ++q) {
         const double v = Ap[q][off];
@@ -143,8 +136,8 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
       const int e = tid + r * NT;
       const int row = e / BN, col = e % BN;
       const int64_t gk = k0 + row, gj = n0 + col;
-      const bool ok = gk < g.l && gj < g.n;
-      const int64_t off = ok ? gk * g.ldb + gj : 0;
+      const bool ok = gk < l && gj < n;
+      const int64_t off = ok ? gk * ldb + gj : 0;
 #pragma unroll
       for (int q = 0; q < L; ++q) {
         const double v = Bp[q][off];
@@ -158,13 +151,13 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
       const int e = tid + r * NT;
       const int row = e / BK, col = e % BK;
 #pragma unroll
-      for (int q = 0; q < L; ++q) sA[buf][q][row * LDS_A + col] = ra[q][r];
+      for (int q = 0; q < L; ++q) sm.A[buf][q][row * LDS_A + col] = ra[q][r];
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       const int e = tid + r * NT;
 #pragma unroll
-      for (int q = 0; q < L; ++q) sB[buf][q][e] = rb[q][r];
+      for (int q = 0; q < L; ++q) sm.B[buf][q][e] = rb[q][r];
     }
   };
 
@@ -176,9 +169,11 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
 #pragma unroll
       for (int q = 0; q < L; ++q) acc[i][j][q] = 0.0;
 
-  const int numK = (int)((g.l + BK - 1) / BK);
-  load_tile(0);
-  store_tile(0);
+  const int numK = (int)((l + BK - 1) / BK);
+  if (numK > 0) {
+    load_tile(0);
+    store_tile(0);
+  }
   __syncthreads();
 
   for (int t = 0; t < numK; ++t) {
@@ -194,7 +189,7 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int q = 0; q < L; ++q)
-          a2[i][q] = *reinterpret_cast<const double2*>(&sA[cur][q][(ty * TM + i) * LDS_A + kp]);
+          a2[i][q] = *reinterpret_cast<const double2*>(&sm.A[cur][q][(ty * TM + i) * LDS_A + kp]);
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
         double b[TN][L];
@@ -203,7 +198,7 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
 #pragma unroll
           for (int q = 0; q < L; ++q) {
             const double2 x =
-                *reinterpret_cast<const double2*>(&sB[cur][q][(kp + kk) * BN + tx * TN + j]);
+                *reinterpret_cast<const double2*>(&sm.B[cur][q][(kp + kk) * BN + tx * TN + j]);
             b[j][q] = x.x;
             b[j + 1][q] = x.y;
           }
@@ -230,16 +225,42 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int64_t gi = m0 + ty * TM + i;
-    if (gi >= g.m) continue;
+    if (gi >= m) continue;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int64_t gj = n0 + tx * TN + j;
-      if (gj >= g.n) continue;
+      if (gj >= n) continue;
       Arith::finish(acc[i][j]);
 #pragma unroll
-      for (int q = 0; q < L; ++q) g.C[q][p * g.sC + gi * g.ldc + gj] = acc[i][j][q];
+      for (int q = 0; q < L; ++q) Cp[q][gi * ldc + gj] = acc[i][j][q];
     }
   }
+}
+
+// Block algorithm, Eq. (2): one workgroup per output tile of one of
+// g.count equal-shape problems.  MINW is the minimum number of resident
+// wavefronts per SIMD the register allocation must allow.
+template <class Arith, int BM, int BN, int BK, int TM, int TN, int MINW>
+__global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(GemmBatch g, int tiles_m,
+                                                                            int tiles_n) {
+  constexpr int L = Arith::L;
+  __shared__ BlockSmem<L, BM, BN, BK> sm;
+  const int per_problem = tiles_m * tiles_n;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int p = w / per_problem;
+  int tm, tn;
+  tile_coords(w - p * per_problem, tiles_m, tiles_n, tm, tn);
+  const double* Ap[L];
+  const double* Bp[L];
+  double* Cp[L];
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    Ap[q] = g.A[q] + p * g.sA;
+    Bp[q] = g.B[q] + p * g.sB;
+    Cp[q] = g.C[q] + p * g.sC;
+  }
+  block_tile<Arith, BM, BN, BK, TM, TN>(sm, g.m, g.n, g.l, Ap, g.lda, Bp, g.ldb, Cp, g.ldc,
+                                        (int64_t)tm * BM, (int64_t)tn * BN);
 }
 
 template <class Arith, int BM, int BN, int BK, int TM, int TN, int MINW = 2>

@@ -39,6 +39,14 @@ class mpg_tile(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class mpg_dd_problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("l", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldc", ctypes.c_int64),
+                ("A_hi", ctypes.c_void_p), ("A_lo", ctypes.c_void_p),
+                ("B_hi", ctypes.c_void_p), ("B_lo", ctypes.c_void_p),
+                ("C_hi", ctypes.c_void_p), ("C_lo", ctypes.c_void_p)]
+
+
 class MpgemmError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{message} (status {status})")
@@ -73,6 +81,12 @@ _sig("mpgemm_ozaki_dd", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, 
 _sig("mpg_ozaki_slices_exact", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(_ci)])
 _sig("mpg_ozaki_split", [_vp, _ci, _i64, _i64, _vp, _i64, _ci, _vp, _i64, _i64, _vp])
 _sig("mpg_ozaki_last_slices", [_vp])
+_sig("mpgemm_dd_batched", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile)])
+_sig("mpg_batch_plan_create", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile),
+                               ctypes.POINTER(_vp)])
+_sig("mpg_batch_plan_launch", [_vp, _vp])
+_sig("mpg_batch_plan_update", [_vp, ctypes.POINTER(mpg_dd_problem)])
+_sig("mpg_batch_plan_destroy", [_vp])
 _sig("mpg_prof_enable", [_vp, _ci])
 _sig("mpg_prof_read", [_vp, _ci, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
 
@@ -249,6 +263,67 @@ def ozaki_split(ctx: Context, X, slices: int, side: int = 0):
     ctx.check(_lib.mpg_ozaki_split(ctx.handle, side, rows, cols, _ptr(X), ldx, slices, _ptr(out),
                                    kp, lp * kp, _ptr(exps)), "mpg_ozaki_split")
     return out, exps
+
+
+def _problems(probs):
+    """probs: list of (A, B, C) with A, B, C (hi, lo) tensor pairs."""
+    arr = (mpg_dd_problem * max(1, len(probs)))()
+    for i, (A, B, C) in enumerate(probs):
+        m, l, lda = _mat(A[0], "A_hi")
+        l2, n, ldb = _mat(B[0], "B_hi")
+        m2, n2, ldc = _mat(C[0], "C_hi")
+        if l2 != l or m2 != m or n2 != n:
+            raise MpgemmError(MPG_ERR_ARG, f"problem {i}: shape mismatch")
+        arr[i] = mpg_dd_problem(m, n, l, lda, ldb, ldc, A[0].data_ptr(), A[1].data_ptr(),
+                                B[0].data_ptr(), B[1].data_ptr(), C[0].data_ptr(), C[1].data_ptr())
+    return arr
+
+
+def mpgemm_dd_batched(ctx: Context, probs, tile=None):
+    arr = _problems(probs)
+    t = make_tile(tile)
+    ctx.bind_stream()
+    ctx.check(_lib.mpgemm_dd_batched(ctx.handle, len(probs), arr,
+                                     ctypes.byref(t) if t is not None else None), "mpgemm_dd_batched")
+
+
+class BatchPlan:
+    """A persistent batched launch captured once in a HIP graph."""
+
+    def __init__(self, ctx: Context, probs, tile=None):
+        self.ctx = ctx
+        self.count = len(probs)
+        self._keep = probs
+        arr = _problems(probs)
+        t = make_tile(tile)
+        h = _vp()
+        ctx.bind_stream()
+        ctx.check(_lib.mpg_batch_plan_create(ctx.handle, self.count, arr,
+                                             ctypes.byref(t) if t is not None else None,
+                                             ctypes.byref(h)), "mpg_batch_plan_create")
+        self.handle = h
+
+    def launch(self):
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_batch_plan_launch(self.handle, None), "mpg_batch_plan_launch")
+
+    def update(self, probs):
+        if len(probs) != self.count:
+            raise MpgemmError(MPG_ERR_ARG, "update needs the same problem count")
+        self._keep = probs
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_batch_plan_update(self.handle, _problems(probs)), "mpg_batch_plan_update")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mpg_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def empty_like_limbs(m: int, n: int, limbs: int, device="cuda"):
