@@ -196,6 +196,87 @@ int mpg_ozaki_split(mpg_ctx* ctx, int side, int64_t rows, int64_t cols,
 /* Slice count used by the context's last mpgemm_ozaki_dd call. */
 int mpg_ozaki_last_slices(const mpg_ctx* ctx);
 
+/* ---- tuner (Section 3) ------------------------------------------------ */
+
+typedef enum {
+  MPG_TUNE_EXHAUSTIVE = 0, /* time every candidate at full size */
+  MPG_TUNE_PAPER = 1,      /* the paper's procedure: (1) predict the block time of
+                              every tile from a slab product, keep the best tile;
+                              (2) time simple, block and Strassen over that tile;
+                              (3) take the fastest */
+  MPG_TUNE_MLP = 2         /* the run-time model ranks every candidate; only the
+                              best `topk` are timed, the fastest measured wins */
+} mpg_tune_mode;
+
+/* Candidates for a shape: MPG_SIMPLE, MPG_BLOCK with every built tile,
+ * MPG_STRASSEN with every tile and depth 1..3 (DD) / 1..2 (QD) while the
+ * leaves keep at least 64 per side.  precision: 2 (DD) or 4 (QD). */
+int mpg_num_candidates(int precision, int64_t m, int64_t n, int64_t l);
+int mpg_candidate(int precision, int64_t m, int64_t n, int64_t l, int index,
+                  int* algo, mpg_tile* tile);
+
+/* Append every measurement to the JSONL file `path` (NULL: stop). */
+int mpg_tune_set_db(mpg_ctx* ctx, const char* path);
+
+/* Median of `reps` HIP-event timings (after one warm-up run) of one
+ * candidate on library-owned buffers of the shape; milliseconds. */
+int mpg_time_candidate(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
+                       int algo, const mpg_tile* tile, int reps, double* ms);
+
+/* Section 3's prediction of the full-size block time from a partial
+ * product: time A[0:r, :] B and scale.  rule 1: r = 2 bm (two block rows)
+ * scaled by m / r, as printed for CPUs; rule 0 (GPU form): r holds enough
+ * tile rows to occupy every resident workgroup once, scaled by the ratio of
+ * workgroup waves of the full and the partial product. */
+int mpg_predict_block(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
+                      const mpg_tile* tile, int rule, double* predicted_ms, double* slab_ms);
+
+/* Tune one shape; the winner also enters the context's table used by
+ * MPG_AUTO.  topk: candidates timed in MLP mode (0: 3).  Outputs (each
+ * nullable): winner, its median time, wall-clock seconds of the search
+ * (trials, warm-ups, predictions and model inference), number of
+ * full-size trials. */
+int mpg_tune(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l, int mode, int topk,
+             int* best_algo, mpg_tile* best_tile, double* best_ms, double* seconds, int* trials);
+
+/* Put a choice into the table used by MPG_AUTO directly. */
+int mpg_tune_table_set(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
+                       int algo, const mpg_tile* tile);
+
+/* ---- run-time model (MLP) -------------------------------------------- */
+
+/* Features of one candidate (MPG_MLP_FEATURES floats): log2 m, n, l / 12;
+ * DD and QD indicators; simple / block / Strassen indicators; log2 bm / 8,
+ * log2 bn / 8, log2 bk / 5, tm tn / 64, Strassen depth / 3, log2 batch / 10.
+ * Target of the model: natural log of milliseconds. */
+#define MPG_MLP_FEATURES 14
+int mpg_mlp_features(int precision, int64_t m, int64_t n, int64_t l, int algo,
+                     const mpg_tile* tile, int batch, float* out);
+
+/* The model: MPG_MLP_FEATURES -> 64 -> 64 -> 1, ReLU, FP32, parameters in
+ * one array W1 (64 x F), b1, W2 (64 x 64), b2, W3 (64), b3, row-major. */
+int mpg_mlp_num_params(void);
+/* Set / read the parameters (host arrays of mpg_mlp_num_params floats);
+ * setting them resets the optimiser state. */
+int mpg_mlp_set_params(mpg_ctx* ctx, const float* params, int count);
+int mpg_mlp_get_params(mpg_ctx* ctx, float* params, int count);
+/* Mean squared error of the model on (X rows x F, y) and its gradient
+ * (host arrays), computed on the GPU. */
+int mpg_mlp_grad(mpg_ctx* ctx, const float* X, const float* y, int rows, float* loss,
+                 float* grad);
+/* Full-batch Adam (beta1 0.9, beta2 0.999, eps 1e-8) for `epochs` steps on
+ * the GPU; initialises the parameters (He-uniform, fixed seed) if none are
+ * set.  losses (nullable, `epochs` floats): loss before each step. */
+int mpg_mlp_train(mpg_ctx* ctx, const float* X, const float* y, int rows, int epochs,
+                  float lr, float* losses);
+/* Train on every trial row of a timing database written by the tuner. */
+int mpg_mlp_train_db(mpg_ctx* ctx, const char* path, int epochs, float lr,
+                     float* final_loss, int* rows_used);
+/* Predicted log-milliseconds for `rows` feature rows. */
+int mpg_mlp_predict(mpg_ctx* ctx, const float* X, int rows, float* out);
+int mpg_mlp_save(mpg_ctx* ctx, const char* path);
+int mpg_mlp_load(mpg_ctx* ctx, const char* path);
+
 /* ---- kernel timing (HIP events on the context stream) ------------------ */
 
 /* Kernel classes timed when profiling is on. */

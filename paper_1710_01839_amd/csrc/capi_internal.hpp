@@ -43,6 +43,9 @@ struct mpg_ctx {
   // tuning table: (precision, m, n, l) -> (algo, tile)
   std::map<std::tuple<int, int64_t, int64_t, int64_t>, std::pair<int, mpg_tile>> table;
 
+  // JSONL timing database of the tuner (empty: none)
+  std::string db_path;
+
   // slice count used by the last split-precision product
   int last_slices = 0;
 

@@ -5,19 +5,19 @@
 namespace mpg {
 namespace {
 
-using kern::launch_block;
+using kern::variant_entry;
 using kern::VariantEntry;
 
 // Built DD tile variants (BM, BN, BK, TM, TN, threads).  Index 0 is the
 // default.  BK must be a multiple of the 8-step renormalisation period.
 const VariantEntry kVariants[] = {
-    {{64, 64, 16, 4, 4, 256}, launch_block<DDArith, 64, 64, 16, 4, 4>},
-    {{32, 32, 16, 2, 2, 256}, launch_block<DDArith, 32, 32, 16, 2, 2>},
-    {{128, 64, 8, 8, 4, 256}, launch_block<DDArith, 128, 64, 8, 8, 4, 1>},
-    {{64, 128, 8, 4, 8, 256}, launch_block<DDArith, 64, 128, 8, 4, 8, 1>},
-    {{128, 128, 8, 8, 8, 256}, launch_block<DDArith, 128, 128, 8, 8, 8, 1>},
-    {{64, 64, 8, 4, 4, 256}, launch_block<DDArith, 64, 64, 8, 4, 4>},
-    {{32, 64, 16, 2, 4, 256}, launch_block<DDArith, 32, 64, 16, 2, 4>},
+    variant_entry<DDArith, 64, 64, 16, 4, 4>(),
+    variant_entry<DDArith, 32, 32, 16, 2, 2>(),
+    variant_entry<DDArith, 128, 64, 8, 8, 4, 1>(),
+    variant_entry<DDArith, 64, 128, 8, 4, 8, 1>(),
+    variant_entry<DDArith, 128, 128, 8, 8, 8, 1>(),
+    variant_entry<DDArith, 64, 64, 8, 4, 4>(),
+    variant_entry<DDArith, 32, 64, 16, 2, 4>(),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void zero_kernel(double* C0, double* C1, doubl
 
 int dd_num_variants() { return kNumVariants; }
 const TileVariant& dd_variant(int v) { return kVariants[v].v; }
+int dd_variant_resident(int v) { return kern::resident_blocks(kVariants[v]); }
 
 hipError_t launch_dd_simple(const GemmBatch& g, hipStream_t s) {
   return kern::launch_simple<DDArith>(g, s);

@@ -279,7 +279,22 @@ using LaunchFn = hipError_t (*)(const GemmBatch&, hipStream_t);
 struct VariantEntry {
   TileVariant v;
   LaunchFn fn;
+  const void* kernel;
 };
+
+template <class Arith, int BM, int BN, int BK, int TM, int TN, int MINW = 2>
+constexpr VariantEntry variant_entry() {
+  return VariantEntry{{BM, BN, BK, TM, TN, (BM / TM) * (BN / TN)},
+                      launch_block<Arith, BM, BN, BK, TM, TN, MINW>,
+                      reinterpret_cast<const void*>(&block_kernel<Arith, BM, BN, BK, TM, TN, MINW>)};
+}
+
+inline int resident_blocks(const VariantEntry& e) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, e.kernel, e.v.threads, 0) != hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
 
 // ---------------------------------------------------------------------
 // Winograd operand formation and assembly (accurate multi-limb sums).

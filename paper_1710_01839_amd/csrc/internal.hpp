@@ -29,6 +29,7 @@ struct TileVariant {
 // ---- DD (dd_gemm.hip) ----
 int dd_num_variants();
 const TileVariant& dd_variant(int v);
+int dd_variant_resident(int v);  // workgroups per CU
 hipError_t launch_dd_simple(const GemmBatch& g, hipStream_t s);
 hipError_t launch_dd_block(int variant, const GemmBatch& g, hipStream_t s);
 
@@ -65,6 +66,7 @@ hipError_t launch_dd_winograd_assemble(const AssembleArgs& a, hipStream_t s);
 // ---- QD (qd_gemm.hip) ----
 int qd_num_variants();
 const TileVariant& qd_variant(int v);
+int qd_variant_resident(int v);
 hipError_t launch_qd_simple(const GemmBatch& g, hipStream_t s);
 hipError_t launch_qd_block(int variant, const GemmBatch& g, hipStream_t s);
 hipError_t launch_qd_winograd_form(const FormArgs& a, hipStream_t s);

@@ -5,16 +5,16 @@
 namespace mpg {
 namespace {
 
-using kern::launch_block;
+using kern::variant_entry;
 using kern::VariantEntry;
 
 // Built QD tile variants (BM, BN, BK, TM, TN, threads).  Index 0 is the
 // default.
 const VariantEntry kVariants[] = {
-    {{32, 32, 8, 2, 2, 256}, launch_block<QDArith, 32, 32, 8, 2, 2>},
-    {{64, 32, 8, 4, 2, 256}, launch_block<QDArith, 64, 32, 8, 4, 2>},
-    {{64, 64, 8, 4, 4, 256}, launch_block<QDArith, 64, 64, 8, 4, 4, 1>},
-    {{32, 64, 8, 2, 4, 256}, launch_block<QDArith, 32, 64, 8, 2, 4>},
+    variant_entry<QDArith, 32, 32, 8, 2, 2>(),
+    variant_entry<QDArith, 64, 32, 8, 4, 2>(),
+    variant_entry<QDArith, 64, 64, 8, 4, 4, 1>(),
+    variant_entry<QDArith, 32, 64, 8, 2, 4>(),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -22,6 +22,7 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int qd_num_variants() { return kNumVariants; }
 const TileVariant& qd_variant(int v) { return kVariants[v].v; }
+int qd_variant_resident(int v) { return kern::resident_blocks(kVariants[v]); }
 
 hipError_t launch_qd_simple(const GemmBatch& g, hipStream_t s) {
   return kern::launch_simple<QDArith>(g, s);

@@ -1,5 +1,410 @@
-// Tuning table of the context (filled by the tuner).
+// Tuner: chooses the algorithm (simple / block / Strassen) and its tile and
+// depth for a shape by measured run time, following the tuning program of
+// Section 3: (1) predict the full-size block time of every tile from a
+// partial product (a slab of A's rows against the full B) and keep the best
+// tile, (2) time simple, block and Strassen at full size, (3) take the
+// fastest.  Also an exhaustive mode (every candidate timed) and a mode
+// where the run-time MLP ranks all candidates and only the best few are
+// timed.  Measurements are appended to a JSONL timing database.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "capi_internal.hpp"
+
+using namespace mpg;
+
+bool mpg_mlp_ready(mpg_ctx* c);
+void mpg_mlp_free(mpg_ctx* c);
+
+namespace {
+
+struct Cand {
+  int algo;
+  mpg_tile tile;
+};
+
+std::vector<Cand> candidates(int prec, int64_t m, int64_t n, int64_t l) {
+  std::vector<Cand> out;
+  Cand s{};
+  s.algo = MPG_SIMPLE;
+  out.push_back(s);
+  const int nv = mpg_num_variants(prec);
+  for (int v = 0; v < nv; ++v) {
+    Cand b{};
+    b.algo = MPG_BLOCK;
+    mpg_variant(prec, v, &b.tile);
+    out.push_back(b);
+  }
+  const int64_t mn = std::min(m, std::min(n, l));
+  const int maxd = prec == 2 ? 3 : 2;
+  for (int d = 1; d <= maxd; ++d) {
+    if (mn < (int64_t)64 << d) break;  // leaves of at least 64 per side
+    for (int v = 0; v < nv; ++v) {
+      Cand t{};
+      t.algo = MPG_STRASSEN;
+      mpg_variant(prec, v, &t.tile);
+      t.tile.depth = d;
+      out.push_back(t);
+    }
+  }
+  return out;
+}
+
+// Timing buffers for one shape: inputs are canonical multi-limb values with
+// zero lower limbs (the kernels' run time does not depend on the values).
+struct Scratch {
+  int limbs = 0;
+  int64_t m = 0, n = 0, l = 0;
+  double* A[4] = {};
+  double* B[4] = {};
+  double* C[4] = {};
+};
+
+__global__ void fill_kernel(double* p, int64_t n, uint64_t seed, int zero) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    if (zero) {
+      p[i] = 0.0;
+      continue;
+    }
+    uint64_t z = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    p[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+  }
+}
+
+void free_scratch(Scratch& s) {
+  for (int q = 0; q < 4; ++q) {
+    if (s.A[q]) (void)hipFree(s.A[q]);
+    if (s.B[q]) (void)hipFree(s.B[q]);
+    if (s.C[q]) (void)hipFree(s.C[q]);
+    s.A[q] = s.B[q] = s.C[q] = nullptr;
+  }
+}
+
+int make_scratch(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l, Scratch& s) {
+  s.limbs = limbs;
+  s.m = m;
+  s.n = n;
+  s.l = l;
+  hipError_t r = hipSuccess;
+  for (int q = 0; q < limbs && r == hipSuccess; ++q) {
+    r = hipMalloc(&s.A[q], (size_t)(m * l) * sizeof(double));
+    if (r == hipSuccess) r = hipMalloc(&s.B[q], (size_t)(l * n) * sizeof(double));
+    if (r == hipSuccess) r = hipMalloc(&s.C[q], (size_t)(m * n) * sizeof(double));
+  }
+  if (r != hipSuccess) {
+    free_scratch(s);
+    (void)hipGetLastError();
+    return mpg_fail(c, MPG_ERR_NOMEM, "tuner buffers for %lldx%lldx%lld", (long long)m,
+                    (long long)n, (long long)l);
+  }
+  for (int q = 0; q < limbs; ++q) {
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c->stream, s.A[q], m * l,
+                       (uint64_t)(11 + q), q > 0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c->stream, s.B[q], l * n,
+                       (uint64_t)(23 + q), q > 0);
+  }
+  r = hipStreamSynchronize(c->stream);
+  if (r != hipSuccess) {
+    free_scratch(s);
+    return mpg_hip_fail(c, r, "tuner buffer fill");
+  }
+  return MPG_OK;
+}
+
+int run(mpg_ctx* c, Scratch& s, int64_t rows, const Cand& cd) {
+  return mpg_gemm_common(c, s.limbs, rows, s.n, s.l, s.A, s.l, s.B, s.n, s.C, s.n,
+                         (mpg_algo)cd.algo, &cd.tile);
+}
+
+// Median of `reps` event-timed runs after one warm-up run.
+int time_rows(mpg_ctx* c, Scratch& s, int64_t rows, const Cand& cd, int reps, double* ms) {
+  int st = run(c, s, rows, cd);
+  if (st != MPG_OK) return st;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return mpg_fail(c, MPG_ERR_HIP, "hipEventCreate");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return mpg_fail(c, MPG_ERR_HIP, "hipEventCreate");
+  }
+  std::vector<double> t;
+  for (int r = 0; r < reps && st == MPG_OK; ++r) {
+    (void)hipEventRecord(a, c->stream);
+    st = run(c, s, rows, cd);
+    (void)hipEventRecord(b, c->stream);
+    if (st != MPG_OK) break;
+    hipError_t e = hipEventSynchronize(b);
+    float f = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+    if (e != hipSuccess) st = mpg_hip_fail(c, e, "tuner timing");
+    t.push_back(f);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != MPG_OK) return st;
+  std::sort(t.begin(), t.end());
+  *ms = t[t.size() / 2];
+  return MPG_OK;
+}
+
+void db_append(mpg_ctx* c, int prec, int64_t m, int64_t n, int64_t l, const Cand& cd, double ms,
+               const char* kind) {
+  if (c->db_path.empty()) return;
+  FILE* f = std::fopen(c->db_path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"prec\":%d,\"m\":%lld,\"n\":%lld,\"l\":%lld,\"algo\":%d,\"bm\":%d,\"bn\":%d,"
+               "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"ms\":%.6f,\"kind\":\"%s\"}\n",
+               prec, (long long)m, (long long)n, (long long)l, cd.algo, cd.tile.bm, cd.tile.bn,
+               cd.tile.bk, cd.tile.tm, cd.tile.tn, cd.algo == MPG_STRASSEN ? cd.tile.depth : 0, ms,
+               kind);
+  std::fclose(f);
+}
+
+// Workgroups of a block variant resident per CU (occupancy of the built
+// kernel).
+int resident_per_cu(mpg_ctx* c, int prec, const mpg_tile& t) {
+  int v = 0;
+  if (mpg_resolve_variant(c, prec, &t, &v) != MPG_OK) return 1;
+  return prec == 2 ? dd_variant_resident(v) : qd_variant_resident(v);
+}
+
+}  // namespace
+
+extern "C" int mpg_num_candidates(int precision, int64_t m, int64_t n, int64_t l) {
+  if ((precision != 2 && precision != 4) || m <= 0 || n <= 0 || l <= 0) return 0;
+  return (int)candidates(precision, m, n, l).size();
+}
+
+extern "C" int mpg_candidate(int precision, int64_t m, int64_t n, int64_t l, int index, int* algo,
+                             mpg_tile* tile) {
+  if ((precision != 2 && precision != 4) || !algo || !tile) return MPG_ERR_ARG;
+  auto cs = candidates(precision, m, n, l);
+  if (index < 0 || index >= (int)cs.size()) return MPG_ERR_ARG;
+  *algo = cs[index].algo;
+  *tile = cs[index].tile;
+  return MPG_OK;
+}
+
+extern "C" int mpg_tune_set_db(mpg_ctx* c, const char* path) {
+  if (!c) return MPG_ERR_ARG;
+  c->db_path = path ? path : "";
+  return MPG_OK;
+}
+
+extern "C" int mpg_time_candidate(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l,
+                                  int algo, const mpg_tile* tile, int reps, double* ms) {
+  if (!c || !ms || (precision != 2 && precision != 4) || m <= 0 || n <= 0 || l <= 0 || reps < 1)
+    return c ? mpg_fail(c, MPG_ERR_ARG, "bad timing request") : MPG_ERR_ARG;
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  Scratch s;
+  if ((st = make_scratch(c, precision, m, n, l, s)) != MPG_OK) return st;
+  Cand cd{};
+  cd.algo = algo;
+  if (tile) cd.tile = *tile;
+  st = time_rows(c, s, m, cd, reps, ms);
+  if (st == MPG_OK) db_append(c, precision, m, n, l, cd, *ms, "trial");
+  free_scratch(s);
+  return st;
+}
+
+// Prediction of the full-size block-algorithm time from a partial product
+// (Section 3).  rule 0 (GPU): the slab holds enough tile rows to fill the
+// GPU once (all resident workgroups busy); time scales with the number of
+// waves of workgroups.  rule 1 (as printed for CPUs): the slab is two block
+// rows (2 bm rows) and time scales linearly in rows.
+static int predict_block(mpg_ctx* c, Scratch& s, int prec, const mpg_tile& t, int rule,
+                         double* pred, double* slab_ms) {
+  const int64_t m = s.m, n = s.n;
+  Cand cd{};
+  cd.algo = MPG_BLOCK;
+  cd.tile = t;
+  const int64_t tiles_n = (n + t.bn - 1) / t.bn, tiles_m = (m + t.bm - 1) / t.bm;
+  int64_t rows;
+  double scale;
+  if (rule == 1) {
+    rows = std::min<int64_t>(m, 2 * (int64_t)t.bm);
+    scale = (double)m / (double)rows;
+  } else {
+    const int64_t W = (int64_t)c->num_cu * resident_per_cu(c, prec, t);
+    const int64_t tile_rows = std::min<int64_t>(tiles_m, std::max<int64_t>(1, (W + tiles_n - 1) / tiles_n));
+    rows = std::min<int64_t>(m, tile_rows * t.bm);
+    const int64_t waves_full = (tiles_m * tiles_n + W - 1) / W;
+    const int64_t waves_slab = (((rows + t.bm - 1) / t.bm) * tiles_n + W - 1) / W;
+    scale = (double)waves_full / (double)std::max<int64_t>(1, waves_slab);
+  }
+  int st = time_rows(c, s, rows, cd, 3, slab_ms);
+  if (st != MPG_OK) return st;
+  *pred = *slab_ms * scale;
+  return MPG_OK;
+}
+
+extern "C" int mpg_predict_block(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l,
+                                 const mpg_tile* tile, int rule, double* predicted_ms,
+                                 double* slab_ms) {
+  if (!c || !predicted_ms || (precision != 2 && precision != 4) || m <= 0 || n <= 0 || l <= 0 ||
+      (rule != 0 && rule != 1))
+    return c ? mpg_fail(c, MPG_ERR_ARG, "bad prediction request") : MPG_ERR_ARG;
+  int v = 0;
+  int st = mpg_resolve_variant(c, precision, tile, &v);
+  if (st != MPG_OK) return st;
+  mpg_tile t;
+  mpg_variant(precision, v, &t);
+  if ((st = mpg_device_guard(c)) != MPG_OK) return st;
+  Scratch s;
+  if ((st = make_scratch(c, precision, m, n, l, s)) != MPG_OK) return st;
+  double sm = 0.0;
+  st = predict_block(c, s, precision, t, rule, predicted_ms, &sm);
+  if (slab_ms) *slab_ms = sm;
+  free_scratch(s);
+  return st;
+}
+
+extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l, int mode,
+                        int topk, int* best_algo, mpg_tile* best_tile, double* best_ms,
+                        double* seconds, int* trials) {
+  if (!c) return MPG_ERR_ARG;
+  if ((precision != 2 && precision != 4) || m <= 0 || n <= 0 || l <= 0 || mode < 0 || mode > 2)
+    return mpg_fail(c, MPG_ERR_ARG, "bad tuning request");
+  if (mode == MPG_TUNE_MLP && !mpg_mlp_ready(c))
+    return mpg_fail(c, MPG_ERR_STATE, "MLP mode needs a trained or loaded run-time model");
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  Scratch s;
+  if ((st = make_scratch(c, precision, m, n, l, s)) != MPG_OK) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  const auto cands = candidates(precision, m, n, l);
+  int ntrials = 0;
+  Cand best{};
+  double bms = INFINITY;
+  auto trial = [&](const Cand& cd) -> int {
+    double ms = 0.0;
+    int r = time_rows(c, s, m, cd, 3, &ms);
+    if (r != MPG_OK) return r;
+    ++ntrials;
+    db_append(c, precision, m, n, l, cd, ms, "trial");
+    if (ms < bms) {
+      bms = ms;
+      best = cd;
+    }
+    return MPG_OK;
+  };
+  if (mode == MPG_TUNE_EXHAUSTIVE) {
+    for (const auto& cd : cands)
+      if ((st = trial(cd)) != MPG_OK) break;
+  } else if (mode == MPG_TUNE_PAPER) {
+    // (1) predicted block time for every tile, keep the best tile
+    double bp = INFINITY;
+    mpg_tile bt{};
+    for (const auto& cd : cands) {
+      if (cd.algo != MPG_BLOCK) continue;
+      double pred = 0.0, slab = 0.0;
+      if ((st = predict_block(c, s, precision, cd.tile, 0, &pred, &slab)) != MPG_OK) break;
+      db_append(c, precision, m, n, l, cd, pred, "predicted");
+      if (pred < bp) {
+        bp = pred;
+        bt = cd.tile;
+      }
+    }
+    // (2) simple, block with that tile, and Strassen over it, at full size
+    if (st == MPG_OK) {
+      std::vector<Cand> finals;
+      Cand x{};
+      x.algo = MPG_SIMPLE;
+      finals.push_back(x);
+      x.algo = MPG_BLOCK;
+      x.tile = bt;
+      finals.push_back(x);
+      for (const auto& cd : cands)
+        if (cd.algo == MPG_STRASSEN && cd.tile.bm == bt.bm && cd.tile.bn == bt.bn &&
+            cd.tile.bk == bt.bk && cd.tile.tm == bt.tm && cd.tile.tn == bt.tn)
+          finals.push_back(cd);
+      // (3) the fastest of them
+      for (const auto& cd : finals)
+        if ((st = trial(cd)) != MPG_OK) break;
+    }
+  } else {
+    // the run-time model ranks every candidate, the best `topk` are timed
+    std::vector<float> X(cands.size() * MPG_MLP_FEATURES), y(cands.size());
+    for (size_t i = 0; i < cands.size(); ++i)
+      mpg_mlp_features(precision, m, n, l, cands[i].algo, &cands[i].tile, 1,
+                       &X[i * MPG_MLP_FEATURES]);
+    st = mpg_mlp_predict(c, X.data(), (int)cands.size(), y.data());
+    if (st == MPG_OK) {
+      std::vector<size_t> idx(cands.size());
+      for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+      std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return y[a] < y[b]; });
+      const int k = std::max(1, std::min<int>(topk > 0 ? topk : 3, (int)idx.size()));
+      for (int i = 0; i < k; ++i)
+        if ((st = trial(cands[idx[i]])) != MPG_OK) break;
+    }
+  }
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  free_scratch(s);
+  if (st != MPG_OK) return st;
+  if (best_algo) *best_algo = best.algo;
+  if (best_tile) *best_tile = best.tile;
+  if (best_ms) *best_ms = bms;
+  if (seconds) *seconds = secs;
+  if (trials) *trials = ntrials;
+  c->table[std::make_tuple(precision, m, n, l)] = std::make_pair(best.algo, best.tile);
+  return MPG_OK;
+}
+
+extern "C" int mpg_tune_table_set(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l,
+                                  int algo, const mpg_tile* tile) {
+  if (!c || (precision != 2 && precision != 4) || algo < MPG_SIMPLE || algo > MPG_STRASSEN)
+    return MPG_ERR_ARG;
+  mpg_tile t{};
+  if (tile) t = *tile;
+  c->table[std::make_tuple(precision, m, n, l)] = std::make_pair(algo, t);
+  return MPG_OK;
+}
+
+// Train the run-time model on every "trial" row of a timing database
+// (target: natural log of the milliseconds).
+extern "C" int mpg_mlp_train_db(mpg_ctx* c, const char* path, int epochs, float lr,
+                                float* final_loss, int* rows_used) {
+  if (!c || !path) return MPG_ERR_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return mpg_fail(c, MPG_ERR_ARG, "cannot open %s", path);
+  std::vector<float> X, y;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    int prec, algo, bm, bn, bk, tm, tn, depth;
+    long long m, n, l;
+    double ms;
+    char kind[32];
+    if (std::sscanf(line,
+                    "{\"prec\":%d,\"m\":%lld,\"n\":%lld,\"l\":%lld,\"algo\":%d,\"bm\":%d,\"bn\":%d,"
+                    "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"ms\":%lf,\"kind\":\"%31[a-z]\"",
+                    &prec, &m, &n, &l, &algo, &bm, &bn, &bk, &tm, &tn, &depth, &ms, kind) != 13)
+      continue;
+    if (std::strcmp(kind, "trial") != 0 || !(ms > 0.0)) continue;
+    mpg_tile t{bm, bn, bk, tm, tn, depth, 0};
+    float feat[MPG_MLP_FEATURES];
+    if (mpg_mlp_features(prec, m, n, l, algo, &t, 1, feat) != MPG_OK) continue;
+    X.insert(X.end(), feat, feat + MPG_MLP_FEATURES);
+    y.push_back((float)std::log(ms));
+  }
+  std::fclose(f);
+  if (y.empty()) return mpg_fail(c, MPG_ERR_ARG, "no timing rows in %s", path);
+  std::vector<float> losses(epochs);
+  int st = mpg_mlp_train(c, X.data(), y.data(), (int)y.size(), epochs, lr, losses.data());
+  if (st != MPG_OK) return st;
+  if (final_loss) *final_loss = losses.back();
+  if (rows_used) *rows_used = (int)y.size();
+  return MPG_OK;
+}
 
 bool mpg_table_lookup(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l, int* algo,
                       mpg_tile* tile) {
@@ -10,4 +415,4 @@ bool mpg_table_lookup(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l
   return true;
 }
 
-void mpg_destroy_cached(mpg_ctx*) {}
+void mpg_destroy_cached(mpg_ctx* c) { mpg_mlp_free(c); }

@@ -87,6 +87,26 @@ _sig("mpg_batch_plan_create", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.
 _sig("mpg_batch_plan_launch", [_vp, _vp])
 _sig("mpg_batch_plan_update", [_vp, ctypes.POINTER(mpg_dd_problem)])
 _sig("mpg_batch_plan_destroy", [_vp])
+_f = ctypes.POINTER(ctypes.c_float)
+_d = ctypes.POINTER(ctypes.c_double)
+_sig("mpg_num_candidates", [_ci, _i64, _i64, _i64])
+_sig("mpg_candidate", [_ci, _i64, _i64, _i64, _ci, ctypes.POINTER(_ci), ctypes.POINTER(mpg_tile)])
+_sig("mpg_tune_set_db", [_vp, ctypes.c_char_p])
+_sig("mpg_time_candidate", [_vp, _ci, _i64, _i64, _i64, _ci, ctypes.POINTER(mpg_tile), _ci, _d])
+_sig("mpg_predict_block", [_vp, _ci, _i64, _i64, _i64, ctypes.POINTER(mpg_tile), _ci, _d, _d])
+_sig("mpg_tune", [_vp, _ci, _i64, _i64, _i64, _ci, _ci, ctypes.POINTER(_ci), ctypes.POINTER(mpg_tile),
+                  _d, _d, ctypes.POINTER(_ci)])
+_sig("mpg_tune_table_set", [_vp, _ci, _i64, _i64, _i64, _ci, ctypes.POINTER(mpg_tile)])
+_sig("mpg_mlp_features", [_ci, _i64, _i64, _i64, _ci, ctypes.POINTER(mpg_tile), _ci, _f])
+_sig("mpg_mlp_num_params", [])
+_sig("mpg_mlp_set_params", [_vp, _f, _ci])
+_sig("mpg_mlp_get_params", [_vp, _f, _ci])
+_sig("mpg_mlp_grad", [_vp, _f, _f, _ci, _f, _f])
+_sig("mpg_mlp_train", [_vp, _f, _f, _ci, _ci, ctypes.c_float, _f])
+_sig("mpg_mlp_train_db", [_vp, ctypes.c_char_p, _ci, ctypes.c_float, _f, ctypes.POINTER(_ci)])
+_sig("mpg_mlp_predict", [_vp, _f, _ci, _f])
+_sig("mpg_mlp_save", [_vp, ctypes.c_char_p])
+_sig("mpg_mlp_load", [_vp, ctypes.c_char_p])
 _sig("mpg_prof_enable", [_vp, _ci])
 _sig("mpg_prof_read", [_vp, _ci, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
 
@@ -324,6 +344,145 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+MLP_FEATURES = 14
+TUNE_MODES = {"exhaustive": 0, "paper": 1, "mlp": 2}
+PRECISION = {"dd": 2, "qd": 4}
+
+
+def _prec(p):
+    return PRECISION.get(p, p) if isinstance(p, str) else int(p)
+
+
+def candidates(precision, m, n, l):
+    p = _prec(precision)
+    out = []
+    for i in range(_lib.mpg_num_candidates(p, m, n, l)):
+        a, t = ctypes.c_int(), mpg_tile()
+        _lib.mpg_candidate(p, m, n, l, i, ctypes.byref(a), ctypes.byref(t))
+        out.append((a.value, t.as_dict()))
+    return out
+
+
+def mlp_features(precision, m, n, l, algo, tile=None, batch=1):
+    import numpy as np
+    out = np.zeros(MLP_FEATURES, dtype=np.float32)
+    t = make_tile(tile)
+    st = _lib.mpg_mlp_features(_prec(precision), m, n, l, ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
+                               ctypes.byref(t) if t is not None else None, batch,
+                               out.ctypes.data_as(_f))
+    if st != MPG_OK:
+        raise MpgemmError(st, "mpg_mlp_features")
+    return out
+
+
+def _fp(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(_f)
+
+
+class Tuner:
+    """Tuner calls on a context (library-owned timing buffers)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+
+    def set_db(self, path):
+        self.ctx.check(_lib.mpg_tune_set_db(self.ctx.handle, path.encode() if path else None),
+                       "mpg_tune_set_db")
+
+    def time(self, precision, m, n, l, algo, tile=None, reps=3):
+        ms = ctypes.c_double()
+        t = make_tile(tile)
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_time_candidate(self.ctx.handle, _prec(precision), m, n, l,
+                                               ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
+                                               ctypes.byref(t) if t is not None else None, reps,
+                                               ctypes.byref(ms)), "mpg_time_candidate")
+        return ms.value
+
+    def predict_block(self, precision, m, n, l, tile=None, rule=0):
+        pred, slab = ctypes.c_double(), ctypes.c_double()
+        t = make_tile(tile)
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_predict_block(self.ctx.handle, _prec(precision), m, n, l,
+                                              ctypes.byref(t) if t is not None else None, rule,
+                                              ctypes.byref(pred), ctypes.byref(slab)), "mpg_predict_block")
+        return pred.value, slab.value
+
+    def tune(self, precision, m, n, l, mode="exhaustive", topk=0):
+        a, t = ctypes.c_int(), mpg_tile()
+        ms, secs, trials = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_tune(self.ctx.handle, _prec(precision), m, n, l,
+                                     TUNE_MODES.get(mode, mode), topk, ctypes.byref(a), ctypes.byref(t),
+                                     ctypes.byref(ms), ctypes.byref(secs), ctypes.byref(trials)), "mpg_tune")
+        return {"algo": a.value, "tile": t.as_dict(), "ms": ms.value, "seconds": secs.value,
+                "trials": trials.value}
+
+
+class MLP:
+    """The run-time model owned by a context (GPU kernels)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.nparams = _lib.mpg_mlp_num_params()
+
+    def set_params(self, flat):
+        a, p = _fp(flat)
+        self.ctx.check(_lib.mpg_mlp_set_params(self.ctx.handle, p, a.size), "mpg_mlp_set_params")
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.nparams, dtype=np.float32)
+        self.ctx.check(_lib.mpg_mlp_get_params(self.ctx.handle, out.ctypes.data_as(_f), out.size),
+                       "mpg_mlp_get_params")
+        return out
+
+    def grad(self, X, y):
+        import numpy as np
+        Xa, Xp = _fp(X)
+        ya, yp = _fp(y)
+        g = np.zeros(self.nparams, dtype=np.float32)
+        loss = ctypes.c_float()
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_mlp_grad(self.ctx.handle, Xp, yp, ya.size, ctypes.byref(loss),
+                                         g.ctypes.data_as(_f)), "mpg_mlp_grad")
+        return loss.value, g
+
+    def train(self, X, y, epochs, lr=1e-3):
+        import numpy as np
+        Xa, Xp = _fp(X)
+        ya, yp = _fp(y)
+        losses = np.zeros(epochs, dtype=np.float32)
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_mlp_train(self.ctx.handle, Xp, yp, ya.size, epochs, lr,
+                                          losses.ctypes.data_as(_f)), "mpg_mlp_train")
+        return losses
+
+    def train_db(self, path, epochs, lr=1e-3):
+        loss, rows = ctypes.c_float(), ctypes.c_int()
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_mlp_train_db(self.ctx.handle, path.encode(), epochs, lr,
+                                             ctypes.byref(loss), ctypes.byref(rows)), "mpg_mlp_train_db")
+        return loss.value, rows.value
+
+    def predict(self, X):
+        import numpy as np
+        Xa, Xp = _fp(X)
+        out = np.zeros(Xa.shape[0], dtype=np.float32)
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_mlp_predict(self.ctx.handle, Xp, Xa.shape[0], out.ctypes.data_as(_f)),
+                       "mpg_mlp_predict")
+        return out
+
+    def save(self, path):
+        self.ctx.check(_lib.mpg_mlp_save(self.ctx.handle, path.encode()), "mpg_mlp_save")
+
+    def load(self, path):
+        self.ctx.check(_lib.mpg_mlp_load(self.ctx.handle, path.encode()), "mpg_mlp_load")
 
 
 def empty_like_limbs(m: int, n: int, limbs: int, device="cuda"):

@@ -1,0 +1,162 @@
+"""Run-time model kernels against the float64 oracle, the slab prediction of
+the block time, and the three tuning modes."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_ref
+from paper_1710_01839_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+F, H = 14, 64
+
+
+def _dataset(M, rows=300, seed=0):
+    g = np.random.default_rng(seed)
+    X = []
+    for _ in range(rows):
+        prec = "dd" if g.random() < 0.7 else "qd"
+        m, n, l = (int(x) for x in np.exp(g.uniform(np.log(64), np.log(4096), 3)))
+        cands = M.candidates(prec, m, n, l)
+        algo, tile = cands[g.integers(0, len(cands))]
+        X.append(M.mlp_features(prec, m, n, l, algo, tile))
+    X = np.array(X, dtype=np.float32)
+    y = (X[:, :3].sum(axis=1) * 3 + X[:, 5] * 2 - X[:, 7] + g.normal(0, 0.1, rows)).astype(np.float32)
+    return X, y
+
+
+def _init():
+    P = inputs.mlp_init(F, H)
+    return P, mlp_ref.flatten(P).astype(np.float32)
+
+
+def test_features_host_only(gpu):
+    M, _ = gpu
+    f = M.mlp_features("dd", 4096, 1024, 256, "strassen", {"bm": 64, "bn": 32, "bk": 16, "tm": 4,
+                                                            "tn": 2, "depth": 2})
+    assert np.allclose(f[:3], [1.0, 10 / 12, 8 / 12]) and f[3] == 1 and f[7] == 1
+    assert np.isclose(f[8], 6 / 8) and np.isclose(f[9], 5 / 8) and np.isclose(f[12], 2 / 3)
+
+
+def test_mlp_gradient_matches_oracle(gpu):
+    M, ctx = gpu
+    mlp = M.MLP(ctx)
+    P, flat = _init()
+    mlp.set_params(flat)
+    X, y = _dataset(M)
+    loss, g = mlp.grad(X, y)
+    P64 = {k: v.astype(np.float64) for k, v in P.items()}
+    rloss, rg = mlp_ref.loss_and_grads(P64, X.astype(np.float64), y.astype(np.float64))
+    rflat = mlp_ref.flatten(rg)
+    assert abs(loss - rloss) <= 1e-5 * abs(rloss)
+    # FP32 sums of 300 rows: relative error well below 1e-4 of the largest gradient
+    for k, (a, b) in {"all": (g, rflat)}.items():
+        assert np.max(np.abs(a - b)) <= 1e-4 * np.max(np.abs(b)), k
+
+
+def test_mlp_forward_matches_oracle(gpu):
+    M, ctx = gpu
+    mlp = M.MLP(ctx)
+    P, flat = _init()
+    mlp.set_params(flat)
+    X, _ = _dataset(M, 100, 1)
+    got = mlp.predict(X)
+    want, _ = mlp_ref.forward({k: v.astype(np.float64) for k, v in P.items()}, X.astype(np.float64))
+    assert np.max(np.abs(got - want)) <= 1e-5 * max(1.0, np.max(np.abs(want)))
+
+
+def test_mlp_training_matches_oracle(gpu):
+    """Ten full-batch Adam steps on the GPU follow the float64 reference."""
+    M, ctx = gpu
+    mlp = M.MLP(ctx)
+    P, flat = _init()
+    mlp.set_params(flat)
+    X, y = _dataset(M, 200, 2)
+    losses = mlp.train(X, y, 10, lr=1e-3)
+    P64 = {k: v.astype(np.float64) for k, v in P.items()}
+    Pr, rlosses = mlp_ref.adam_train(P64, X.astype(np.float64), y.astype(np.float64), 10, lr=1e-3)
+    assert np.allclose(losses, rlosses, rtol=1e-4)
+    got = mlp.get_params()
+    want = mlp_ref.flatten(Pr)
+    # Adam's steps are +-lr-sized; FP32 gradients can flip the direction of
+    # near-zero components, so compare against the step size
+    assert np.max(np.abs(got - want)) <= 10 * 1e-3
+
+
+def test_mlp_learns_and_saves(gpu, tmp_path):
+    M, ctx = gpu
+    mlp = M.MLP(ctx)
+    P, flat = _init()
+    mlp.set_params(flat)
+    X, y = _dataset(M, 400, 3)
+    losses = mlp.train(X, y, 400, lr=3e-3)
+    assert losses[-1] < 0.05 * losses[0]
+    path = str(tmp_path / "model.bin")
+    mlp.save(path)
+    before = mlp.predict(X[:20])
+    mlp.set_params(flat)
+    mlp.load(path)
+    assert np.array_equal(mlp.predict(X[:20]), before)
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_slab_prediction_gpu_rule(gpu, variant):
+    """Section 3's prediction in GPU form (slab = one full wave of tiles,
+    scaled by wave counts) predicts the full-size block time."""
+    M, ctx = gpu
+    T = M.Tuner(ctx)
+    v = M.variants(2)[variant]
+    n = 2048
+    real = T.time("dd", n, n, n, "block", v, reps=5)
+    pred, slab = T.predict_block("dd", n, n, n, v, rule=0)
+    print("variant", v, "real", real, "predicted", pred, "slab", slab)
+    assert slab < real
+    assert abs(pred - real) <= 0.25 * real
+
+
+def test_tuner_modes(gpu, tmp_path):
+    """Exhaustive, paper and MLP-pruned tuning on held-out shapes: the MLP
+    (trained on exhaustive timings of other shapes) times a few candidates
+    and stays close to the exhaustive best."""
+    M, ctx = gpu
+    T = M.Tuner(ctx)
+    db = str(tmp_path / "db.jsonl")
+    T.set_db(db)
+    for n in (256, 384, 512, 768, 1024, 1536):
+        T.tune("dd", n, n, n, "exhaustive")
+    for n in (256, 512, 1024):
+        T.tune("qd", n, n, n, "exhaustive")
+    T.set_db(None)
+    mlp = M.MLP(ctx)
+    loss, rows = mlp.train_db(db, 3000, 3e-3)
+    assert rows > 100 and loss < 0.05
+    for prec, n in (("dd", 640), ("dd", 1280), ("qd", 768)):
+        ex = T.tune(prec, n, n, n, "exhaustive")
+        pa = T.tune(prec, n, n, n, "paper")
+        ml = T.tune(prec, n, n, n, "mlp", 3)
+        assert ml["trials"] == 3 and ex["trials"] == len(M.candidates(prec, n, n, n))
+        assert pa["trials"] <= 1 + 1 + 3
+        best = T.time(prec, n, n, n, ex["algo"], ex["tile"], reps=5)
+        got = T.time(prec, n, n, n, ml["algo"], ml["tile"], reps=5)
+        print(prec, n, "exhaustive", ex, "paper", pa, "mlp", ml)
+        assert got <= 1.15 * best
+        assert ml["seconds"] <= 0.5 * ex["seconds"]
+
+
+def test_auto_uses_tuning_table(gpu):
+    """MPG_AUTO follows the table the tuner fills; results equal the explicit
+    choice bit for bit."""
+    M, ctx = gpu
+    T = M.Tuner(ctx)
+    n = 256
+    r = T.tune("dd", n, n, n, "exhaustive")
+    A, B = M.to_device(inputs.dd_uniform(n, n, 1)), M.to_device(inputs.dd_uniform(n, n, 2))
+    C1, C2 = M.empty_like_limbs(n, n, 2), M.empty_like_limbs(n, n, 2)
+    M.mpgemm_dd(ctx, A, B, C1, algo="auto")
+    algo = {1: "simple", 2: "block", 3: "strassen"}[r["algo"]]
+    M.mpgemm_dd(ctx, A, B, C2, algo=algo, tile=r["tile"])
+    torch.cuda.synchronize()
+    assert torch.equal(C1[0], C2[0]) and torch.equal(C1[1], C2[1])
