@@ -3,8 +3,9 @@
 One step = one DD product C := AB of two 4096 x 4096 double-double matrices
 (hi/lo planes, synthetic: hi ~ U[-1,1], lo inside hi's half-ulp), inputs and
 output resident in HBM.  The algorithm (block kernel, or Winograd's Strassen
-of depth 1 or 2 over it) is chosen by timing each once after warm-up, then
-exactly --steps products of the chosen algorithm are timed.
+of depth 1 or 2 over it) is chosen by timing each candidate once, then
+exactly --steps products of the chosen algorithm are timed.  Candidates: every
+block tile variant alone and under Strassen depth 1 and 2.
 
 Printed (one JSON line): DD Gflop/s = 2 n^3 / t (Strassen counted by the
 same conventional 2 n^3), the roofline of the dominant kernel (the grouped
@@ -27,6 +28,11 @@ sys.path.insert(0, ROOT)
 DD_OPS_PER_MADD = 10.0 + 6.0 / 8.0
 # MI355X FP64 VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 FP64_ISSUE_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# HBM bytes per launch of the multiply-add kernel, from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE runs of this exact kernel and launch, each scaled by what
+# the counter reads for a plain 1 GiB device copy (fetch x 2.000, write
+# x 1.000).  Candidates not measured that way report null.
+MEASURED_TRAFFIC = {"strassen2_0": {"read": 4.924e9, "write": 0.822e9}}
 
 
 def parse():
@@ -35,7 +41,9 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=4096)
-    p.add_argument("--algo", default="auto", help="auto | block | strassen1 | strassen2")
+    p.add_argument("--algo", default="auto",
+                   help="auto (choose among all tiles x depth 0..2) | block | strassen1 | strassen2 | "
+                        "a candidate key such as strassen2_1 (depth 2 over tile variant 1)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the oracle sample")
@@ -87,25 +95,38 @@ def main():
     B = M.to_device(inputs.dd_uniform(n, n, 21))
     C = M.empty_like_limbs(n, n, 2)
 
-    cands = {"block": ("block", None), "strassen1": ("strassen", {"depth": 1}),
-             "strassen2": ("strassen", {"depth": 2})}
+    # candidates: every block tile variant, alone and under Winograd's
+    # Strassen of depth 1 and 2 (the depths of the n = 4096 configuration)
+    cands = {}
+    for i, v in enumerate(M.variants(2)):
+        cands[f"block{i}"] = ("block", dict(v))
+        for d in (1, 2):
+            cands[f"strassen{d}_{i}"] = ("strassen", dict(v, depth=d))
 
     def step(key):
         algo, tile = cands[key]
         M.mpgemm_dd(ctx, A, B, C, algo=algo, tile=tile)
 
-    # warm-up (also the algorithm choice when --algo auto)
+    # warm-up, and the choice of algorithm when --algo auto: each candidate
+    # once untimed, then once timed; the fastest is the measured step
     times = {}
-    keys = list(cands) if args.algo == "auto" else [args.algo]
+    if args.algo == "auto":
+        keys = list(cands)
+    elif args.algo in ("block", "strassen1", "strassen2"):
+        keys = ["block0" if args.algo == "block" else f"{args.algo}_0"]
+    else:
+        keys = [args.algo]
     for key in keys:
-        for _ in range(max(1, args.warmup)):
-            step(key)
+        step(key)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         step(key)
         torch.cuda.synchronize()
         times[key] = time.perf_counter() - t0
     key = min(times, key=times.get)
+    for _ in range(args.warmup):
+        step(key)
+    torch.cuda.synchronize()
 
     if args.calibrate_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
@@ -128,7 +149,7 @@ def main():
 
     ms_per_step = elapsed / args.steps * 1e3
     value = 2.0 * n ** 3 * args.steps / elapsed / 1e9
-    depth = cands[key][1]["depth"] if cands[key][1] else 0
+    depth = cands[key][1].get("depth", 0) if cands[key][0] == "strassen" else 0
     madds_per_launch = (7 / 8) ** depth * n ** 3
     launch_ms = gemm_ms / max(gemm_n, 1)
     achieved = madds_per_launch * DD_OPS_PER_MADD / (launch_ms * 1e-3) / 1e12
@@ -147,10 +168,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"double-double square GEMM C=AB, n={n}, hi~U[-1,1], lo in hi's half-ulp",
                    "n": n, "algo": cands[key][0], "strassen_depth": depth,
-                   "tile": M.variants(2)[0], "candidates_ms": {k: round(v * 1e3, 3) for k, v in times.items()}},
+                   "tile": {k: v for k, v in cands[key][1].items() if k in ("bm", "bn", "bk", "tm", "tn")},
+                   "candidate": key,
+                   "candidates_ms": {k: round(v * 1e3, 3) for k, v in sorted(times.items(), key=lambda x: x[1])[:6]}},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_ISSUE_PEAK_TOPS,
                      "unit": "TOP/s (FP64 VALU lane-ops)", "frac": round(achieved / FP64_ISSUE_PEAK_TOPS, 4),
-                     "traffic": None,
+                     "traffic": (MEASURED_TRAFFIC[key]["read"] + MEASURED_TRAFFIC[key]["write"])
+                     if key in MEASURED_TRAFFIC else None,
+                     "traffic_unit": "HBM bytes per launch (read + write)",
+                     # each leaf's A and B read once and its product written once
+                     "algorithmic_bytes": 7 ** depth * 3 * (n >> depth) ** 2 * 16,
                      "kernel": "grouped DD block multiply-add launch",
                      "launch_ms": round(launch_ms, 4), "launches": gemm_n,
                      "ops_per_launch": madds_per_launch * DD_OPS_PER_MADD,

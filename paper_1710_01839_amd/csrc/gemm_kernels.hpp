@@ -84,9 +84,10 @@ hipError_t launch_simple(const GemmBatch& g, hipStream_t s) {
 // so every c_ij sees exactly the operation sequence of the simple kernel
 // (zero padding beyond l changes no accumulator).
 // ---------------------------------------------------------------------
-// LDS of one block-kernel workgroup.
+// LDS of one block-kernel workgroup (16-byte aligned: the k-pair reads are
+// ds_read_b128).
 template <int L, int BM, int BN, int BK>
-struct BlockSmem {
+struct alignas(16) BlockSmem {
   double A[2][L][BM * (BK + 2)];
   double B[2][L][BK * BN];
 };

@@ -14,7 +14,7 @@ import os
 import torch  # loads the HIP runtime the library binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmpgemm.so")
+LIB_PATH = os.environ.get("MPGEMM_LIB") or os.path.join(_HERE, "libmpgemm.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
