@@ -49,3 +49,19 @@ def test_host_only_calls(lib):
     lib.mpgemm_dd.restype = ctypes.c_int
     assert lib.mpgemm_dd(None, 1, 1, 1, None, None, 1, None, None, 1, None, None, 1, 2, None) == -1
     assert lib.mpg_destroy(None) == 0
+
+
+def test_tuner_host_logic(lib):
+    """Candidate space and feature map are host-only (no GPU needed)."""
+    import numpy as np
+    from paper_1710_01839_amd import mpgemm as M
+    nv_dd, nv_qd = lib.mpg_num_variants(2), lib.mpg_num_variants(4)
+    # simple + every tile + every tile under each admissible Strassen depth
+    assert len(M.candidates("dd", 4096, 4096, 4096)) == 1 + nv_dd * 4
+    assert len(M.candidates("qd", 2048, 2048, 2048)) == 1 + nv_qd * 3
+    assert len(M.candidates("dd", 200, 200, 200)) == 1 + nv_dd * 2      # leaves >= 64: depth 1 only
+    assert len(M.candidates("dd", 100, 5000, 5000)) == 1 + nv_dd
+    f = M.mlp_features("qd", 256, 512, 1024, "block", M.variants(4)[0], batch=8)
+    assert f.dtype == np.float32 and f.shape == (M.MLP_FEATURES,)
+    assert np.allclose(f[:3], [8 / 12, 9 / 12, 10 / 12]) and f[4] == 1 and f[6] == 1
+    assert np.isclose(f[13], 0.3)
