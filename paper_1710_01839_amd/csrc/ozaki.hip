@@ -16,6 +16,15 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+// The hardware deals workgroups round-robin over the 8 XCDs; remap the
+// linear id so consecutive logical tiles run on one XCD.
+__device__ __forceinline__ int xcd_remap(int w, int total) {
+  constexpr int X = 8;
+  const int q = total / X, r = total % X;
+  const int xcd = w % X, local = w / X;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
 // ---------------------------------------------------------------------
 // exponent scans
 // ---------------------------------------------------------------------
@@ -336,6 +345,162 @@ __global__ __launch_bounds__(256, 1) void ozaki_mfma_kernel(OzakiGemmArgs a) {
       }
 }
 
+// ---------------------------------------------------------------------
+// INT8 MFMA product, register-resident form (slices <= kOzRegMaxS).
+//
+// Each wavefront owns one 16 x 16 block of C and keeps the INT32 sum of
+// every diagonal g = s + t live in registers (4 per lane and diagonal), so
+// every digit-plane fragment it loads is used by all S pairs it belongs to:
+// per 64-wide K step the wave loads S fragments of A and S of B (16 bytes
+// per lane, straight from the K-contiguous digit planes into registers: no
+// LDS, no barriers) and issues the S^2 (or S(S+1)/2) MFMAs.
+// A workgroup is 4 independent waves on a 32 x 32 tile (the two waves of a
+// row share A fragments through L1, the two of a column share B).  The
+// diagonal sums stay exact INT32 over `kchunk` K steps (kchunk S 64 127^2 <
+// 2^31); at the end of each chunk they are scaled and added to the
+// double-double accumulators, smallest weights first.
+// ---------------------------------------------------------------------
+constexpr int kOzRegMaxS = 24;
+
+template <int S, bool TRI>
+__global__ __launch_bounds__(256, 1) void ozaki_reg_kernel(OzakiGemmArgs a, int tiles_m,
+                                                           int tiles_n, int kchunk) {
+  constexpr int G = 2 * S - 1;  // diagonals g = 2 .. 2S (0-based index g - 2)
+  // double-double accumulators of each lane, parked in LDS during the K
+  // loop (they are touched only when diagonal sums are flushed)
+  __shared__ double dd_hi[4][256], dd_lo[4][256];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  int tm, tn;
+  {
+    // XCD-aware grouped order: consecutive logical tiles run on one XCD
+    // and walk 8 tile-rows column by column, so the waves resident on an
+    // XCD share A and B digit panels in its L2
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    constexpr int GR = 8;
+    const int per_group = GR * tiles_n;
+    const int group = w / per_group;
+    const int first = group * GR;
+    const int gsize = min(tiles_m - first, GR);
+    const int in = w - group * per_group;
+    tm = first + in % gsize;
+    tn = in / gsize;
+  }
+  const int64_t r0 = (int64_t)tm * 32 + 16 * (wave / 2);
+  const int64_t c0 = (int64_t)tn * 32 + 16 * (wave % 2);
+  const int64_t col = c0 + lane % 16;
+
+  // lane -> operand row / column and 16-byte chunk of the K step
+  const uint32_t voffA = (uint32_t)((r0 + lane % 16) * a.l_pad + 16 * (lane / 16));
+  const uint32_t voffB = (uint32_t)((c0 + lane % 16) * a.l_pad + 16 * (lane / 16));
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i) dd_hi[i][threadIdx.x] = dd_lo[i][threadIdx.x] = 0.0;
+
+  v4i acc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g] = v4i{0, 0, 0, 0};
+
+  v4i fa[S], fb[S];
+  const int numK = (int)(a.l_pad / 64);
+  auto ldA = [&](int s, int kt) {
+    const int8_t* base = a.A + s * a.planeA + (int64_t)kt * 64;  // uniform
+    return *reinterpret_cast<const v4i*>(base + voffA);
+  };
+  auto ldB = [&](int t, int kt) {
+    const int8_t* base = a.B + t * a.planeB + (int64_t)kt * 64;
+    return *reinterpret_cast<const v4i*>(base + voffB);
+  };
+  // exact diagonal sums -> double-double, smallest weights first (adding
+  // an exact zero changes nothing, so no branch)
+  auto flush = [&]() {
+    int erow[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + 4 * (lane / 16) + i;
+      erow[i] = r < a.m ? a.e[r] : 0;
+    }
+    const int fcol = col < a.n ? a.f[col] : 0;
+    double hi[4], lo[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      hi[i] = dd_hi[i][threadIdx.x];
+      lo[i] = dd_lo[i][threadIdx.x];
+    }
+#pragma unroll
+    for (int g = G - 1; g >= 0; --g) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double x = ldexp((double)acc[g][i], erow[i] + fcol - 7 * (g + 2));
+        double sum, err;
+        two_sum(hi[i], x, sum, err);
+        hi[i] = sum;
+        lo[i] = lo[i] + err;
+      }
+      acc[g] = v4i{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dd_hi[i][threadIdx.x] = hi[i];
+      dd_lo[i][threadIdx.x] = lo[i];
+    }
+  };
+  auto keep = [](int s, int t) { return !TRI || s + t <= S - 1; };  // 1-based s + t <= S + 1
+
+  for (int kc = 0; kc < numK; kc += kchunk) {
+    const int kend = min(numK, kc + kchunk);
+    for (int kt = kc; kt < kend; ++kt) {
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        fa[q] = ldA(q, kt);
+        fb[q] = ldB(q, kt);
+      }
+      // s outer, t inner: consecutive MFMAs update different diagonals, so
+      // no MFMA waits for the one before it
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+          if (keep(s2, t))
+            acc[s2 + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s2], fb[t], acc[s2 + t], 0, 0, 0);
+    }
+    flush();
+  }
+
+  if (col < a.n) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + 4 * (lane / 16) + i;
+      if (r < a.m) {
+        double h = dd_hi[i][threadIdx.x], l = dd_lo[i][threadIdx.x];
+        dd_renorm(h, l);
+        a.C_hi[r * a.ldc + col] = h;
+        a.C_lo[r * a.ldc + col] = l;
+      }
+    }
+  }
+}
+
+using OzRegFn = void (*)(OzakiGemmArgs, int, int, int);
+
+template <int S>
+struct OzRegTable {
+  static void fill(const void** all, const void** tri) {
+    all[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, false>);
+    tri[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, true>);
+    OzRegTable<S - 1>::fill(all, tri);
+  }
+};
+template <>
+struct OzRegTable<0> {
+  static void fill(const void**, const void**) {}
+};
+
+struct OzRegKernels {
+  const void* all[kOzRegMaxS + 1] = {};
+  const void* tri[kOzRegMaxS + 1] = {};
+  OzRegKernels() { OzRegTable<kOzRegMaxS>::fill(all, tri); }
+};
+
 }  // namespace
 
 int ozaki_max_slices() { return kMaxSlices; }
@@ -389,6 +554,20 @@ hipError_t launch_ozaki_split_cols(const double* X, int64_t K, int64_t C, int64_
 }
 
 hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
+  if (a.S >= 1 && a.S <= kOzRegMaxS) {
+    // register-resident kernel on 32 x 32 tiles (digit planes are padded to
+    // multiples of 64 rows, so every tile reads inside the planes)
+    static const OzRegKernels table;
+    const int64_t tiles_m = (a.m + 31) / 32, tiles_n = (a.n + 31) / 32;
+    // diagonal sums: at most S pairs of 64 k per K step, each |d d'| <= 127^2
+    const double per_step = (double)a.S * 64.0 * 127.0 * 127.0;
+    const int kchunk = std::max(1, (int)(2147483647.0 / per_step));
+    OzakiGemmArgs args = a;
+    int tm = (int)tiles_m, tn = (int)tiles_n;
+    void* kargs[] = {(void*)&args, (void*)&tm, (void*)&tn, (void*)&kchunk};
+    return hipLaunchKernel(a.triangle ? table.tri[a.S] : table.all[a.S],
+                           dim3((unsigned)(tiles_m * tiles_n)), dim3(256), kargs, 0, s);
+  }
   const int64_t tiles = ((a.m + kOzTile - 1) / kOzTile) * ((a.n + kOzTile - 1) / kOzTile);
   if (tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(ozaki_mfma_kernel<4>, dim3((unsigned)tiles), dim3(256), 0, s, a);
