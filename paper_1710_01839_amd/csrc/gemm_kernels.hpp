@@ -208,14 +208,11 @@ __device__ __forceinline__ void block_tile(BlockSmem<Arith::L, BM, BN, BK>& sm, 
           double a[L];
 #pragma unroll
           for (int q = 0; q < L; ++q) a[q] = kk ? a2[i][q].y : a2[i][q].x;
-#pragma unroll
-          for (int j = 0; j < TN; ++j) Arith::madd(acc[i][j], a, b[j]);
+          Arith::template madd_row<TN>(acc[i], a, b);
         }
         if (Arith::kRenorm && ((kp + kk) % Arith::kRenorm) == Arith::kRenorm - 1) {
 #pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) Arith::renorm(acc[i][j]);
+          for (int i = 0; i < TM; ++i) Arith::template renorm_row<TN>(acc[i]);
         }
       }
     }

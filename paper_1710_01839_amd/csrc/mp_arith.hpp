@@ -194,7 +194,64 @@ struct DDArith {
                                               const double (&b)[2]) {
     dd_madd(c[0], c[1], a[0], a[1], b[0], b[1]);
   }
+  // N independent steps c[j] += a * b[j], written stage by stage across j so
+  // that consecutive instructions belong to different accumulators (each
+  // accumulator sees exactly the operations of dd_madd, in the same order).
+  // One wavefront then has N-way instruction-level parallelism to cover the
+  // FP64 pipeline latency instead of one dependent chain.
+  template <int N>
+  __device__ static __forceinline__ void madd_row(double (*c)[2], const double (&a)[2],
+                                                  const double (*b)[2]) {
+    if constexpr (N > 4) {  // groups of four keep the temporaries in registers
+      madd_row<4>(c, a, b);
+      madd_row<N - 4>(c + 4, a, b + 4);
+      return;
+    }
+    double p[N], s[N], t[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) p[j] = a[0] * b[j][0];
+#pragma unroll
+    for (int j = 0; j < N; ++j) c[j][1] = __builtin_fma(a[0], b[j][1], c[j][1]);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s[j] = c[j][0] + p[j];
+#pragma unroll
+    for (int j = 0; j < N; ++j) c[j][1] = __builtin_fma(a[1], b[j][0], c[j][1]);
+#pragma unroll
+    for (int j = 0; j < N; ++j) t[j] = s[j] - c[j][0];                        // bv
+#pragma unroll
+    for (int j = 0; j < N; ++j) p[j] = __builtin_fma(a[0], b[j][0], -t[j]);   // db
+#pragma unroll
+    for (int j = 0; j < N; ++j) t[j] = s[j] - t[j];                           // av
+#pragma unroll
+    for (int j = 0; j < N; ++j) t[j] = c[j][0] - t[j];                        // da
+#pragma unroll
+    for (int j = 0; j < N; ++j) t[j] = t[j] + p[j];                           // da + db
+#pragma unroll
+    for (int j = 0; j < N; ++j) c[j][1] = c[j][1] + t[j];
+#pragma unroll
+    for (int j = 0; j < N; ++j) c[j][0] = s[j];
+  }
   __device__ static __forceinline__ void renorm(double (&c)[2]) { dd_renorm(c[0], c[1]); }
+  // exact TwoSum of N accumulators, interleaved like madd_row
+  template <int N>
+  __device__ static __forceinline__ void renorm_row(double (*c)[2]) {
+    double s[N], bv[N], t[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) s[j] = c[j][0] + c[j][1];
+#pragma unroll
+    for (int j = 0; j < N; ++j) bv[j] = s[j] - c[j][0];
+#pragma unroll
+    for (int j = 0; j < N; ++j) t[j] = s[j] - bv[j];
+#pragma unroll
+    for (int j = 0; j < N; ++j) t[j] = c[j][0] - t[j];
+#pragma unroll
+    for (int j = 0; j < N; ++j) bv[j] = c[j][1] - bv[j];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      c[j][0] = s[j];
+      c[j][1] = t[j] + bv[j];
+    }
+  }
   __device__ static __forceinline__ void finish(double (&c)[2]) { dd_renorm(c[0], c[1]); }
   __device__ static __forceinline__ void add(const double (&a)[2], const double (&b)[2],
                                              double (&r)[2]) {
@@ -209,7 +266,15 @@ struct QDArith {
                                               const double (&b)[4]) {
     qd_madd(c, a, b);
   }
+  template <int N>
+  __device__ static __forceinline__ void madd_row(double (*c)[4], const double (&a)[4],
+                                                  const double (*b)[4]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) qd_madd(c[j], a, b[j]);
+  }
   __device__ static __forceinline__ void renorm(double (&)[4]) {}
+  template <int N>
+  __device__ static __forceinline__ void renorm_row(double (*)[4]) {}
   __device__ static __forceinline__ void finish(double (&c)[4]) { qd_finish(c); }
   __device__ static __forceinline__ void add(const double (&a)[4], const double (&b)[4],
                                              double (&r)[4]) {
