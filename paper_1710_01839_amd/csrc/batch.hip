@@ -47,7 +47,7 @@ const Entry kEntries[] = {
     MPG_ENTRY(64, 64, 16, 4, 4, 2),  MPG_ENTRY(32, 32, 16, 2, 2, 2),
     MPG_ENTRY(128, 64, 8, 8, 4, 1),  MPG_ENTRY(64, 128, 8, 4, 8, 1),
     MPG_ENTRY(128, 128, 8, 8, 8, 1), MPG_ENTRY(64, 64, 8, 4, 4, 2),
-    MPG_ENTRY(32, 64, 16, 2, 4, 2),
+    MPG_ENTRY(32, 64, 16, 2, 4, 2),  MPG_ENTRY(64, 64, 8, 2, 4, 2),
 };
 constexpr int kN = sizeof(kEntries) / sizeof(kEntries[0]);
 

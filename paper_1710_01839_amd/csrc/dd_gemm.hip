@@ -1,5 +1,6 @@
 // Double-double GEMM kernel instances (simple, block variants, Winograd
 // operand formation / assembly).
+#include "gemm_direct.hpp"
 #include "gemm_kernels.hpp"
 
 namespace mpg {
@@ -18,6 +19,7 @@ const VariantEntry kVariants[] = {
     variant_entry<DDArith, 128, 128, 8, 8, 8, 1>(),
     variant_entry<DDArith, 64, 64, 8, 4, 4>(),
     variant_entry<DDArith, 32, 64, 16, 2, 4>(),
+    kern::direct_entry<DDArith, 2, 4>(),  // 64x64x8, 2x4, 512 threads, load unit to LDS
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

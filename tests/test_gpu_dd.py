@@ -52,6 +52,57 @@ def test_block_variants_ragged(gpu, dist):
         assert np.array_equal(C[0], ref[0]) and np.array_equal(C[1], ref[1]), v
 
 
+def _direct_variants(M):
+    """The variant whose operand tiles the load unit moves to LDS (64x64x8,
+    2x4 per thread, 512 threads)."""
+    vs = [v for v in M.variants(2) if (v["bm"], v["bn"], v["bk"], v["tm"], v["tn"]) == (64, 64, 8, 2, 4)]
+    assert len(vs) == 1
+    return vs
+
+
+def _padded_view(X, extra, fill):
+    """Device copies of the limbs inside wider buffers (extra columns = fill)."""
+    out = []
+    for x in X:
+        buf = torch.full((x.shape[0], x.shape[1] + extra), fill, dtype=torch.float64, device="cuda")
+        buf[:, :x.shape[1]] = torch.from_numpy(x).cuda()
+        out.append(buf[:, :x.shape[1]])
+    return tuple(out)
+
+
+@pytest.mark.parametrize("shape", [(203, 142, 158), (64, 64, 8), (1, 2, 2), (130, 66, 520), (65, 64, 10)])
+def test_direct_variants_ragged(gpu, shape):
+    """Load-unit-to-LDS variants on shapes meeting their alignment (n, l
+    even) with tails in every dimension, also on operands that are views
+    into wider buffers whose extra columns hold NaN: out-of-range chunks must
+    be zero-filled, never read.  Bit-identical to the simple kernel."""
+    M, ctx = gpu
+    m, n, l = shape
+    A, B = inputs.dd_uniform(m, l, 12), inputs.dd_uniform(l, n, 13)
+    ref = run_dd(M, ctx, A, B, "simple")
+    for v in _direct_variants(M):
+        C = run_dd(M, ctx, A, B, "block", v)
+        assert np.array_equal(C[0], ref[0]) and np.array_equal(C[1], ref[1]), v
+        Ad, Bd = _padded_view(A, 6, float("nan")), _padded_view(B, 4, float("nan"))
+        Cd = M.empty_like_limbs(m, n, 2)
+        M.mpgemm_dd(ctx, Ad, Bd, Cd, algo="block", tile=v)
+        torch.cuda.synchronize()
+        C = M.to_host(Cd)
+        assert np.array_equal(C[0], ref[0]) and np.array_equal(C[1], ref[1]), (v, "padded")
+
+
+def test_direct_variants_fallback(gpu):
+    """Odd l or n (or odd leading dimensions) take the register-staged
+    kernel of the same tile: results stay bit-identical."""
+    M, ctx = gpu
+    for (m, n, l) in ((70, 63, 40), (70, 64, 41)):
+        A, B = inputs.dd_uniform(m, l, 14), inputs.dd_uniform(l, n, 15)
+        ref = run_dd(M, ctx, A, B, "simple")
+        for v in _direct_variants(M):
+            C = run_dd(M, ctx, A, B, "block", v)
+            assert np.array_equal(C[0], ref[0]) and np.array_equal(C[1], ref[1]), (v, m, n, l)
+
+
 def test_integer_inputs_bit_exact(gpu):
     """Integer inputs |x| <= 2^30: every step is exact, so the result is the
     canonical DD of the integer product, bit for bit."""
