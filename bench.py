@@ -32,7 +32,7 @@ FP64_ISSUE_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # and WRITE_SIZE runs of this exact kernel and launch, each scaled by what
 # the counter reads for a plain 1 GiB device copy (fetch x 2.000, write
 # x 1.000).  Candidates not measured that way report null.
-MEASURED_TRAFFIC = {"strassen2_0": {"read": 4.924e9, "write": 0.822e9}}
+MEASURED_TRAFFIC = {"strassen2_7": {"read": 4.929e9, "write": 0.822e9}}
 
 
 def parse():
@@ -67,9 +67,9 @@ def cpu_baseline(n: int, target_s: float):
         t0 = time.perf_counter()
         cref.gemm_simple(As, B, threads=threads)
         dt = time.perf_counter() - t0
-        if dt >= 0.3 * target_s or rows >= n:
+        if dt >= 0.6 * target_s or rows >= n:
             break
-        rows = min(n, int(rows * max(2.0, 0.6 * target_s / max(dt, 1e-3))))
+        rows = min(n, int(rows * max(2.0, target_s / max(dt, 1e-3))))
     return {"value": 2.0 * rows * n * n / dt / 1e9, "unit": "DD Gflop/s", "cores": threads,
             "kind": "oracle",
             "sample": f"rows 0..{rows - 1} of A ({rows}x{n}) times the full {n}x{n} B, DD simple "
