@@ -33,66 +33,136 @@ __global__ __launch_bounds__(256) void fill_int_kernel(int* p, int64_t n, int v)
     p[i] = v;
 }
 
-// e_i = max over the row of frexp's exponent (max |x| < 2^e_i); rows of X
-// (R x K, leading dimension ld) when by_col == 0, columns when by_col == 1.
-// Each thread folds a strided set of elements, then one atomic max per
-// thread (max is order independent: deterministic).
-__global__ __launch_bounds__(256) void exp_scan_kernel(const double* X, int64_t R, int64_t K,
-                                                       int64_t ld, int by_col, int* e) {
-  if (!by_col) {
-    // one workgroup per row
-    const int64_t i = blockIdx.x;
-    if (i >= R) return;
-    int best = INT_MIN;
-    for (int64_t k = threadIdx.x; k < K; k += 256) {
-      const double x = X[i * ld + k];
-      if (x != 0.0) best = max(best, ilogb(x) + 1);
-    }
-    if (best != INT_MIN) atomicMax(&e[i], best);
+// Exponents of the leading bit (ilogb) and of the lowest set bit of a
+// finite x != 0, read from its bit pattern (subnormals included).
+__device__ __forceinline__ void bit_range(double x, int& top, int& low) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x) & 0x7FFFFFFFFFFFFFFFull;
+  const int be = (int)(b >> 52);
+  const unsigned long long mant = b & 0x000FFFFFFFFFFFFFull;
+  if (be != 0) {
+    top = be - 1023;
+    low = top - 52 + __builtin_ctzll(mant | 0x0010000000000000ull);
   } else {
-    // threads over columns, rows split over gridDim.y
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= K) return;
-    const int64_t chunk = (R + gridDim.y - 1) / gridDim.y;
-    const int64_t r0 = blockIdx.y * chunk, r1 = min(R, r0 + chunk);
-    int best = INT_MIN;
-    for (int64_t r = r0; r < r1; ++r) {
-      const double x = X[r * ld + j];
-      if (x != 0.0) best = max(best, ilogb(x) + 1);
+    top = 63 - __builtin_clzll(mant) - 1074;
+    low = __builtin_ctzll(mant) - 1074;
+  }
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Digits of 7 bits that hold every element of a line exactly once it is
+// scaled by 2^-e: ceil((e - lowest set bit) / 7).
+__device__ __forceinline__ int line_digits(int e, int low) {
+  const int d = e - low;
+  return d > 0 ? (d + 6) / 7 : 0;
+}
+
+// Rows of X (R x K): one workgroup per row writes e[r] = 1 + max ilogb over
+// the row (max |x| < 2^e; 0 for an all-zero row) and, when `need` is given,
+// raises *need to the row's digit count.  One pass over X.
+__global__ __launch_bounds__(256) void row_scan_kernel(const double* X, int64_t K, int64_t ld, int* e,
+                                                       int* need) {
+  __shared__ int s_top[4], s_low[4];
+  const int64_t r = blockIdx.x;
+  const double* row = X + r * ld;
+  int top = INT_MIN, low = INT_MAX;
+  for (int64_t k = threadIdx.x; k < K; k += 256) {
+    const double x = row[k];
+    if (x != 0.0) {
+      int t, lo;
+      bit_range(x, t, lo);
+      top = max(top, t);
+      low = min(low, lo);
     }
-    if (best != INT_MIN) atomicMax(&e[j], best);
+  }
+  top = wave_max_int(top);
+  low = wave_min_int(low);
+  if ((threadIdx.x & 63) == 0) {
+    s_top[threadIdx.x >> 6] = top;
+    s_low[threadIdx.x >> 6] = low;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      top = max(top, s_top[w]);
+      low = min(low, s_low[w]);
+    }
+    const int er = top == INT_MIN ? 0 : top + 1;
+    e[r] = er;
+    if (need && top != INT_MIN) {
+      const int d = line_digits(er, low);
+      if (d > 0) atomicMax(need, d);
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void exp_finish_kernel(int* e, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n && e[i] == INT_MIN) e[i] = 0;
-}
-
-// Digits needed to hold x 2^-e exactly: ceil((e - low) / 7), low the
-// exponent of x's lowest set bit.
-__device__ __forceinline__ int digits_needed(double x, int e) {
-  if (x == 0.0) return 0;
-  const int top = ilogb(x);                            // x = 1.f * 2^top
-  const unsigned long long bits = __double_as_longlong(x);
-  const unsigned long long mant = (bits & 0x000FFFFFFFFFFFFFull) | 0x0010000000000000ull;
-  const int low = top - 52 + __builtin_ctzll(mant);
-  const int need = e - low;
-  return need <= 0 ? 0 : (need + 6) / 7;
-}
-
-__global__ __launch_bounds__(256) void need_scan_kernel(const double* X, int64_t R, int64_t K,
-                                                        int64_t ld, int by_col, const int* e,
-                                                        int* out) {
-  int best = 0;
-  const int64_t total = R * K;
-  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * 256) {
-    const int64_t r = idx / K, k = idx % K;
-    const double x = X[r * ld + k];
-    best = max(best, digits_needed(x, by_col ? e[k] : e[r]));
+// Columns of X (R x K): a workgroup covers 64 columns (each row's 64
+// doubles are one coalesced read) and 64 rows, 4 threads per column; the
+// per-workgroup maxima / minima go to top[c] / low[c] (initialised to
+// INT_MIN / INT_MAX) with one atomic each.
+constexpr int kColScanRows = 64;
+__global__ __launch_bounds__(256) void col_scan_kernel(const double* X, int64_t R, int64_t K,
+                                                       int64_t ld, int* top, int* low) {
+  __shared__ int s_t[4][64], s_l[4][64];
+  const int tc = threadIdx.x & 63, tg = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + tc;
+  const int64_t r0 = (int64_t)blockIdx.y * kColScanRows;
+  int t = INT_MIN, lo = INT_MAX;
+  if (c < K) {
+#pragma unroll 4
+    for (int i = tg; i < kColScanRows; i += 4) {
+      const int64_t r = r0 + i;
+      if (r < R) {
+        const double x = X[r * ld + c];
+        if (x != 0.0) {
+          int a, b;
+          bit_range(x, a, b);
+          t = max(t, a);
+          lo = min(lo, b);
+        }
+      }
+    }
   }
-  atomicMax(out, best);
+  s_t[tg][tc] = t;
+  s_l[tg][tc] = lo;
+  __syncthreads();
+  if (tg == 0 && c < K) {
+#pragma unroll
+    for (int g = 1; g < 4; ++g) {
+      t = max(t, s_t[g][tc]);
+      lo = min(lo, s_l[g][tc]);
+    }
+    if (t != INT_MIN) {
+      atomicMax(&top[c], t);
+      if (low) atomicMin(&low[c], lo);
+    }
+  }
+}
+
+// top[c] -> e[c] = top + 1 in place (0 for an all-zero column); raises
+// *need (when given) to the columns' digit count, one atomic per wave.
+__global__ __launch_bounds__(256) void col_finish_kernel(int* top_e, const int* low, int64_t K,
+                                                         int* need) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int d = 0;
+  if (c < K) {
+    const int t = top_e[c];
+    const int er = t == INT_MIN ? 0 : t + 1;
+    top_e[c] = er;
+    if (need && t != INT_MIN) d = line_digits(er, low[c]);
+  }
+  d = wave_max_int(d);
+  if (need && (threadIdx.x & 63) == 0 && d > 0) atomicMax(need, d);
 }
 
 // ---------------------------------------------------------------------
@@ -346,19 +416,19 @@ __global__ __launch_bounds__(256, 1) void ozaki_mfma_kernel(OzakiGemmArgs a) {
 }
 
 // ---------------------------------------------------------------------
-// INT8 MFMA product, register-resident form (slices <= kOzRegMaxS).
+// INT8 MFMA product, register-resident form (slices <= kOzRegMaxS; used
+// where the LDS-staged form below does not fit).
 //
-// Each wavefront owns one 16 x 16 block of C and keeps the INT32 sum of
-// every diagonal g = s + t live in registers (4 per lane and diagonal), so
-// every digit-plane fragment it loads is used by all S pairs it belongs to:
-// per 64-wide K step the wave loads S fragments of A and S of B (16 bytes
-// per lane, straight from the K-contiguous digit planes into registers: no
-// LDS, no barriers) and issues the S^2 (or S(S+1)/2) MFMAs.
-// A workgroup is 4 independent waves on a 32 x 32 tile (the two waves of a
-// row share A fragments through L1, the two of a column share B).  The
-// diagonal sums stay exact INT32 over `kchunk` K steps (kchunk S 64 127^2 <
-// 2^31); at the end of each chunk they are scaled and added to the
-// double-double accumulators, smallest weights first.
+// Each wavefront owns WM x WN blocks of 16 x 16 outputs and keeps the INT32
+// sum of every diagonal g = s + t live in registers (4 per lane, diagonal
+// and block), so every digit-plane fragment it loads is used by all pairs
+// it belongs to: per 64-wide K step the wave loads S WM fragments of A and
+// S WN of B (16 bytes per lane, straight from the K-contiguous digit planes
+// into registers: no LDS, no barriers) and issues the MFMAs.  A workgroup is
+// 2 x 2 independent waves.  The diagonal sums stay exact INT32 over `kchunk`
+// K steps (kchunk S 64 127^2 < 2^31); at the end of each chunk they are
+// scaled and added to the double-double accumulators, smallest weights
+// first.
 // ---------------------------------------------------------------------
 constexpr int kOzRegMaxS = 24;
 
@@ -576,6 +646,196 @@ __global__ __launch_bounds__(256, 1) void ozaki_reg_kernel(OzakiGemmArgs a, int 
     }
 }
 
+// ---------------------------------------------------------------------
+// INT8 MFMA product, LDS-staged form (slices <= kOzLdsMaxS).
+//
+// The register-resident form moves every fragment from L2 once per wave,
+// and the L2 -> CU path (about 15 bytes per clock and CU) then bounds it.
+// Here the load unit moves the workgroup's digit blocks of one K step
+// straight into LDS (global_load_lds, 16 bytes per lane, no registers),
+// double-buffered, and the four wavefronts read their fragments from LDS,
+// so each block crosses from L2 once per workgroup.  A block is 16 rows (or
+// columns) x 64 k of one slice, stored in MFMA lane order: lane l's 16 bytes
+// (row l % 16, k chunk l / 16) at byte 16 l, so both the load and the
+// fragment read are one contiguous 1 KiB per wavefront.
+// Workgroup tile BM x BN, 2 x 2 waves of (BM / 32) x (BN / 32) blocks; the
+// double-double accumulators stay in registers.
+// ---------------------------------------------------------------------
+constexpr int kOzLdsMaxS = 18;
+
+template <int S>
+struct OzLdsShape {
+  static constexpr int BM = S <= 12 ? 64 : 32;
+  static constexpr int BN = S <= 9 ? 64 : 32;
+  static constexpr int WM = BM / 32, WN = BN / 32;     // 16 x 16 blocks per wave
+  static constexpr int NBA = BM / 16, NBB = BN / 16;   // blocks per slice and operand
+  static constexpr int BLOCKS = S * (NBA + NBB);       // 1 KiB blocks per K step
+};
+
+using lds_ptr = __attribute__((address_space(3))) void*;
+
+// Moves step `kn`'s digit blocks of the workgroup tile into `dst`: block
+// `blk` (A: slice blk / NBA, rows 16 (blk % NBA) ..; then B likewise) is one
+// global_load_lds per wavefront, wavefronts taking blocks round-robin.
+template <int S>
+__device__ __forceinline__ void oz_lds_issue(int8_t* __restrict__ dst, const OzakiGemmArgs& a,
+                                             int64_t m0, int64_t n0, int kn, uint32_t lane_off,
+                                             int wave) {
+  using Sh = OzLdsShape<S>;
+  constexpr int NBA = Sh::NBA, NBB = Sh::NBB, NBLK = Sh::BLOCKS;
+#pragma unroll
+  for (int i = 0; i < (NBLK + 3) / 4; ++i) {
+    const int blk = wave + 4 * i;
+    if (blk < NBLK) {
+      const int8_t* src;
+      if (blk < S * NBA) {
+        const int s = blk / NBA, b = blk % NBA;
+        src = a.A + s * a.planeA + (m0 + 16 * b) * a.l_pad + (int64_t)kn * 64;
+      } else {
+        const int t = (blk - S * NBA) / NBB, b = (blk - S * NBA) % NBB;
+        src = a.B + t * a.planeB + (n0 + 16 * b) * a.l_pad + (int64_t)kn * 64;
+      }
+      __builtin_amdgcn_global_load_lds(src + lane_off, (lds_ptr)(dst + blk * 1024), 16, 0, 0);
+    }
+  }
+}
+
+// One K step: start moving step `kn`'s blocks into `nxt` (when `more`),
+// then the MFMAs on the fragments in `cur`.  The two buffers are distinct
+// restrict pointers, so the compiler knows the fragment reads need not wait
+// for the loads into the other buffer.
+template <int S, bool TRI>
+__device__ __forceinline__ void oz_lds_step(int8_t* __restrict__ nxt, const int8_t* __restrict__ cur,
+                                            const OzakiGemmArgs& a, int64_t m0, int64_t n0, int kn,
+                                            bool more, uint32_t lane_off, int lane, int wave,
+                                            v4i (&acc)[2 * S - 1][OzLdsShape<S>::WM][OzLdsShape<S>::WN]) {
+  using Sh = OzLdsShape<S>;
+  constexpr int WM = Sh::WM, WN = Sh::WN, NBA = Sh::NBA, NBB = Sh::NBB;
+  if (more) oz_lds_issue<S>(nxt, a, m0, n0, kn, lane_off, wave);
+  const int wr = wave / 2, wc = wave % 2;
+  v4i fb[S][WN];
+#pragma unroll
+  for (int t = 0; t < S; ++t)
+#pragma unroll
+    for (int bj = 0; bj < WN; ++bj)
+      fb[t][bj] = *reinterpret_cast<const v4i*>(cur + (S * NBA + t * NBB + wc * WN + bj) * 1024 + 16 * lane);
+  // A fragments one slice ahead of the MFMAs that use them
+  v4i fa[2][WM];
+  auto read_a = [&](int s2, v4i (&f)[WM]) {
+#pragma unroll
+    for (int bi = 0; bi < WM; ++bi)
+      f[bi] = *reinterpret_cast<const v4i*>(cur + (s2 * NBA + wr * WM + bi) * 1024 + 16 * lane);
+  };
+  read_a(0, fa[0]);
+#pragma unroll
+  for (int s2 = 0; s2 < S; ++s2) {
+    if (s2 + 1 < S) read_a(s2 + 1, fa[(s2 + 1) & 1]);
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      if (!TRI || s2 + t <= S - 1)
+#pragma unroll
+        for (int bi = 0; bi < WM; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < WN; ++bj)
+            acc[s2 + t][bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s2 & 1][bi], fb[t][bj],
+                                                                        acc[s2 + t][bi][bj], 0, 0, 0);
+    // keeps the reads of later slices from being hoisted (registers)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int S, bool TRI>
+__global__ __launch_bounds__(256, 1) void ozaki_lds_kernel(OzakiGemmArgs a, int tiles_m,
+                                                           int tiles_n, int kchunk) {
+  using Sh = OzLdsShape<S>;
+  constexpr int G = 2 * S - 1;
+  constexpr int BM = Sh::BM, BN = Sh::BN, WM = Sh::WM, WN = Sh::WN, NBLK = Sh::BLOCKS;
+  __shared__ __attribute__((aligned(16))) int8_t lds[2 * NBLK * 1024];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  int tm, tn;
+  {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    constexpr int GR = 8;
+    const int per_group = GR * tiles_n;
+    const int group = w / per_group;
+    const int first = group * GR;
+    const int gsize = min(tiles_m - first, GR);
+    const int in = w - group * per_group;
+    tm = first + in % gsize;
+    tn = in / gsize;
+  }
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t r0 = m0 + 16 * WM * (wave / 2), c0 = n0 + 16 * WN * (wave % 2);
+  // this lane's row / column inside a block and its 16-byte k chunk
+  const uint32_t lane_off = (uint32_t)((lane % 16) * a.l_pad + 16 * (lane / 16));
+
+  v4i acc[G][WM][WN];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int bi = 0; bi < WM; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < WN; ++bj) acc[g][bi][bj] = v4i{0, 0, 0, 0};
+
+  // exact diagonal sums -> double-double, smallest weights first.  The
+  // double-double accumulators live in C itself between K chunks (each
+  // lane owns its outputs), so they take no registers during the MFMAs.
+  auto flush = [&](bool first, bool last) {
+#pragma unroll
+    for (int bi = 0; bi < WM; ++bi) {
+#pragma unroll
+      for (int bj = 0; bj < WN; ++bj) {
+        const int64_t col = c0 + 16 * bj + lane % 16;
+        const int fcol = col < a.n ? a.f[col] : 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t r = r0 + 16 * bi + 4 * (lane / 16) + i;
+          const bool inside = r < a.m && col < a.n;
+          const int erow = r < a.m ? a.e[r] : 0;
+          double hi = 0.0, lo = 0.0;
+          if (!first && inside) {
+            hi = a.C_hi[r * a.ldc + col];
+            lo = a.C_lo[r * a.ldc + col];
+          }
+#pragma unroll
+          for (int g = G - 1; g >= 0; --g) {
+            const double x = ldexp((double)acc[g][bi][bj][i], erow + fcol - 7 * (g + 2));
+            double sum, err;
+            two_sum(hi, x, sum, err);
+            hi = sum;
+            lo = lo + err;
+          }
+          if (last) dd_renorm(hi, lo);
+          if (inside) {
+            a.C_hi[r * a.ldc + col] = hi;
+            a.C_lo[r * a.ldc + col] = lo;
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g][bi][bj] = v4i{0, 0, 0, 0};
+      }
+    }
+  };
+
+  const int numK = (int)(a.l_pad / 64);
+  // step 0's blocks into buffer 0 (the issue half of a step, no MFMAs)
+  if (numK > 0) oz_lds_issue<S>(lds, a, m0, n0, 0, lane_off, wave);
+  for (int kc = 0; kc < numK; kc += kchunk) {
+    const int kend = min(numK, kc + kchunk);
+    for (int kt = kc; kt < kend; ++kt) {
+      int8_t* cur = lds + (kt & 1) * NBLK * 1024;
+      int8_t* nxt = lds + ((kt & 1) ^ 1) * NBLK * 1024;
+      // this thread's loads into `cur` are done; after the barrier
+      // everyone's are, and nobody reads `nxt` any more
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      __syncthreads();
+      oz_lds_step<S, TRI>(nxt, cur, a, m0, n0, kt + 1, kt + 1 < numK, lane_off, lane, wave, acc);
+    }
+    flush(kc == 0, kend == numK);
+  }
+  if (numK == 0) flush(true, true);  // empty K: C := 0
+}
+
 using OzRegFn = void (*)(OzakiGemmArgs, int, int, int);
 
 struct OzRegKernels;
@@ -589,6 +849,8 @@ struct OzRegTable<0> {
   static void fill(OzRegKernels&) {}
 };
 
+// Kernel per slice count: LDS-staged up to kOzLdsMaxS, register-resident
+// above (its operand blocks would not fit LDS twice).
 struct OzRegKernels {
   const void* all[kOzRegMaxS + 1] = {};
   const void* tri[kOzRegMaxS + 1] = {};
@@ -599,10 +861,17 @@ struct OzRegKernels {
 
 template <int S>
 void OzRegTable<S>::fill(OzRegKernels& k) {
-  k.all[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, false>);
-  k.tri[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, true>);
-  k.tile_m[S] = 32 * OzRegShape<S>::WM;
-  k.tile_n[S] = 32 * OzRegShape<S>::WN;
+  if constexpr (S <= kOzLdsMaxS) {
+    k.all[S] = reinterpret_cast<const void*>(&ozaki_lds_kernel<S, false>);
+    k.tri[S] = reinterpret_cast<const void*>(&ozaki_lds_kernel<S, true>);
+    k.tile_m[S] = OzLdsShape<S>::BM;
+    k.tile_n[S] = OzLdsShape<S>::BN;
+  } else {
+    k.all[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, false>);
+    k.tri[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, true>);
+    k.tile_m[S] = 32 * OzRegShape<S>::WM;
+    k.tile_n[S] = 32 * OzRegShape<S>::WN;
+  }
   OzRegTable<S - 1>::fill(k);
 }
 
@@ -611,30 +880,27 @@ void OzRegTable<S>::fill(OzRegKernels& k) {
 int ozaki_max_slices() { return kMaxSlices; }
 int ozaki_block_slices() { return 4; }
 
-hipError_t launch_ozaki_exponents(const double* X, int64_t R, int64_t K, int64_t ld, int by_col,
-                                  int* e, hipStream_t s) {
-  const int64_t n = by_col ? K : R;
-  if (n <= 0) return hipSuccess;
-  const unsigned fb = (unsigned)std::min<int64_t>((n + 255) / 256, 65535);
-  hipLaunchKernelGGL(fill_int_kernel, dim3(fb), dim3(256), 0, s, e, n, INT_MIN);
-  if (R > 0 && K > 0) {
-    if (!by_col) {
-      hipLaunchKernelGGL(exp_scan_kernel, dim3((unsigned)R), dim3(256), 0, s, X, R, K, ld, 0, e);
-    } else {
-      const unsigned gy = (unsigned)std::min<int64_t>(std::max<int64_t>(R / 64, 1), 256);
-      hipLaunchKernelGGL(exp_scan_kernel, dim3((unsigned)((K + 255) / 256), gy), dim3(256), 0, s,
-                         X, R, K, ld, 1, e);
-    }
+hipError_t launch_ozaki_scan(const double* X, int64_t R, int64_t K, int64_t ld, int by_col, int* e,
+                             int* low, int* need, hipStream_t s) {
+  if (!by_col) {
+    if (R <= 0) return hipSuccess;
+    if (R > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(row_scan_kernel, dim3((unsigned)R), dim3(256), 0, s, X, K, ld, e, need);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(exp_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, e, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_ozaki_need(const double* X, int64_t R, int64_t K, int64_t ld, int by_col,
-                             const int* e, int* out, hipStream_t s) {
-  if (R <= 0 || K <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)std::min<int64_t>((R * K + 255) / 256, 8192);
-  hipLaunchKernelGGL(need_scan_kernel, dim3(blocks), dim3(256), 0, s, X, R, K, ld, by_col, e, out);
+  if (K <= 0) return hipSuccess;
+  if (need && !low) return hipErrorInvalidValue;
+  const unsigned fb = (unsigned)std::min<int64_t>((K + 255) / 256, 65535);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(fb), dim3(256), 0, s, e, K, INT_MIN);
+  if (need) hipLaunchKernelGGL(fill_int_kernel, dim3(fb), dim3(256), 0, s, low, K, INT_MAX);
+  const int64_t gy = (R + kColScanRows - 1) / kColScanRows;
+  if (R > 0) {
+    if (gy > 65535 || (K + 63) / 64 > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(col_scan_kernel, dim3((unsigned)((K + 63) / 64), (unsigned)gy), dim3(256), 0, s,
+                       X, R, K, ld, e, need ? low : nullptr);
+  }
+  hipLaunchKernelGGL(col_finish_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, e, low, K,
+                     need);
   return hipGetLastError();
 }
 

@@ -13,19 +13,9 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
-// Device scan for the slice count that makes the digit planes exact; the
-// result is read back (the stream is synchronised).
-int slices_exact(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda,
-                 const double* B, int64_t ldb, int* e, int* f, int* counter, int* S) {
-  int st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->stream, counter);
-    hipError_t r = hipGetLastError();
-    if (r != hipSuccess) return r;
-    r = launch_ozaki_need(A, m, l, lda, 0, e, counter, c->stream);
-    if (r != hipSuccess) return r;
-    return launch_ozaki_need(B, l, n, ldb, 1, f, counter, c->stream);
-  }, "slice-count scan");
-  if (st != MPG_OK) return st;
+// Reads back the slice count the exponent scan found (the stream is
+// synchronised).
+int read_need(mpg_ctx* c, const int* counter, int* S) {
   int h = 0;
   hipError_t r = hipMemcpyAsync(&h, counter, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
@@ -45,20 +35,28 @@ int check_fp64_args(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A
   return MPG_OK;
 }
 
-// Exponents of A rows and B columns in the small workspace slot.
+// Exponents of A rows and B columns in the small workspace slot; with
+// `with_need` the same pass also finds the exact slice count (in *counter).
 int exponents(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda,
-              const double* B, int64_t ldb, int** e, int** f, int** counter) {
+              const double* B, int64_t ldb, bool with_need, int** e, int** f, int** counter) {
   void* small = nullptr;
   const int64_t mp = round_up(std::max<int64_t>(m, 1), 64), np = round_up(std::max<int64_t>(n, 1), 64);
-  int st = mpg_workspace(c, 1, (size_t)(mp + np + 64) * sizeof(int), &small);
+  int st = mpg_workspace(c, 1, (size_t)(mp + 2 * np + 64) * sizeof(int), &small);
   if (st != MPG_OK) return st;
   *e = (int*)small;
   *f = *e + mp;
-  *counter = *f + np;
+  int* low = *f + np;
+  *counter = low + np;
   return mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    hipError_t r = launch_ozaki_exponents(A, m, l, lda, 0, *e, c->stream);
+    if (with_need) {
+      hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->stream, *counter);
+      hipError_t r = hipGetLastError();
+      if (r != hipSuccess) return r;
+    }
+    int* need = with_need ? *counter : nullptr;
+    hipError_t r = launch_ozaki_scan(A, m, l, lda, 0, *e, nullptr, need, c->stream);
     if (r != hipSuccess) return r;
-    return launch_ozaki_exponents(B, l, n, ldb, 1, *f, c->stream);
+    return launch_ozaki_scan(B, l, n, ldb, 1, *f, low, need, c->stream);
   }, "exponent scan");
 }
 
@@ -74,8 +72,8 @@ extern "C" int mpg_ozaki_slices_exact(mpg_ctx* c, int64_t m, int64_t n, int64_t 
   if (m == 0 || n == 0 || l == 0) return MPG_OK;
   if ((st = mpg_device_guard(c)) != MPG_OK) return st;
   int *e, *f, *counter;
-  if ((st = exponents(c, m, n, l, A, lda, B, ldb, &e, &f, &counter)) != MPG_OK) return st;
-  return slices_exact(c, m, n, l, A, lda, B, ldb, e, f, counter, slices);
+  if ((st = exponents(c, m, n, l, A, lda, B, ldb, true, &e, &f, &counter)) != MPG_OK) return st;
+  return read_need(c, counter, slices);
 }
 
 extern "C" int mpg_ozaki_split(mpg_ctx* c, int side, int64_t rows, int64_t cols, const double* X,
@@ -95,7 +93,7 @@ extern "C" int mpg_ozaki_split(mpg_ctx* c, int side, int64_t rows, int64_t cols,
   int st = mpg_device_guard(c);
   if (st != MPG_OK) return st;
   return mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    hipError_t r = launch_ozaki_exponents(X, rows, cols, ldx, side, exps, c->stream);
+    hipError_t r = launch_ozaki_scan(X, rows, cols, ldx, side, exps, nullptr, nullptr, c->stream);
     if (r != hipSuccess) return r;
     if (side == 0)
       return launch_ozaki_split_rows(X, rows, cols, ldx, exps, slices, out, ld_out, plane, lines_p,
@@ -137,10 +135,10 @@ extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
   if ((double)ozaki_block_slices() * (double)lp * 127.0 * 127.0 >= 2147483647.0)
     return mpg_fail(c, MPG_ERR_UNSUPPORTED, "l = %lld too large for exact INT32 sums", (long long)l);
   int *e, *f, *counter;
-  if ((st = exponents(c, m, n, l, A, lda, B, ldb, &e, &f, &counter)) != MPG_OK) return st;
+  if ((st = exponents(c, m, n, l, A, lda, B, ldb, slices == 0, &e, &f, &counter)) != MPG_OK) return st;
   int S = slices;
   if (S == 0) {
-    if ((st = slices_exact(c, m, n, l, A, lda, B, ldb, e, f, counter, &S)) != MPG_OK) return st;
+    if ((st = read_need(c, counter, &S)) != MPG_OK) return st;
     S = std::max(S, 1);
     if (S > ozaki_max_slices())
       return mpg_fail(c, MPG_ERR_UNSUPPORTED, "exact slicing needs %d slices (max %d)", S,

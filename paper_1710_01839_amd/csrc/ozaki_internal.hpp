@@ -23,10 +23,13 @@ struct OzakiGemmArgs {
 
 int ozaki_max_slices();
 int ozaki_block_slices();
-hipError_t launch_ozaki_exponents(const double* X, int64_t R, int64_t K, int64_t ld, int by_col,
-                                  int* e, hipStream_t s);
-hipError_t launch_ozaki_need(const double* X, int64_t R, int64_t K, int64_t ld, int by_col,
-                             const int* e, int* out, hipStream_t s);
+// Exponents e of the rows (by_col 0) or columns (by_col 1) of X (R x K):
+// 1 + max ilogb, 0 for an all-zero line.  When `need` is given it is raised
+// to the largest number of 7-bit digits any line needs to hold its
+// elements exactly after scaling by 2^-e (columns then use `low`, K ints of
+// scratch).  One pass over X.
+hipError_t launch_ozaki_scan(const double* X, int64_t R, int64_t K, int64_t ld, int by_col, int* e,
+                             int* low, int* need, hipStream_t s);
 hipError_t launch_ozaki_split_rows(const double* X, int64_t R, int64_t K, int64_t ld, const int* e,
                                    int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Rp,
                                    int64_t Kp, hipStream_t s);

@@ -47,11 +47,34 @@ def test_split_planes_bit_exact(gpu, side):
             assert not planes[s, 101:, :].any() and not planes[s, :, 70:].any()
 
 
-def test_slices_exact_matches_oracle(gpu):
+def _tiny_mix(rows, cols, seed):
+    """Normal numbers near 2^-1000 mixed with subnormals, an all-zero row
+    and an all-zero column: exercises every branch of the bit-range scan."""
+    g = np.random.default_rng(seed)
+    X = np.ldexp(g.uniform(0.5, 1.0, (rows, cols)), -1000 - g.integers(0, 40, (rows, cols)))
+    sub = g.random((rows, cols)) < 0.2
+    X[sub] = np.ldexp(g.integers(1, 2 ** 20, sub.sum()).astype(np.float64), -1074)
+    X[g.random((rows, cols)) < 0.5] *= -1
+    X[3, :] = 0.0
+    X[:, 5] = 0.0
+    return X
+
+
+@pytest.mark.parametrize("kind", ["wide", "subnormal", "uniform"])
+def test_slices_exact_matches_oracle(gpu, kind):
     M, ctx = gpu
-    A, B = inputs.fp64_wide(90, 130, 1), inputs.fp64_wide(130, 60, 2)
-    S = M.ozaki_slices_exact(ctx, torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda())
+    if kind == "wide":
+        A, B = inputs.fp64_wide(90, 130, 1), inputs.fp64_wide(130, 60, 2)
+    elif kind == "subnormal":
+        A, B = _tiny_mix(90, 130, 1), _tiny_mix(130, 60, 2)
+    else:
+        A, B = inputs.dd_uniform(300, 520, 1)[0], inputs.dd_uniform(520, 270, 2)[0]
+    At, Bt = torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda()
+    S = M.ozaki_slices_exact(ctx, At, Bt)
     assert S == ozaki.slices_exact(A, B)
+    for side, X, want in ((0, A, ozaki.row_exponents(A)), (1, B, ozaki.col_exponents(B))):
+        _, exps = M.ozaki_split(ctx, torch.as_tensor(X).cuda(), 1, side)
+        assert np.array_equal(exps.cpu().numpy(), want), side
 
 
 def test_single_slice_integer_product_exact(gpu):
