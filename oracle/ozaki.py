@@ -17,6 +17,11 @@ products of small integers:
    weight 2^(e_i + f_j - 7g);
 4. C_ij = sum_g 2^(e_i + f_j - 7g) G_g[i, j].
 
+Double-double inputs (hi + lo) are split as one exact value: with the
+exact remainder r_0 = (hi + lo) 2^-e_i, D_s = trunc(RN(128 r_{s-1})) and
+r_s = 128 r_{s-1} - D_s, RN the rounding of the exact value to binary64
+(for lo = 0 this is step 2 again); the scale e_i comes from the hi limbs.
+
 Pairs kept: all S^2 ('all') or the triangle s + t <= S + 1 ('triangle').
 This module forms the digit planes exactly, the diagonal sums with int64
 matrix products and the combination exactly in Python integers, then rounds
@@ -59,6 +64,32 @@ def split_cols(X: np.ndarray, f: np.ndarray, S: int):
     return [np.ascontiguousarray(x.T) for x in d], np.ascontiguousarray(y.T)
 
 
+def split_rows_dd(Xhi: np.ndarray, Xlo: np.ndarray, e: np.ndarray, S: int):
+    """Digit planes of the double-double values hi + lo scaled by 2^-e_i per
+    row: D_s = trunc(RN(128 r_{s-1})), r_s = 128 r_{s-1} - D_s from the exact
+    r_0 = (hi + lo) 2^-e_i, in exact rational arithmetic (small inputs only).
+    Returns the planes and the exact remainders r_S (object array)."""
+    R, K = Xhi.shape
+    D = [np.zeros((R, K), dtype=np.int8) for _ in range(S)]
+    rem = np.empty((R, K), dtype=object)
+    for i in range(R):
+        scale = Fraction(2) ** int(-e[i])
+        for k in range(K):
+            r = (Fraction(float(Xhi[i, k])) + Fraction(float(Xlo[i, k]))) * scale
+            for s in range(S):
+                v = 128 * r
+                d = int(float(v))      # float() rounds to nearest, int() truncates
+                D[s][i, k] = d
+                r = v - d
+            rem[i, k] = r
+    return D, rem
+
+
+def split_cols_dd(Xhi: np.ndarray, Xlo: np.ndarray, f: np.ndarray, S: int):
+    D, rem = split_rows_dd(np.ascontiguousarray(Xhi.T), np.ascontiguousarray(Xlo.T), f, S)
+    return [np.ascontiguousarray(x.T) for x in D], rem.T
+
+
 def slices_needed_rows(X: np.ndarray, e: np.ndarray) -> int:
     """Smallest S for which split_rows reproduces every entry exactly:
     ceil((e_i - exponent of the lowest set bit of x) / 7), maximised."""
@@ -76,9 +107,16 @@ def slices_needed_rows(X: np.ndarray, e: np.ndarray) -> int:
     return int(max(0, np.ceil(bits.max() / 7)))
 
 
-def slices_exact(A: np.ndarray, B: np.ndarray) -> int:
-    return max(slices_needed_rows(A, row_exponents(A)),
-               slices_needed_rows(np.ascontiguousarray(B.T), col_exponents(B)))
+def slices_exact(A, B) -> int:
+    """Slices that make every digit expansion exact.  A, B: FP64 arrays or
+    (hi, lo) pairs; a pair needs the lowest set bit of either limb, against
+    the scale of the hi limbs."""
+    Ap = A if isinstance(A, tuple) else (A,)
+    Bp = B if isinstance(B, tuple) else (B,)
+    e, f = row_exponents(Ap[0]), col_exponents(Bp[0])
+    need = [slices_needed_rows(x, e) for x in Ap]
+    need += [slices_needed_rows(np.ascontiguousarray(x.T), f) for x in Bp]
+    return max(need)
 
 
 def pairs(S: int, mode: str = "all"):
@@ -118,12 +156,18 @@ def to_fraction(N, E0, idx) -> Fraction:
     return Fraction(int(N[idx])) * (Fraction(2) ** k)
 
 
-def ozaki_dd(A: np.ndarray, B: np.ndarray, S: int, mode: str = "all"):
+def ozaki_dd(A, B, S: int, mode: str = "all"):
     """The split-precision product rounded to double-double, plus the exact
-    pieces (N, E0) of the value before rounding."""
-    e, f = row_exponents(A), col_exponents(B)
-    DA, _ = split_rows(A, e, S)
-    DB, _ = split_cols(B, f, S)
+    pieces (N, E0) of the value before rounding.  A, B: FP64 arrays or
+    (hi, lo) double-double pairs."""
+    if isinstance(A, tuple):
+        e, f = row_exponents(A[0]), col_exponents(B[0])
+        DA, _ = split_rows_dd(A[0], A[1], e, S)
+        DB, _ = split_cols_dd(B[0], B[1], f, S)
+    else:
+        e, f = row_exponents(A), col_exponents(B)
+        DA, _ = split_rows(A, e, S)
+        DB, _ = split_cols(B, f, S)
     G = group_sums(DA, DB, S, mode)
     N, E0 = combine_exact(G, e, f)
     hi = np.zeros(N.shape)

@@ -81,3 +81,60 @@ def test_pair_sets():
     assert len(ozaki.pairs(5, "all")) == 25
     assert len(ozaki.pairs(5, "triangle")) == 15
     assert all(s + t <= 6 for s, t in ozaki.pairs(5, "triangle"))
+
+
+def test_dd_split_reduces_to_fp64_split():
+    """lo = 0: the double-double split is the FP64 split, digit for digit."""
+    A = inputs.fp64_wide(7, 11, 4)
+    e = ozaki.row_exponents(A)
+    D1, y1 = ozaki.split_rows(A, e, 9)
+    D2, r2 = ozaki.split_rows_dd(A, np.zeros_like(A), e, 9)
+    for s in range(9):
+        assert np.array_equal(D1[s], D2[s])
+    for idx in np.ndindex(A.shape):
+        assert r2[idx] == Fraction(float(y1[idx]))
+
+
+def test_dd_split_reconstructs_exactly():
+    """hi + lo = 2^e sum_s D_s 128^-s once S covers the lowest set bit of
+    either limb; digits stay in [-127, 127]; one slice fewer leaves a
+    nonzero remainder (the count is the smallest exact one)."""
+    hi, lo = inputs.dd_uniform(6, 9, 5)
+    e = ozaki.row_exponents(hi)
+    S = ozaki.slices_exact((hi, lo), (hi.T.copy(), lo.T.copy()))
+    assert S >= 16                      # ~106 bits below the row scale
+    D, rem = ozaki.split_rows_dd(hi, lo, e, S)
+    for i in range(6):
+        for k in range(9):
+            v = sum(Fraction(int(D[s][i, k]), 128 ** (s + 1)) for s in range(S))
+            assert v * Fraction(2) ** int(e[i]) == Fraction(float(hi[i, k])) + Fraction(float(lo[i, k]))
+            assert rem[i, k] == 0
+            assert all(-127 <= int(D[s][i, k]) <= 127 for s in range(S))
+    need_rows = max(ozaki.slices_needed_rows(hi, e), ozaki.slices_needed_rows(lo, e))
+    _, rem2 = ozaki.split_rows_dd(hi, lo, e, need_rows - 1)
+    assert any(r != 0 for r in rem2.flat)
+
+
+def test_dd_split_signed_digits_worked_example():
+    """hi = 1/2, lo = -2^-60 (value just below 1/2, e = 0): 128 r_0 =
+    64 - 2^-53 rounds to 64, so D_1 = 64 and the remainder r_1 = -2^-53 is
+    carried by a negative digit: r grows by 128 per step until
+    128 r_8 = -2^-53 128^8 = -8, so D_9 = -8 (8 128^-9 = 2^-60)."""
+    hi = np.array([[0.5]])
+    lo = np.array([[-2.0 ** -60]])
+    D, rem = ozaki.split_rows_dd(hi, lo, np.array([0]), 10)
+    got = [int(D[s][0, 0]) for s in range(10)]
+    assert got == [64, 0, 0, 0, 0, 0, 0, 0, -8, 0]
+    assert rem[0, 0] == 0
+
+
+def test_dd_exact_slices_give_exact_product():
+    """Double-double inputs with the exact slice count: the combination is
+    exactly A B (the exact product of the limb sums)."""
+    A = inputs.dd_uniform(5, 12, 6)
+    B = inputs.dd_uniform(12, 4, 7)
+    S = ozaki.slices_exact(A, B)
+    (hi, lo), (N, E0) = ozaki.ozaki_dd(A, B, S, "all")
+    Ci, s = exact.matmul_exact(A, B)
+    for idx in np.ndindex(hi.shape):
+        assert ozaki.to_fraction(N, E0, idx) == Fraction(int(Ci[idx]), 2 ** s)
