@@ -55,7 +55,8 @@ typedef enum {
   MPG_SIMPLE = 1,   /* Eq. (1): one thread per c_ij, k in order */
   MPG_BLOCK = 2,    /* Eq. (2): LDS-staged tiles, register-blocked accumulators */
   MPG_STRASSEN = 3, /* Eq. (3), Winograd's form, `depth` levels over MPG_BLOCK */
-  MPG_OZAKI = 4     /* split-precision INT8 product (mpgemm_ozaki_dd only) */
+  MPG_OZAKI = 4     /* split-precision INT8 product (DD only: mpgemm_dd_ozaki with
+                       tile->slices, all pairs) */
 } mpg_algo;
 
 /* Tile / algorithm parameters.  Zero fields mean "library default".
@@ -177,6 +178,22 @@ int mpgemm_ozaki_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
                     const double* A, int64_t lda, const double* B, int64_t ldb,
                     double* C_hi, double* C_lo, int64_t ldc, int slices, int pairs_mode);
 
+/* C := A B for double-double inputs (A_hi + A_lo, B_hi + B_lo) through the
+ * same INT8 path.  Each element's two limbs are split together as one
+ * exact value: the scaled remainder is kept as a renormalised pair (a
+ * TwoSum after each multiplication by 128), the digit is the truncation of
+ * its leading part.  The scales e_i, f_j come from the hi limbs; the exact
+ * slice count (slices = 0) covers the lowest set bit of either limb, so the
+ * result is the exact product of the limb sums up to the double-double
+ * recombination (inside the DD bound 8 l 2^-104 (|A||B|)_ij).  Arguments,
+ * limits and errors as for mpgemm_ozaki_dd; the lo limbs share the leading
+ * dimension of their hi limbs.  mpgemm_dd with MPG_OZAKI calls this with
+ * tile->slices and pairs_mode 0. */
+int mpgemm_dd_ozaki(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
+                    const double* A_hi, const double* A_lo, int64_t lda,
+                    const double* B_hi, const double* B_lo, int64_t ldb,
+                    double* C_hi, double* C_lo, int64_t ldc, int slices, int pairs_mode);
+
 /* The slice count that makes the digit planes of A's rows and B's columns
  * exact (the count slices = 0 would use).  Synchronises the stream. */
 int mpg_ozaki_slices_exact(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
@@ -193,7 +210,7 @@ int mpg_ozaki_split(mpg_ctx* ctx, int side, int64_t rows, int64_t cols,
                     const double* X, int64_t ldx, int slices,
                     int8_t* out, int64_t ld_out, int64_t plane, int32_t* exps);
 
-/* Slice count used by the context's last mpgemm_ozaki_dd call. */
+/* Slice count used by the context's last mpgemm_ozaki_dd / mpgemm_dd_ozaki call. */
 int mpg_ozaki_last_slices(const mpg_ctx* ctx);
 
 /* ---- tuner (Section 3) ------------------------------------------------ */

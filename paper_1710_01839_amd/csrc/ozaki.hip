@@ -69,8 +69,10 @@ __device__ __forceinline__ int line_digits(int e, int low) {
 // Rows of X (R x K): one workgroup per row writes e[r] = 1 + max ilogb over
 // the row (max |x| < 2^e; 0 for an all-zero row) and, when `need` is given,
 // raises *need to the row's digit count.  One pass over X.
-__global__ __launch_bounds__(256) void row_scan_kernel(const double* X, int64_t K, int64_t ld, int* e,
-                                                       int* need) {
+// With Xlo (need only) the lowest set bit of the lo limbs counts too; the
+// scale comes from X alone.
+__global__ __launch_bounds__(256) void row_scan_kernel(const double* X, const double* Xlo, int64_t K,
+                                                       int64_t ld, int* e, int* need) {
   __shared__ int s_top[4], s_low[4];
   const int64_t r = blockIdx.x;
   const double* row = X + r * ld;
@@ -82,6 +84,14 @@ __global__ __launch_bounds__(256) void row_scan_kernel(const double* X, int64_t 
       bit_range(x, t, lo);
       top = max(top, t);
       low = min(low, lo);
+    }
+    if (Xlo) {
+      const double xl = Xlo[r * ld + k];
+      if (xl != 0.0) {
+        int t, lo;
+        bit_range(xl, t, lo);
+        low = min(low, lo);
+      }
     }
   }
   top = wave_max_int(top);
@@ -111,8 +121,8 @@ __global__ __launch_bounds__(256) void row_scan_kernel(const double* X, int64_t 
 // per-workgroup maxima / minima go to top[c] / low[c] (initialised to
 // INT_MIN / INT_MAX) with one atomic each.
 constexpr int kColScanRows = 64;
-__global__ __launch_bounds__(256) void col_scan_kernel(const double* X, int64_t R, int64_t K,
-                                                       int64_t ld, int* top, int* low) {
+__global__ __launch_bounds__(256) void col_scan_kernel(const double* X, const double* Xlo, int64_t R,
+                                                       int64_t K, int64_t ld, int* top, int* low) {
   __shared__ int s_t[4][64], s_l[4][64];
   const int tc = threadIdx.x & 63, tg = threadIdx.x >> 6;
   const int64_t c = (int64_t)blockIdx.x * 64 + tc;
@@ -129,6 +139,14 @@ __global__ __launch_bounds__(256) void col_scan_kernel(const double* X, int64_t 
           bit_range(x, a, b);
           t = max(t, a);
           lo = min(lo, b);
+        }
+        if (Xlo) {
+          const double xl = Xlo[r * ld + c];
+          if (xl != 0.0) {
+            int a, b;
+            bit_range(xl, a, b);
+            lo = min(lo, b);
+          }
         }
       }
     }
@@ -170,28 +188,40 @@ __global__ __launch_bounds__(256) void col_finish_kernel(int* top_e, const int* 
 // ---------------------------------------------------------------------
 // Rows of X (R x K) -> planes out[s][r][k] (r < Rp, k < Kp, zero padded).
 // Each thread handles 8 consecutive k of one row and writes 8 bytes per
-// plane.
-__global__ __launch_bounds__(256) void split_rows_kernel(const double* X, int64_t R, int64_t K,
-                                                         int64_t ld, const int* e, int S,
+// plane.  With DD the value is X + Xlo, split as one exact value: the
+// scaled remainder is kept as a renormalised pair (TwoSum after each
+// multiplication by 128, both exact), the digit is the truncation of its
+// leading part, and subtracting the digit from that part is exact.
+template <bool DD>
+__global__ __launch_bounds__(256) void split_rows_kernel(const double* X, const double* Xlo, int64_t R,
+                                                         int64_t K, int64_t ld, const int* e, int S,
                                                          int8_t* out, int64_t ld_out,
                                                          int64_t plane, int64_t Rp, int64_t Kp) {
   const int64_t per_row = Kp / 8;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= Rp * per_row) return;
   const int64_t r = idx / per_row, k0 = (idx % per_row) * 8;
-  double y[8];
+  double y[8], yl[8];
   const int er = r < R ? e[r] : 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int64_t k = k0 + q;
-    const double x = (r < R && k < K) ? X[r * ld + k] : 0.0;
-    y[q] = ldexp(x, -er);
+    const bool ok = r < R && k < K;
+    y[q] = ldexp(ok ? X[r * ld + k] : 0.0, -er);
+    yl[q] = DD ? ldexp(ok ? Xlo[r * ld + k] : 0.0, -er) : 0.0;
   }
   for (int s = 0; s < S; ++s) {
     unsigned long long word = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      y[q] = y[q] * 128.0;
+      if (DD) {
+        double sh, sl;
+        two_sum(y[q] * 128.0, yl[q] * 128.0, sh, sl);
+        y[q] = sh;
+        yl[q] = sl;
+      } else {
+        y[q] = y[q] * 128.0;
+      }
       const double d = trunc(y[q]);
       y[q] = y[q] - d;
       word |= (unsigned long long)(uint8_t)(int8_t)(int)d << (8 * q);
@@ -204,10 +234,12 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const double* X, int64_
 // k < Kp, zero padded).  A 32 (k) x 64 (c) tile is read coalesced along c
 // (each thread keeps 8 remainders in registers); for each digit plane the
 // digits pass through LDS and are written back as 8-byte runs along k.
+// DD as in split_rows_kernel.
 constexpr int kColTileK = 32;
 constexpr int kMaxSlices = 40;
-__global__ __launch_bounds__(256) void split_cols_kernel(const double* X, int64_t K, int64_t C,
-                                                         int64_t ld, const int* f, int S,
+template <bool DD>
+__global__ __launch_bounds__(256) void split_cols_kernel(const double* X, const double* Xlo, int64_t K,
+                                                         int64_t C, int64_t ld, const int* f, int S,
                                                          int8_t* out, int64_t ld_out,
                                                          int64_t plane, int64_t Cp, int64_t Kp) {
   __shared__ int8_t dig[64][kColTileK + 8];
@@ -215,19 +247,27 @@ __global__ __launch_bounds__(256) void split_cols_kernel(const double* X, int64_
   const int tc = threadIdx.x % 64, tk = threadIdx.x / 64;  // 64 columns x 4
   const int64_t c = c0 + tc;
   const int fc = c < C ? f[c] : 0;
-  double y[kColTileK / 4];
+  double y[kColTileK / 4], yl[kColTileK / 4];
 #pragma unroll
   for (int q = 0; q < kColTileK / 4; ++q) {
     const int64_t k = k0 + tk + 4 * q;
-    const double x = (c < C && k < K) ? X[k * ld + c] : 0.0;
-    y[q] = ldexp(x, -fc);
+    const bool ok = c < C && k < K;
+    y[q] = ldexp(ok ? X[k * ld + c] : 0.0, -fc);
+    yl[q] = DD ? ldexp(ok ? Xlo[k * ld + c] : 0.0, -fc) : 0.0;
   }
   const int wc = threadIdx.x / 4, wk = (threadIdx.x % 4) * 8;
   const int64_t cc = c0 + wc;
   for (int s = 0; s < S; ++s) {
 #pragma unroll
     for (int q = 0; q < kColTileK / 4; ++q) {
-      y[q] = y[q] * 128.0;
+      if (DD) {
+        double sh, sl;
+        two_sum(y[q] * 128.0, yl[q] * 128.0, sh, sl);
+        y[q] = sh;
+        yl[q] = sl;
+      } else {
+        y[q] = y[q] * 128.0;
+      }
       const double d = trunc(y[q]);
       y[q] = y[q] - d;
       dig[tc][tk + 4 * q] = (int8_t)(int)d;
@@ -880,12 +920,13 @@ void OzRegTable<S>::fill(OzRegKernels& k) {
 int ozaki_max_slices() { return kMaxSlices; }
 int ozaki_block_slices() { return 4; }
 
-hipError_t launch_ozaki_scan(const double* X, int64_t R, int64_t K, int64_t ld, int by_col, int* e,
-                             int* low, int* need, hipStream_t s) {
+hipError_t launch_ozaki_scan(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                             int by_col, int* e, int* low, int* need, hipStream_t s) {
+  if (!need) Xlo = nullptr;  // the lo limbs only matter for the digit count
   if (!by_col) {
     if (R <= 0) return hipSuccess;
     if (R > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(row_scan_kernel, dim3((unsigned)R), dim3(256), 0, s, X, K, ld, e, need);
+    hipLaunchKernelGGL(row_scan_kernel, dim3((unsigned)R), dim3(256), 0, s, X, Xlo, K, ld, e, need);
     return hipGetLastError();
   }
   if (K <= 0) return hipSuccess;
@@ -897,30 +938,40 @@ hipError_t launch_ozaki_scan(const double* X, int64_t R, int64_t K, int64_t ld, 
   if (R > 0) {
     if (gy > 65535 || (K + 63) / 64 > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(col_scan_kernel, dim3((unsigned)((K + 63) / 64), (unsigned)gy), dim3(256), 0, s,
-                       X, R, K, ld, e, need ? low : nullptr);
+                       X, Xlo, R, K, ld, e, need ? low : nullptr);
   }
   hipLaunchKernelGGL(col_finish_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, e, low, K,
                      need);
   return hipGetLastError();
 }
 
-hipError_t launch_ozaki_split_rows(const double* X, int64_t R, int64_t K, int64_t ld, const int* e,
-                                   int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Rp,
-                                   int64_t Kp, hipStream_t s) {
+hipError_t launch_ozaki_split_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                                   const int* e, int S, int8_t* out, int64_t ld_out, int64_t plane,
+                                   int64_t Rp, int64_t Kp, hipStream_t s) {
   const int64_t work = Rp * (Kp / 8);
   if (work <= 0 || S <= 0) return hipSuccess;
-  hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, X, R,
-                     K, ld, e, S, out, ld_out, plane, Rp, Kp);
+  const dim3 grid((unsigned)((work + 255) / 256));
+  if (Xlo)
+    hipLaunchKernelGGL(split_rows_kernel<true>, grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, out,
+                       ld_out, plane, Rp, Kp);
+  else
+    hipLaunchKernelGGL(split_rows_kernel<false>, grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, out,
+                       ld_out, plane, Rp, Kp);
   return hipGetLastError();
 }
 
-hipError_t launch_ozaki_split_cols(const double* X, int64_t K, int64_t C, int64_t ld, const int* f,
-                                   int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Cp,
-                                   int64_t Kp, hipStream_t s) {
+hipError_t launch_ozaki_split_cols(const double* X, const double* Xlo, int64_t K, int64_t C, int64_t ld,
+                                   const int* f, int S, int8_t* out, int64_t ld_out, int64_t plane,
+                                   int64_t Cp, int64_t Kp, hipStream_t s) {
   if (Cp <= 0 || Kp <= 0 || S <= 0) return hipSuccess;
   if (S > kMaxSlices) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(split_cols_kernel, dim3((unsigned)(Cp / 64), (unsigned)(Kp / kColTileK)),
-                     dim3(256), 0, s, X, K, C, ld, f, S, out, ld_out, plane, Cp, Kp);
+  const dim3 grid((unsigned)(Cp / 64), (unsigned)(Kp / kColTileK));
+  if (Xlo)
+    hipLaunchKernelGGL(split_cols_kernel<true>, grid, dim3(256), 0, s, X, Xlo, K, C, ld, f, S, out,
+                       ld_out, plane, Cp, Kp);
+  else
+    hipLaunchKernelGGL(split_cols_kernel<false>, grid, dim3(256), 0, s, X, Xlo, K, C, ld, f, S, out,
+                       ld_out, plane, Cp, Kp);
   return hipGetLastError();
 }
 

@@ -37,8 +37,9 @@ int check_fp64_args(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A
 
 // Exponents of A rows and B columns in the small workspace slot; with
 // `with_need` the same pass also finds the exact slice count (in *counter).
-int exponents(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda,
-              const double* B, int64_t ldb, bool with_need, int** e, int** f, int** counter) {
+int exponents(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
+              int64_t lda, const double* B, const double* B_lo, int64_t ldb, bool with_need, int** e,
+              int** f, int** counter) {
   void* small = nullptr;
   const int64_t mp = round_up(std::max<int64_t>(m, 1), 64), np = round_up(std::max<int64_t>(n, 1), 64);
   int st = mpg_workspace(c, 1, (size_t)(mp + 2 * np + 64) * sizeof(int), &small);
@@ -54,9 +55,9 @@ int exponents(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, int6
       if (r != hipSuccess) return r;
     }
     int* need = with_need ? *counter : nullptr;
-    hipError_t r = launch_ozaki_scan(A, m, l, lda, 0, *e, nullptr, need, c->stream);
+    hipError_t r = launch_ozaki_scan(A, A_lo, m, l, lda, 0, *e, nullptr, need, c->stream);
     if (r != hipSuccess) return r;
-    return launch_ozaki_scan(B, l, n, ldb, 1, *f, low, need, c->stream);
+    return launch_ozaki_scan(B, B_lo, l, n, ldb, 1, *f, low, need, c->stream);
   }, "exponent scan");
 }
 
@@ -72,7 +73,8 @@ extern "C" int mpg_ozaki_slices_exact(mpg_ctx* c, int64_t m, int64_t n, int64_t 
   if (m == 0 || n == 0 || l == 0) return MPG_OK;
   if ((st = mpg_device_guard(c)) != MPG_OK) return st;
   int *e, *f, *counter;
-  if ((st = exponents(c, m, n, l, A, lda, B, ldb, true, &e, &f, &counter)) != MPG_OK) return st;
+  if ((st = exponents(c, m, n, l, A, nullptr, lda, B, nullptr, ldb, true, &e, &f, &counter)) != MPG_OK)
+    return st;
   return read_need(c, counter, slices);
 }
 
@@ -93,22 +95,29 @@ extern "C" int mpg_ozaki_split(mpg_ctx* c, int side, int64_t rows, int64_t cols,
   int st = mpg_device_guard(c);
   if (st != MPG_OK) return st;
   return mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    hipError_t r = launch_ozaki_scan(X, rows, cols, ldx, side, exps, nullptr, nullptr, c->stream);
+    hipError_t r = launch_ozaki_scan(X, nullptr, rows, cols, ldx, side, exps, nullptr, nullptr, c->stream);
     if (r != hipSuccess) return r;
     if (side == 0)
-      return launch_ozaki_split_rows(X, rows, cols, ldx, exps, slices, out, ld_out, plane, lines_p,
-                                     len_p, c->stream);
-    return launch_ozaki_split_cols(X, rows, cols, ldx, exps, slices, out, ld_out, plane, lines_p,
-                                   len_p, c->stream);
+      return launch_ozaki_split_rows(X, nullptr, rows, cols, ldx, exps, slices, out, ld_out, plane,
+                                     lines_p, len_p, c->stream);
+    return launch_ozaki_split_cols(X, nullptr, rows, cols, ldx, exps, slices, out, ld_out, plane,
+                                   lines_p, len_p, c->stream);
   }, "digit split");
 }
 
-extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A,
-                               int64_t lda, const double* B, int64_t ldb, double* C_hi,
-                               double* C_lo, int64_t ldc, int slices, int pairs_mode) {
+namespace {
+
+// C := A B through the INT8 path; A_lo / B_lo (both or neither) make the
+// inputs double-double, each element split as one exact value.
+int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
+                  int64_t lda, const double* B, const double* B_lo, int64_t ldb, double* C_hi,
+                  double* C_lo, int64_t ldc, int slices, int pairs_mode) {
   if (!c) return MPG_ERR_ARG;
   int st = check_fp64_args(c, m, n, l, A, lda, B, ldb);
   if (st != MPG_OK) return st;
+  const bool dd = A_lo || B_lo;
+  if (dd && l > 0 && m > 0 && n > 0 && (!A_lo || !B_lo))
+    return mpg_fail(c, MPG_ERR_ARG, "NULL lo limb");
   if (m == 0 || n == 0) return MPG_OK;
   if (!C_hi || !C_lo || ldc < n) return mpg_fail(c, MPG_ERR_ARG, "bad C");
   if (pairs_mode != 0 && pairs_mode != 1) return mpg_fail(c, MPG_ERR_ARG, "pairs_mode must be 0 or 1");
@@ -121,7 +130,8 @@ extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
       return x && y && a && b && (const char*)x < (const char*)y + b && (const char*)y < (const char*)x + a;
     };
     if (ov(C_hi, sc, A, sa) || ov(C_hi, sc, B, sb) || ov(C_lo, sc, A, sa) || ov(C_lo, sc, B, sb) ||
-        ov(C_hi, sc, C_lo, sc))
+        ov(C_hi, sc, C_lo, sc) || ov(C_hi, sc, A_lo, sa) || ov(C_hi, sc, B_lo, sb) ||
+        ov(C_lo, sc, A_lo, sa) || ov(C_lo, sc, B_lo, sb))
       return mpg_fail(c, MPG_ERR_ALIAS, "C overlaps an input or its other limb");
   }
   if ((st = mpg_device_guard(c)) != MPG_OK) return st;
@@ -135,7 +145,8 @@ extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
   if ((double)ozaki_block_slices() * (double)lp * 127.0 * 127.0 >= 2147483647.0)
     return mpg_fail(c, MPG_ERR_UNSUPPORTED, "l = %lld too large for exact INT32 sums", (long long)l);
   int *e, *f, *counter;
-  if ((st = exponents(c, m, n, l, A, lda, B, ldb, slices == 0, &e, &f, &counter)) != MPG_OK) return st;
+  if ((st = exponents(c, m, n, l, A, A_lo, lda, B, B_lo, ldb, slices == 0, &e, &f, &counter)) != MPG_OK)
+    return st;
   int S = slices;
   if (S == 0) {
     if ((st = read_need(c, counter, &S)) != MPG_OK) return st;
@@ -151,9 +162,9 @@ extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
   int8_t* Asl = (int8_t*)big;
   int8_t* Bsl = Asl + (size_t)S * planeA;
   st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    hipError_t r = launch_ozaki_split_rows(A, m, l, lda, e, S, Asl, lp, planeA, mp, lp, c->stream);
+    hipError_t r = launch_ozaki_split_rows(A, A_lo, m, l, lda, e, S, Asl, lp, planeA, mp, lp, c->stream);
     if (r != hipSuccess) return r;
-    return launch_ozaki_split_cols(B, l, n, ldb, f, S, Bsl, lp, planeB, np, lp, c->stream);
+    return launch_ozaki_split_cols(B, B_lo, l, n, ldb, f, S, Bsl, lp, planeB, np, lp, c->stream);
   }, "digit split");
   if (st != MPG_OK) return st;
   OzakiGemmArgs g{};
@@ -173,6 +184,24 @@ extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
   g.ldc = ldc;
   return mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_ozaki_gemm(g, c->stream); },
                     "INT8 MFMA product");
+}
+
+}  // namespace
+
+extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A,
+                               int64_t lda, const double* B, int64_t ldb, double* C_hi,
+                               double* C_lo, int64_t ldc, int slices, int pairs_mode) {
+  return ozaki_product(c, m, n, l, A, nullptr, lda, B, nullptr, ldb, C_hi, C_lo, ldc, slices,
+                       pairs_mode);
+}
+
+extern "C" int mpgemm_dd_ozaki(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A_hi,
+                               const double* A_lo, int64_t lda, const double* B_hi,
+                               const double* B_lo, int64_t ldb, double* C_hi, double* C_lo,
+                               int64_t ldc, int slices, int pairs_mode) {
+  if (c && l > 0 && m > 0 && n > 0 && (!A_lo || !B_lo)) return mpg_fail(c, MPG_ERR_ARG, "NULL lo limb");
+  return ozaki_product(c, m, n, l, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc, slices,
+                       pairs_mode);
 }
 
 extern "C" int mpg_ozaki_last_slices(const mpg_ctx* c) { return c ? c->last_slices : 0; }

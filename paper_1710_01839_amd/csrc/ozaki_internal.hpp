@@ -27,15 +27,18 @@ int ozaki_block_slices();
 // 1 + max ilogb, 0 for an all-zero line.  When `need` is given it is raised
 // to the largest number of 7-bit digits any line needs to hold its
 // elements exactly after scaling by 2^-e (columns then use `low`, K ints of
-// scratch).  One pass over X.
-hipError_t launch_ozaki_scan(const double* X, int64_t R, int64_t K, int64_t ld, int by_col, int* e,
-                             int* low, int* need, hipStream_t s);
-hipError_t launch_ozaki_split_rows(const double* X, int64_t R, int64_t K, int64_t ld, const int* e,
-                                   int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Rp,
-                                   int64_t Kp, hipStream_t s);
-hipError_t launch_ozaki_split_cols(const double* X, int64_t K, int64_t C, int64_t ld, const int* f,
-                                   int S, int8_t* out, int64_t ld_out, int64_t plane, int64_t Cp,
-                                   int64_t Kp, hipStream_t s);
+// scratch); with Xlo (double-double input) the lo limbs' lowest set bits
+// count too, the scale comes from X.  One pass over X (and Xlo).
+hipError_t launch_ozaki_scan(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                             int by_col, int* e, int* low, int* need, hipStream_t s);
+// Digit planes of the rows (columns) of X, or of X + Xlo split as one
+// exact value when Xlo is given (double-double input).
+hipError_t launch_ozaki_split_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                                   const int* e, int S, int8_t* out, int64_t ld_out, int64_t plane,
+                                   int64_t Rp, int64_t Kp, hipStream_t s);
+hipError_t launch_ozaki_split_cols(const double* X, const double* Xlo, int64_t K, int64_t C, int64_t ld,
+                                   const int* f, int S, int8_t* out, int64_t ld_out, int64_t plane,
+                                   int64_t Cp, int64_t Kp, hipStream_t s);
 hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s);
 
 }  // namespace mpg

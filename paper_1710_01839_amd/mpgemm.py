@@ -78,6 +78,7 @@ _sig("mpgemm_dd", [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _
 _sig("mpgemm_qd", [_vp, _i64, _i64, _i64, _pp, _i64, _pp, _i64, _pp, _i64, _ci,
                    ctypes.POINTER(mpg_tile)])
 _sig("mpgemm_ozaki_dd", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _ci, _ci])
+_sig("mpgemm_dd_ozaki", [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _ci, _ci])
 _sig("mpg_ozaki_slices_exact", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(_ci)])
 _sig("mpg_ozaki_split", [_vp, _ci, _i64, _i64, _vp, _i64, _ci, _vp, _i64, _i64, _vp])
 _sig("mpg_ozaki_last_slices", [_vp])
@@ -254,6 +255,24 @@ def mpgemm_ozaki_dd(ctx: Context, A, B, C, slices: int = 0, mode: str = "all"):
     st = _lib.mpgemm_ozaki_dd(ctx.handle, m, n, l, _ptr(A), lda, _ptr(B), ldb, _ptr(C[0]),
                               _ptr(C[1]), ldc, int(slices), 1 if mode == "triangle" else 0)
     ctx.check(st, "mpgemm_ozaki_dd")
+    return C
+
+
+def mpgemm_dd_ozaki(ctx: Context, A, B, C, slices: int = 0, mode: str = "all"):
+    """C := A B for double-double inputs on INT8 MFMA.  A, B, C: (hi, lo)
+    tuples of float64 device tensors.  slices = 0 picks the exact count."""
+    m, l, lda = _mat(A[0], "A_hi")
+    l2, n, ldb = _mat(B[0], "B_hi")
+    m2, n2, ldc = _mat(C[0], "C_hi")
+    if l2 != l or m2 != m or n2 != n:
+        raise MpgemmError(MPG_ERR_ARG, "shape mismatch")
+    for t, nm, ld in ((A[1], "A_lo", lda), (B[1], "B_lo", ldb), (C[1], "C_lo", ldc)):
+        if _mat(t, nm)[2] != ld:
+            raise MpgemmError(MPG_ERR_ARG, f"{nm} must share its hi limb's leading dimension")
+    ctx.bind_stream()
+    st = _lib.mpgemm_dd_ozaki(ctx.handle, m, n, l, _ptr(A[0]), _ptr(A[1]), lda, _ptr(B[0]), _ptr(B[1]),
+                              ldb, _ptr(C[0]), _ptr(C[1]), ldc, int(slices), 1 if mode == "triangle" else 0)
+    ctx.check(st, "mpgemm_dd_ozaki")
     return C
 
 

@@ -7,7 +7,7 @@ For each size: the exact slice count (every digit product kept, so the
 result is the product rounded to double-double up to the final
 accumulation, the accuracy class of the DD kernels), a few smaller slice
 counts, and the DD block and Strassen (depth 2) kernels on the same
-operands with zero low parts.  Printed per run (one JSON line): wall time
+operands with zero low parts (or the double-double operands themselves).  Printed per run (one JSON line): wall time
 per product, the INT8 MFMA launch time and its rate against the 5.0 POP/s
 dense INT8 peak, the splitting/scan time, and DD-equivalent Gflop/s
 (2 n^3 / t).
@@ -25,9 +25,13 @@ INT8_PEAK_TOPS = 5000.0
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, nargs="+", default=[2048, 4096])
-    ap.add_argument("--dist", choices=("uniform", "wide"), default="uniform")
+    ap.add_argument("--dist", choices=("uniform", "wide", "dd"), default="uniform",
+                    help="FP64 operands U[-1,1] or with wide exponents, or double-double operands "
+                         "(the DD GEMM workload: hi ~ U[-1,1], lo inside hi's half-ulp)")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--slices", type=int, nargs="*", default=[8, 12, 15])
+    ap.add_argument("--triangle", action="store_true",
+                    help="also time each slice count with only the pairs s + t <= S + 1")
     args = ap.parse_args()
 
     import torch
@@ -50,24 +54,41 @@ def main():
         return wall, gms / max(gn, 1), ams / args.reps
 
     for n in args.n:
-        if args.dist == "uniform":
+        dd = args.dist == "dd"
+        if dd:
+            Ad, Bd = M.to_device(inputs.dd_uniform(n, n, 20)), M.to_device(inputs.dd_uniform(n, n, 21))
+            A, B = Ad[0], Bd[0]
+        elif args.dist == "uniform":
             A = torch.as_tensor(inputs.dd_uniform(n, n, 40)[0]).cuda()
             B = torch.as_tensor(inputs.dd_uniform(n, n, 41)[0]).cuda()
         else:
             A = torch.as_tensor(inputs.fp64_wide(n, n, 40)).cuda()
             B = torch.as_tensor(inputs.fp64_wide(n, n, 41)).cuda()
         C = M.empty_like_limbs(n, n, 2)
-        s_exact = M.ozaki_slices_exact(ctx, A, B)
-        for S in [0] + [s for s in args.slices if s < s_exact]:
-            wall, kms, aux = timed(lambda: M.mpgemm_ozaki_dd(ctx, A, B, C, S, "all"))
+
+        def product(S, mode="all"):
+            if dd:
+                M.mpgemm_dd_ozaki(ctx, Ad, Bd, C, S, mode)
+            else:
+                M.mpgemm_ozaki_dd(ctx, A, B, C, S, mode)
+
+        product(0)
+        s_exact = M.ozaki_last_slices(ctx)
+        runs = [(S, "all") for S in [0] + [s for s in args.slices if s < s_exact]]
+        if args.triangle:
+            runs += [(S, "triangle") for S in [s_exact] + [s for s in args.slices if s < s_exact]]
+        for S, mode in runs:
+            wall, kms, aux = timed(lambda: product(S, mode))
             used = M.ozaki_last_slices(ctx)
-            tops = used * used * 2.0 * n ** 3 / (kms * 1e-3) / 1e12
-            print(json.dumps({"kind": "ozaki", "n": n, "dist": args.dist, "slices": used,
+            npairs = used * used if mode == "all" else used * (used + 1) // 2
+            tops = npairs * 2.0 * n ** 3 / (kms * 1e-3) / 1e12
+            print(json.dumps({"kind": "ozaki", "n": n, "dist": args.dist, "slices": used, "pairs": mode,
                               "exact": S == 0, "wall_ms": round(wall, 3), "mfma_launch_ms": round(kms, 3),
                               "aux_ms": round(aux, 3), "int8_tops": round(tops, 1),
                               "frac_int8_peak": round(tops / INT8_PEAK_TOPS, 4),
                               "dd_equiv_gflops": round(2.0 * n ** 3 / wall / 1e6, 1)}), flush=True)
-        Ad, Bd = (A, torch.zeros_like(A)), (B, torch.zeros_like(B))
+        if not dd:
+            Ad, Bd = (A, torch.zeros_like(A)), (B, torch.zeros_like(B))
         for algo, tile in (("block", None), ("strassen", {"depth": 2})):
             wall, kms, aux = timed(lambda: M.mpgemm_dd(ctx, Ad, Bd, C, algo=algo, tile=tile))
             print(json.dumps({"kind": "dd", "n": n, "algo": algo, "tile": tile, "wall_ms": round(wall, 3),

@@ -159,3 +159,64 @@ def test_full_size_4096_exact_slices_sampled(gpu):
     r = max(e / (n * 2.0 ** -104 * g) for e, g in zip(errs, mags) if g > 0)
     print("n=4096 exact slices", M.ozaki_last_slices(ctx), "ratio", r)
     assert r <= 8.0
+
+
+def run_ddoz(M, ctx, A, B, S, mode="all"):
+    m, n = A[0].shape[0], B[0].shape[1]
+    C = M.empty_like_limbs(m, n, 2)
+    M.mpgemm_dd_ozaki(ctx, M.to_device(A), M.to_device(B), C, S, mode)
+    torch.cuda.synchronize()
+    return M.to_host(C)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "illcond"])
+def test_dd_inputs_exact_slices(gpu, dist):
+    """Double-double inputs with the exact slice count: the count is the
+    oracle's, C meets the DD bound against the exact product of the limb
+    sums, and mpgemm_dd(algo='ozaki') gives the same bits."""
+    M, ctx = gpu
+    gen = inputs.dd_uniform if dist == "uniform" else inputs.dd_illcond
+    m, n, l = 96, 80, 203
+    A, B = gen(m, l, 20), gen(l, n, 21)
+    C = run_ddoz(M, ctx, A, B, 0)
+    S = M.ozaki_last_slices(ctx)
+    assert S == ozaki.slices_exact(A, B)
+    r, _ = error_ratio_full(C, A, B, -104)
+    print(dist, "DD-input exact slices", S, "ratio", r)
+    assert r <= 8.0
+    C2 = M.empty_like_limbs(m, n, 2)
+    M.mpgemm_dd(ctx, M.to_device(A), M.to_device(B), C2, algo="ozaki", tile={"slices": 0})
+    torch.cuda.synchronize()
+    C2 = M.to_host(C2)
+    assert np.array_equal(C[0], C2[0]) and np.array_equal(C[1], C2[1])
+
+
+@pytest.mark.parametrize("S,mode", [(5, "all"), (9, "triangle"), (12, "all")])
+def test_dd_inputs_match_oracle_truncated(gpu, S, mode):
+    """Truncated slicing of double-double inputs: the value the oracle's
+    two-limb split gives, up to the double-double recombination (a digit
+    taken differently would move C by far more)."""
+    M, ctx = gpu
+    m, n, l = 40, 36, 70
+    A, B = inputs.dd_uniform(m, l, 22), inputs.dd_uniform(l, n, 23)
+    C = run_ddoz(M, ctx, A, B, S, mode)
+    (hi, lo), (N, E0) = ozaki.ozaki_dd(A, B, S, mode)
+    G = cref.absprod_exact(A, B)
+    for idx in np.ndindex(hi.shape):
+        got = Fraction(float(C[0][idx])) + Fraction(float(C[1][idx]))
+        want = ozaki.to_fraction(N, E0, idx)
+        assert abs(got - want) <= Fraction(float(G[idx])) * Fraction(256, 2 ** 106) + abs(want) * Fraction(1, 2 ** 104)
+
+
+@pytest.mark.parametrize("S", [0, 6])
+def test_dd_inputs_zero_lo_reduce_to_fp64_path(gpu, S):
+    """lo = 0: the two-limb split takes the same digits as the FP64 split,
+    so both entry points return the same bits (and slice count)."""
+    M, ctx = gpu
+    m, n, l = 70, 130, 190
+    A, B = inputs.fp64_wide(m, l, 25), inputs.fp64_wide(l, n, 26)
+    C1 = run_oz(M, ctx, A, B, S)
+    S1 = M.ozaki_last_slices(ctx)
+    C2 = run_ddoz(M, ctx, (A, np.zeros_like(A)), (B, np.zeros_like(B)), S)
+    assert M.ozaki_last_slices(ctx) == S1
+    assert np.array_equal(C1[0], C2[0]) and np.array_equal(C1[1], C2[1])
