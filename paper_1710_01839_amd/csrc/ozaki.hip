@@ -701,7 +701,7 @@ __global__ __launch_bounds__(256, 1) void ozaki_reg_kernel(OzakiGemmArgs a, int 
 // Workgroup tile BM x BN, 2 x 2 waves of (BM / 32) x (BN / 32) blocks; the
 // double-double accumulators stay in registers.
 // ---------------------------------------------------------------------
-constexpr int kOzLdsMaxS = 18;
+constexpr int kOzLdsMaxS = 20;
 
 template <int S>
 struct OzLdsShape {
