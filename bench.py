@@ -11,6 +11,17 @@ Printed (one JSON line): DD Gflop/s = 2 n^3 / t (Strassen counted by the
 same conventional 2 n^3), the roofline of the dominant kernel (the grouped
 multiply-add launch, FP64 VALU issue bound, measured with HIP events on the
 library's stream), and the CPU oracle's rate on a bounded row slab.
+
+Also measured on the same GPU and reported in the same line:
+  ozaki_vs_plain  the split-precision product (INT8 MFMA, exact slice count,
+                  so DD-class accuracy) against the plain DD kernel on the same
+                  FP64 operands (U[-1,1] 2^round(N(0,10)), the split-precision
+                  workload, and U[-1,1]; n = 4096) and on the DD workload
+                  above; INT8 MFMA roofline of its product launch;
+  tuning          wall-clock tuning time at n = 4096 (DD): exhaustive, the
+                  paper's prediction procedure and MLP-pruned (top 3; the
+                  model trained on exhaustive timings of smaller shapes), with
+                  each pick's regret against the exhaustive pick.
 """
 from __future__ import annotations
 
@@ -28,6 +39,11 @@ sys.path.insert(0, ROOT)
 DD_OPS_PER_MADD = 10.0 + 6.0 / 8.0
 # MI355X FP64 VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 FP64_ISSUE_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X dense INT8 MFMA peak.
+INT8_PEAK_TOPS = 5000.0
+# Shapes whose exhaustive tuning trains the run-time model for the tuning leg.
+TUNING_TRAIN = ([(n, n, n) for n in (192, 256, 384, 512, 768, 1024, 1536, 2048, 3072)]
+                + [(512, 2048, 1024), (2048, 512, 768), (1024, 1024, 4096), (3072, 1024, 2048)])
 # HBM bytes per launch of the multiply-add kernel, from rocprofv3 FETCH_SIZE
 # and WRITE_SIZE runs of this exact kernel and launch, each scaled by what
 # the counter reads for a plain 1 GiB device copy (fetch x 2.000, write
@@ -49,7 +65,91 @@ def parse():
                    help="target CPU time of the oracle sample")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 1 GiB device copy (PMC traffic calibration)")
+    p.add_argument("--no-ozaki", action="store_true", help="skip the split-precision comparison")
+    p.add_argument("--no-tuning", action="store_true", help="skip the tuning-time measurement")
     return p.parse_args()
+
+
+def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
+    """Split-precision product (exact slice count) against the plain DD
+    algorithm `plain_step(A, B, C)` on the same operands: FP64 operands of the
+    split-precision workload (lo = 0 for the DD kernel) and the DD workload."""
+    import torch
+    from paper_1710_01839_amd import inputs
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps * 1e3
+        gms, gn = ctx.prof_read(M.MPG_KCLASS_GEMM)
+        ctx.prof_enable(False)
+        return wall, gms / max(gn, 1)
+
+    out = {}
+    C = M.empty_like_limbs(n, n, 2)
+    for name in ("fp64_wide", "fp64_uniform", "dd_uniform"):
+        if name.startswith("fp64"):
+            if name == "fp64_wide":
+                A = torch.as_tensor(inputs.fp64_wide(n, n, 40)).cuda()
+                B = torch.as_tensor(inputs.fp64_wide(n, n, 41)).cuda()
+                workload = f"FP64 U[-1,1]*2^round(N(0,10)), n={n}"
+            else:
+                A = torch.as_tensor(inputs.dd_uniform(n, n, 40)[0]).cuda()
+                B = torch.as_tensor(inputs.dd_uniform(n, n, 41)[0]).cuda()
+                workload = f"FP64 U[-1,1], n={n}"
+            Ad, Bd = (A, torch.zeros_like(A)), (B, torch.zeros_like(B))
+            oz = lambda: M.mpgemm_ozaki_dd(ctx, A, B, C, 0)
+        else:
+            Ad, Bd = M.to_device(inputs.dd_uniform(n, n, 20)), M.to_device(inputs.dd_uniform(n, n, 21))
+            oz = lambda: M.mpgemm_dd_ozaki(ctx, Ad, Bd, C, 0)
+            workload = f"double-double hi~U[-1,1], lo in hi's half-ulp, n={n}"
+        oz_ms, oz_launch = timed(oz)
+        S = M.ozaki_last_slices(ctx)
+        dd_ms, _ = timed(lambda: plain_step(Ad, Bd, C))
+        tops = S * S * 2.0 * n ** 3 / (oz_launch * 1e-3) / 1e12
+        out[name] = {"workload": workload, "slices": S, "pairs": "all", "ozaki_ms": round(oz_ms, 3),
+                     "plain_dd_ms": round(dd_ms, 3), "speedup": round(dd_ms / oz_ms, 3),
+                     "accuracy": "exact slicing: exact product up to the DD recombination "
+                                 "(inside 8 l 2^-104 (|A||B|)_ij, the DD kernel's bound)",
+                     "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": INT8_PEAK_TOPS,
+                                  "unit": "TOP/s (INT8)", "frac": round(tops / INT8_PEAK_TOPS, 4),
+                                  "kernel": "INT8 MFMA digit-plane product",
+                                  "launch_ms": round(oz_launch, 3)}}
+        del Ad, Bd
+    return out
+
+
+def tuning_time(M, ctx, n):
+    """Tuning of one n x n x n DD product: exhaustive, the paper's procedure
+    and MLP-pruned (top 3), each pick re-timed; the model is trained on the
+    exhaustive timings of TUNING_TRAIN first (not counted in its time)."""
+    import tempfile
+    T = M.Tuner(ctx)
+    db = os.path.join(tempfile.mkdtemp(), "timings.jsonl")
+    T.set_db(db)
+    t0 = time.perf_counter()
+    for m_, n_, l_ in TUNING_TRAIN:
+        T.tune("dd", m_, n_, l_, "exhaustive")
+    train_s = time.perf_counter() - t0
+    T.set_db(None)
+    mlp = M.MLP(ctx)
+    loss, rows = mlp.train_db(db, 3000, 3e-3)
+    res = {mode: T.tune("dd", n, n, n, mode, 3) for mode in ("exhaustive", "paper", "mlp")}
+    best = T.time("dd", n, n, n, res["exhaustive"]["algo"], res["exhaustive"]["tile"], reps=5)
+    out = {"shape": [n, n, n], "precision": "dd", "model_training": {"shapes": len(TUNING_TRAIN),
+                                                                    "rows": rows, "sweep_s": round(train_s, 2),
+                                                                    "final_loss": round(loss, 5)}}
+    for mode, r in res.items():
+        t = best if mode == "exhaustive" else T.time("dd", n, n, n, r["algo"], r["tile"], reps=5)
+        out[mode] = {"seconds": round(r["seconds"], 3), "trials": r["trials"],
+                     "fraction_of_exhaustive": round(r["seconds"] / res["exhaustive"]["seconds"], 4),
+                     "pick_ms": round(t, 3), "regret": round(t / best - 1.0, 4)}
+    return out
 
 
 def cpu_baseline(n: int, target_s: float):
@@ -184,6 +284,12 @@ def main():
                      "aux_ms_per_step": round(aux_ms / args.steps, 4)},
         "cpu_baseline": None,
     }
+    if not args.no_ozaki:
+        plain_algo, plain_tile = cands[key]
+        rec["ozaki_vs_plain"] = ozaki_vs_plain(
+            M, ctx, n, lambda A_, B_, C_: M.mpgemm_dd(ctx, A_, B_, C_, algo=plain_algo, tile=plain_tile))
+    if not args.no_tuning:
+        rec["tuning"] = tuning_time(M, ctx, n)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     ctx.close()
