@@ -456,45 +456,28 @@ __global__ __launch_bounds__(256, 1) void ozaki_mfma_kernel(OzakiGemmArgs a) {
 }
 
 // ---------------------------------------------------------------------
-// INT8 MFMA product, register-resident form (slices <= kOzRegMaxS; used
-// where the LDS-staged form below does not fit).
+// INT8 MFMA product, register-resident form (kOzLdsMaxS < slices <=
+// kOzRegMaxS, where the LDS-staged form below does not fit: two K steps of
+// a 32 x 32 tile would need more than 160 KiB).
 //
-// Each wavefront owns WM x WN blocks of 16 x 16 outputs and keeps the INT32
-// sum of every diagonal g = s + t live in registers (4 per lane, diagonal
-// and block), so every digit-plane fragment it loads is used by all pairs
-// it belongs to: per 64-wide K step the wave loads S WM fragments of A and
-// S WN of B (16 bytes per lane, straight from the K-contiguous digit planes
-// into registers: no LDS, no barriers) and issues the MFMAs.  A workgroup is
-// 2 x 2 independent waves.  The diagonal sums stay exact INT32 over `kchunk`
-// K steps (kchunk S 64 127^2 < 2^31); at the end of each chunk they are
-// scaled and added to the double-double accumulators, smallest weights
-// first.
+// Each wavefront owns one 16 x 16 block of C and keeps the INT32 sum of
+// every diagonal g = s + t live in registers (4 per lane and diagonal), so
+// every digit-plane fragment it loads is used by all S pairs it belongs to:
+// per 64-wide K step the wave loads S fragments of A and S of B (16 bytes
+// per lane, straight from the K-contiguous digit planes into registers) and
+// issues the S^2 (or S(S+1)/2) MFMAs.  A workgroup is 2 x 2 independent
+// waves on a 32 x 32 tile.  The diagonal sums stay exact INT32 over
+// `kchunk` K steps (kchunk S 64 127^2 < 2^31); at the end of each chunk they
+// are scaled and added to the double-double accumulators (parked in LDS
+// between flushes), smallest weights first.
 // ---------------------------------------------------------------------
 constexpr int kOzRegMaxS = 24;
-
-// Wave tile of the register-resident kernel: WM x WN blocks of 16 x 16
-// outputs, so every digit fragment loaded feeds WN (A) or WM (B) MFMAs.
-// Bigger tiles need more accumulator registers (4 per block and diagonal),
-// so the tile shrinks as the slice count grows.
-template <int S>
-struct OzRegShape {
-  static constexpr int WM = S <= 9 ? 2 : 1;
-  static constexpr int WN = S <= 5 ? 2 : 1;
-  // prefetch of the next K step's fragments (a second B buffer) where the
-  // registers allow it
-  static constexpr bool PF = S <= 17;
-};
 
 template <int S, bool TRI>
 __global__ __launch_bounds__(256, 1) void ozaki_reg_kernel(OzakiGemmArgs a, int tiles_m,
                                                            int tiles_n, int kchunk) {
   constexpr int G = 2 * S - 1;  // diagonals g = 2 .. 2S (0-based index g - 2)
-  constexpr int WM = OzRegShape<S>::WM, WN = OzRegShape<S>::WN;
-  constexpr int NB = WM * WN;   // 16 x 16 blocks per wave
-  // double-double accumulators of each lane (4 outputs per block), parked
-  // in LDS during the K loop (they are touched only when diagonal sums are
-  // flushed)
-  __shared__ double dd_hi[4 * NB][256], dd_lo[4 * NB][256];
+  __shared__ double dd_hi[4][256], dd_lo[4][256];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   int tm, tn;
   {
@@ -511,179 +494,99 @@ __global__ __launch_bounds__(256, 1) void ozaki_reg_kernel(OzakiGemmArgs a, int 
     tm = first + in % gsize;
     tn = in / gsize;
   }
-  // workgroup tile (32 WM) x (32 WN); wave (wave / 2, wave % 2) owns the
-  // 16 WM x 16 WN sub-tile at (r0, c0)
-  const int64_t r0 = (int64_t)tm * 32 * WM + 16 * WM * (wave / 2);
-  const int64_t c0 = (int64_t)tn * 32 * WN + 16 * WN * (wave % 2);
+  const int64_t r0 = (int64_t)tm * 32 + 16 * (wave / 2);
+  const int64_t c0 = (int64_t)tn * 32 + 16 * (wave % 2);
+  const int64_t col = c0 + lane % 16;
 
   // lane -> operand row / column and 16-byte chunk of the K step
   const uint32_t voffA = (uint32_t)((r0 + lane % 16) * a.l_pad + 16 * (lane / 16));
   const uint32_t voffB = (uint32_t)((c0 + lane % 16) * a.l_pad + 16 * (lane / 16));
-  const uint32_t blk16 = (uint32_t)(16 * a.l_pad);  // next 16 rows / columns
 
 #pragma unroll
-  for (int i = 0; i < 4 * NB; ++i) dd_hi[i][threadIdx.x] = dd_lo[i][threadIdx.x] = 0.0;
+  for (int i = 0; i < 4; ++i) dd_hi[i][threadIdx.x] = dd_lo[i][threadIdx.x] = 0.0;
 
-  v4i acc[G][WM][WN];
+  v4i acc[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g)
-#pragma unroll
-    for (int bi = 0; bi < WM; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < WN; ++bj) acc[g][bi][bj] = v4i{0, 0, 0, 0};
+  for (int g = 0; g < G; ++g) acc[g] = v4i{0, 0, 0, 0};
 
-  v4i fa[S][WM], fb0[S][WN], fb1[S][WN];
+  v4i fa[S], fb[S];
   const int numK = (int)(a.l_pad / 64);
-  auto ldA = [&](int s, int kt, int bi) {
+  auto ldA = [&](int s, int kt) {
     const int8_t* base = a.A + s * a.planeA + (int64_t)kt * 64;  // uniform
-    return *reinterpret_cast<const v4i*>(base + voffA + bi * blk16);
+    return *reinterpret_cast<const v4i*>(base + voffA);
   };
-  auto ldB = [&](int t, int kt, int bj) {
+  auto ldB = [&](int t, int kt) {
     const int8_t* base = a.B + t * a.planeB + (int64_t)kt * 64;
-    return *reinterpret_cast<const v4i*>(base + voffB + bj * blk16);
+    return *reinterpret_cast<const v4i*>(base + voffB);
   };
   // exact diagonal sums -> double-double, smallest weights first (adding
   // an exact zero changes nothing, so no branch)
   auto flush = [&]() {
+    int erow[4];
 #pragma unroll
-    for (int bi = 0; bi < WM; ++bi) {
-      int erow[4];
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + 4 * (lane / 16) + i;
+      erow[i] = r < a.m ? a.e[r] : 0;
+    }
+    const int fcol = col < a.n ? a.f[col] : 0;
+    double hi[4], lo[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      hi[i] = dd_hi[i][threadIdx.x];
+      lo[i] = dd_lo[i][threadIdx.x];
+    }
+#pragma unroll
+    for (int g = G - 1; g >= 0; --g) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t r = r0 + 16 * bi + 4 * (lane / 16) + i;
-        erow[i] = r < a.m ? a.e[r] : 0;
+        const double x = ldexp((double)acc[g][i], erow[i] + fcol - 7 * (g + 2));
+        double sum, err;
+        two_sum(hi[i], x, sum, err);
+        hi[i] = sum;
+        lo[i] = lo[i] + err;
       }
+      acc[g] = v4i{0, 0, 0, 0};
+    }
 #pragma unroll
-      for (int bj = 0; bj < WN; ++bj) {
-        const int64_t col = c0 + 16 * bj + lane % 16;
-        const int fcol = col < a.n ? a.f[col] : 0;
-        const int slot = 4 * (bi * WN + bj);
-        double hi[4], lo[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          hi[i] = dd_hi[slot + i][threadIdx.x];
-          lo[i] = dd_lo[slot + i][threadIdx.x];
-        }
-#pragma unroll
-        for (int g = G - 1; g >= 0; --g) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const double x = ldexp((double)acc[g][bi][bj][i], erow[i] + fcol - 7 * (g + 2));
-            double sum, err;
-            two_sum(hi[i], x, sum, err);
-            hi[i] = sum;
-            lo[i] = lo[i] + err;
-          }
-          acc[g][bi][bj] = v4i{0, 0, 0, 0};
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          dd_hi[slot + i][threadIdx.x] = hi[i];
-          dd_lo[slot + i][threadIdx.x] = lo[i];
-        }
-      }
+    for (int i = 0; i < 4; ++i) {
+      dd_hi[i][threadIdx.x] = hi[i];
+      dd_lo[i][threadIdx.x] = lo[i];
     }
   };
   auto keep = [](int s, int t) { return !TRI || s + t <= S - 1; };  // 1-based s + t <= S + 1
 
-  // One K step on the fragments in fa / fbc.  With one wavefront per SIMD
-  // nothing else hides load latency, so the next step's fragments are
-  // requested during this one: B into the other buffer up front, each A
-  // slice in place right after its last use.  The last step re-reads its
-  // own fragments (clamped index), so there is no branch.  s outer, t
-  // inner, blocks innermost: consecutive MFMAs update different
-  // accumulators.
-  auto step = [&](v4i (&fbc)[S][WN], v4i (&fbn)[S][WN], int kt) {
-    const int kn = min(kt + 1, numK - 1);
-#pragma unroll
-    for (int t = 0; t < S; ++t)
-#pragma unroll
-      for (int bj = 0; bj < WN; ++bj) fbn[t][bj] = ldB(t, kn, bj);
-#pragma unroll
-    for (int s2 = 0; s2 < S; ++s2) {
-#pragma unroll
-      for (int t = 0; t < S; ++t)
-        if (keep(s2, t))
-#pragma unroll
-          for (int bi = 0; bi < WM; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < WN; ++bj)
-              acc[s2 + t][bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                  fa[s2][bi], fbc[t][bj], acc[s2 + t][bi][bj], 0, 0, 0);
-#pragma unroll
-      for (int bi = 0; bi < WM; ++bi) fa[s2][bi] = ldA(s2, kn, bi);
-      // keep the reload of slice s2 after its last use (otherwise the
-      // scheduler hoists it and both copies need registers)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  };
-
-  if constexpr (!OzRegShape<S>::PF) {
-    for (int kc = 0; kc < numK; kc += kchunk) {
-      const int kend = min(numK, kc + kchunk);
-      for (int kt = kc; kt < kend; ++kt) {
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-#pragma unroll
-          for (int bi = 0; bi < WM; ++bi) fa[q][bi] = ldA(q, kt, bi);
-#pragma unroll
-          for (int bj = 0; bj < WN; ++bj) fb0[q][bj] = ldB(q, kt, bj);
-        }
-#pragma unroll
-        for (int s2 = 0; s2 < S; ++s2)
-#pragma unroll
-          for (int t = 0; t < S; ++t)
-            if (keep(s2, t))
-#pragma unroll
-              for (int bi = 0; bi < WM; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < WN; ++bj)
-                  acc[s2 + t][bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                      fa[s2][bi], fb0[t][bj], acc[s2 + t][bi][bj], 0, 0, 0);
-      }
-      flush();
-    }
-  } else {
-    if (numK > 0) {
+  for (int kc = 0; kc < numK; kc += kchunk) {
+    const int kend = min(numK, kc + kchunk);
+    for (int kt = kc; kt < kend; ++kt) {
 #pragma unroll
       for (int q = 0; q < S; ++q) {
-#pragma unroll
-        for (int bi = 0; bi < WM; ++bi) fa[q][bi] = ldA(q, 0, bi);
-#pragma unroll
-        for (int bj = 0; bj < WN; ++bj) fb0[q][bj] = ldB(q, 0, bj);
+        fa[q] = ldA(q, kt);
+        fb[q] = ldB(q, kt);
       }
+      // s outer, t inner: consecutive MFMAs update different diagonals, so
+      // no MFMA waits for the one before it
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+          if (keep(s2, t))
+            acc[s2 + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s2], fb[t], acc[s2 + t], 0, 0, 0);
     }
-    // kchunk is even, so every chunk but the last starts on buffer fb0
-    for (int kc = 0; kc < numK; kc += kchunk) {
-      const int kend = min(numK, kc + kchunk);
-      int kt = kc;
-      for (; kt + 1 < kend; kt += 2) {
-        step(fb0, fb1, kt);
-        step(fb1, fb0, kt + 1);
-      }
-      if (kt < kend) step(fb0, fb1, kt);  // odd tail of the last chunk
-      flush();
-    }
+    flush();
   }
 
+  if (col < a.n) {
 #pragma unroll
-  for (int bi = 0; bi < WM; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < WN; ++bj) {
-      const int64_t col = c0 + 16 * bj + lane % 16;
-      if (col >= a.n) continue;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t r = r0 + 16 * bi + 4 * (lane / 16) + i;
-        if (r < a.m) {
-          const int slot = 4 * (bi * WN + bj) + i;
-          double h = dd_hi[slot][threadIdx.x], l = dd_lo[slot][threadIdx.x];
-          dd_renorm(h, l);
-          a.C_hi[r * a.ldc + col] = h;
-          a.C_lo[r * a.ldc + col] = l;
-        }
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + 4 * (lane / 16) + i;
+      if (r < a.m) {
+        double h = dd_hi[i][threadIdx.x], l = dd_lo[i][threadIdx.x];
+        dd_renorm(h, l);
+        a.C_hi[r * a.ldc + col] = h;
+        a.C_lo[r * a.ldc + col] = l;
       }
     }
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -909,8 +812,8 @@ void OzRegTable<S>::fill(OzRegKernels& k) {
   } else {
     k.all[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, false>);
     k.tri[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, true>);
-    k.tile_m[S] = 32 * OzRegShape<S>::WM;
-    k.tile_n[S] = 32 * OzRegShape<S>::WN;
+    k.tile_m[S] = 32;
+    k.tile_n[S] = 32;
   }
   OzRegTable<S - 1>::fill(k);
 }
@@ -977,15 +880,15 @@ hipError_t launch_ozaki_split_cols(const double* X, const double* Xlo, int64_t K
 
 hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
   if (a.S >= 1 && a.S <= kOzRegMaxS) {
-    // register-resident kernel on tiles of 32 or 64 rows / columns (digit
-    // planes are padded to multiples of 64, so every tile reads inside them)
+    // LDS-staged or register-resident kernel on tiles of 32 or 64 rows /
+    // columns (digit planes are padded to multiples of 64, so every tile
+    // reads inside them)
     static const OzRegKernels table;
     const int tm_rows = table.tile_m[a.S], tn_cols = table.tile_n[a.S];
     const int64_t tiles_m = (a.m + tm_rows - 1) / tm_rows, tiles_n = (a.n + tn_cols - 1) / tn_cols;
     // diagonal sums: at most S pairs of 64 k per K step, each |d d'| <= 127^2
     const double per_step = (double)a.S * 64.0 * 127.0 * 127.0;
-    // even, so the two fragment buffers alternate across chunks
-    const int kchunk = std::max(2, (int)(2147483647.0 / per_step) & ~1);
+    const int kchunk = std::max(1, (int)(2147483647.0 / per_step));
     OzakiGemmArgs args = a;
     int tm = (int)tiles_m, tn = (int)tiles_n;
     void* kargs[] = {(void*)&args, (void*)&tm, (void*)&tn, (void*)&kchunk};

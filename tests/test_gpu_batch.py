@@ -41,7 +41,7 @@ SHAPES = [(1, 1, 1), (3, 70, 5), (64, 64, 64), (100, 37, 250), (17, 130, 9), (65
           (200, 150, 120), (31, 33, 1), (8, 8, 300), (129, 95, 64)]
 
 
-@pytest.mark.parametrize("variant", [None, 0, 1, 6])
+@pytest.mark.parametrize("variant", [None, 0, 1, 6, 7])
 def test_persistent_matches_single_kernels(gpu, variant):
     M, ctx = gpu
     tile = None if variant is None else M.variants(2)[variant]
