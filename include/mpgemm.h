@@ -59,7 +59,9 @@ typedef enum {
                        tile->slices, all pairs) */
 } mpg_algo;
 
-/* Tile / algorithm parameters.  Zero fields mean "library default".
+/* Tile / algorithm parameters.  Zero fields mean "library default" (DD:
+ * 64 x 64 x 8 with 2 x 4 per thread, operands moved to LDS by the load unit
+ * when n, l and the leading dimensions are even; QD: 32 x 32 x 8, 2 x 2).
  * (bm, bn, bk, tm, tn) must name one of the built block-kernel variants
  * (mpg_num_variants / mpg_variant), otherwise MPG_ERR_UNSUPPORTED.  The
  * paper's block size n_min corresponds to the C tile (bm x bn) and its

@@ -160,7 +160,7 @@ int mpg_check_gemm_args(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
 
 // Resolve a tile request against the built variants of a precision.
 int mpg_resolve_variant(mpg_ctx* c, int precision, const mpg_tile* t, int* variant) {
-  *variant = 0;
+  *variant = precision == 2 ? dd_default_variant() : 0;
   if (!t || (t->bm == 0 && t->bn == 0 && t->bk == 0 && t->tm == 0 && t->tn == 0)) return MPG_OK;
   const int nv = mpg_num_variants(precision);
   for (int v = 0; v < nv; ++v) {

@@ -9,8 +9,9 @@ namespace {
 using kern::variant_entry;
 using kern::VariantEntry;
 
-// Built DD tile variants (BM, BN, BK, TM, TN, threads).  Index 0 is the
-// default.  BK must be a multiple of the 8-step renormalisation period.
+// Built DD tile variants (BM, BN, BK, TM, TN, threads).  The default (tile
+// fields all zero) is the direct kernel, kDefaultVariant.  BK must be a
+// multiple of the 8-step renormalisation period.
 const VariantEntry kVariants[] = {
     variant_entry<DDArith, 64, 64, 16, 4, 4>(),
     variant_entry<DDArith, 32, 32, 16, 2, 2>(),
@@ -22,6 +23,7 @@ const VariantEntry kVariants[] = {
     kern::direct_entry<DDArith, 2, 4>(),  // 64x64x8, 2x4, 512 threads, load unit to LDS
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+constexpr int kDefaultVariant = 7;
 
 __global__ __launch_bounds__(256) void zero_kernel(double* C0, double* C1, double* C2, double* C3,
                                                    int limbs, int64_t m, int64_t n, int64_t ldc) {
@@ -39,6 +41,7 @@ __global__ __launch_bounds__(256) void zero_kernel(double* C0, double* C1, doubl
 }  // namespace
 
 int dd_num_variants() { return kNumVariants; }
+int dd_default_variant() { return kDefaultVariant; }
 const TileVariant& dd_variant(int v) { return kVariants[v].v; }
 int dd_variant_resident(int v) { return kern::resident_blocks(kVariants[v]); }
 

@@ -28,6 +28,7 @@ struct TileVariant {
 
 // ---- DD (dd_gemm.hip) ----
 int dd_num_variants();
+int dd_default_variant();  // index used when a tile leaves every field zero
 const TileVariant& dd_variant(int v);
 int dd_variant_resident(int v);  // workgroups per CU
 hipError_t launch_dd_simple(const GemmBatch& g, hipStream_t s);

@@ -230,13 +230,16 @@ def test_deterministic(gpu):
         assert np.array_equal(C1[0], C2[0]) and np.array_equal(C1[1], C2[1])
 
 
-@pytest.mark.parametrize("algo,tile", [("block", None), ("strassen", {"depth": 1}),
+@pytest.mark.parametrize("algo,tile", [("block", None), ("block", "staged"), ("strassen", {"depth": 1}),
                                        ("strassen", {"depth": 2})])
 def test_full_size_4096_sampled(gpu, algo, tile):
-    """n = 4096, the benchmark's launch configuration: exact error at sampled
-    entries (corners, random) against Python integers."""
+    """n = 4096, the benchmark's launch configuration (Strassen depth 2 over
+    the default, direct tile): exact error at sampled entries (corners,
+    random) against Python integers."""
     M, ctx = gpu
     n = 4096
+    if tile == "staged":
+        tile = M.variants(2)[0]      # the register-staged 64x64x16 kernel
     A, B = inputs.dd_uniform(n, n, 20), inputs.dd_uniform(n, n, 21)
     C = run_dd(M, ctx, A, B, algo, tile)
     pairs = sampled_pairs(n, n, 48)
