@@ -456,144 +456,11 @@ __global__ __launch_bounds__(256, 1) void ozaki_mfma_kernel(OzakiGemmArgs a) {
 }
 
 // ---------------------------------------------------------------------
-// INT8 MFMA product, register-resident form (kOzLdsMaxS < slices <=
-// kOzRegMaxS, where the LDS-staged form below does not fit: two K steps of
-// a 32 x 32 tile would need more than 160 KiB).
-//
-// Each wavefront owns one 16 x 16 block of C and keeps the INT32 sum of
-// every diagonal g = s + t live in registers (4 per lane and diagonal), so
-// every digit-plane fragment it loads is used by all S pairs it belongs to:
-// per 64-wide K step the wave loads S fragments of A and S of B (16 bytes
-// per lane, straight from the K-contiguous digit planes into registers) and
-// issues the S^2 (or S(S+1)/2) MFMAs.  A workgroup is 2 x 2 independent
-// waves on a 32 x 32 tile.  The diagonal sums stay exact INT32 over
-// `kchunk` K steps (kchunk S 64 127^2 < 2^31); at the end of each chunk they
-// are scaled and added to the double-double accumulators (parked in LDS
-// between flushes), smallest weights first.
-// ---------------------------------------------------------------------
-constexpr int kOzRegMaxS = 24;
-
-template <int S, bool TRI>
-__global__ __launch_bounds__(256, 1) void ozaki_reg_kernel(OzakiGemmArgs a, int tiles_m,
-                                                           int tiles_n, int kchunk) {
-  constexpr int G = 2 * S - 1;  // diagonals g = 2 .. 2S (0-based index g - 2)
-  __shared__ double dd_hi[4][256], dd_lo[4][256];
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  int tm, tn;
-  {
-    // XCD-aware grouped order: consecutive logical tiles run on one XCD
-    // and walk 8 tile-rows column by column, so the waves resident on an
-    // XCD share A and B digit panels in its L2
-    const int w = xcd_remap(blockIdx.x, gridDim.x);
-    constexpr int GR = 8;
-    const int per_group = GR * tiles_n;
-    const int group = w / per_group;
-    const int first = group * GR;
-    const int gsize = min(tiles_m - first, GR);
-    const int in = w - group * per_group;
-    tm = first + in % gsize;
-    tn = in / gsize;
-  }
-  const int64_t r0 = (int64_t)tm * 32 + 16 * (wave / 2);
-  const int64_t c0 = (int64_t)tn * 32 + 16 * (wave % 2);
-  const int64_t col = c0 + lane % 16;
-
-  // lane -> operand row / column and 16-byte chunk of the K step
-  const uint32_t voffA = (uint32_t)((r0 + lane % 16) * a.l_pad + 16 * (lane / 16));
-  const uint32_t voffB = (uint32_t)((c0 + lane % 16) * a.l_pad + 16 * (lane / 16));
-
-#pragma unroll
-  for (int i = 0; i < 4; ++i) dd_hi[i][threadIdx.x] = dd_lo[i][threadIdx.x] = 0.0;
-
-  v4i acc[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) acc[g] = v4i{0, 0, 0, 0};
-
-  v4i fa[S], fb[S];
-  const int numK = (int)(a.l_pad / 64);
-  auto ldA = [&](int s, int kt) {
-    const int8_t* base = a.A + s * a.planeA + (int64_t)kt * 64;  // uniform
-    return *reinterpret_cast<const v4i*>(base + voffA);
-  };
-  auto ldB = [&](int t, int kt) {
-    const int8_t* base = a.B + t * a.planeB + (int64_t)kt * 64;
-    return *reinterpret_cast<const v4i*>(base + voffB);
-  };
-  // exact diagonal sums -> double-double, smallest weights first (adding
-  // an exact zero changes nothing, so no branch)
-  auto flush = [&]() {
-    int erow[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = r0 + 4 * (lane / 16) + i;
-      erow[i] = r < a.m ? a.e[r] : 0;
-    }
-    const int fcol = col < a.n ? a.f[col] : 0;
-    double hi[4], lo[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      hi[i] = dd_hi[i][threadIdx.x];
-      lo[i] = dd_lo[i][threadIdx.x];
-    }
-#pragma unroll
-    for (int g = G - 1; g >= 0; --g) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double x = ldexp((double)acc[g][i], erow[i] + fcol - 7 * (g + 2));
-        double sum, err;
-        two_sum(hi[i], x, sum, err);
-        hi[i] = sum;
-        lo[i] = lo[i] + err;
-      }
-      acc[g] = v4i{0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      dd_hi[i][threadIdx.x] = hi[i];
-      dd_lo[i][threadIdx.x] = lo[i];
-    }
-  };
-  auto keep = [](int s, int t) { return !TRI || s + t <= S - 1; };  // 1-based s + t <= S + 1
-
-  for (int kc = 0; kc < numK; kc += kchunk) {
-    const int kend = min(numK, kc + kchunk);
-    for (int kt = kc; kt < kend; ++kt) {
-#pragma unroll
-      for (int q = 0; q < S; ++q) {
-        fa[q] = ldA(q, kt);
-        fb[q] = ldB(q, kt);
-      }
-      // s outer, t inner: consecutive MFMAs update different diagonals, so
-      // no MFMA waits for the one before it
-#pragma unroll
-      for (int s2 = 0; s2 < S; ++s2)
-#pragma unroll
-        for (int t = 0; t < S; ++t)
-          if (keep(s2, t))
-            acc[s2 + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s2], fb[t], acc[s2 + t], 0, 0, 0);
-    }
-    flush();
-  }
-
-  if (col < a.n) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = r0 + 4 * (lane / 16) + i;
-      if (r < a.m) {
-        double h = dd_hi[i][threadIdx.x], l = dd_lo[i][threadIdx.x];
-        dd_renorm(h, l);
-        a.C_hi[r * a.ldc + col] = h;
-        a.C_lo[r * a.ldc + col] = l;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------
 // INT8 MFMA product, LDS-staged form (slices <= kOzLdsMaxS).
 //
-// The register-resident form moves every fragment from L2 once per wave,
-// and the L2 -> CU path (about 15 bytes per clock and CU) then bounds it.
+// A wave that loads both operands itself moves every fragment from L2 once
+// per wave, and the L2 -> CU path (about 15 bytes per clock and CU) then
+// bounds it.
 // Here the load unit moves the workgroup's digit blocks of one K step
 // straight into LDS (global_load_lds, 16 bytes per lane, no registers),
 // double-buffered, and the four wavefronts read their fragments from LDS,
@@ -601,15 +468,15 @@ __global__ __launch_bounds__(256, 1) void ozaki_reg_kernel(OzakiGemmArgs a, int 
 // columns) x 64 k of one slice, stored in MFMA lane order: lane l's 16 bytes
 // (row l % 16, k chunk l / 16) at byte 16 l, so both the load and the
 // fragment read are one contiguous 1 KiB per wavefront.
-// Workgroup tile BM x BN, 2 x 2 waves of (BM / 32) x (BN / 32) blocks; the
-// double-double accumulators stay in registers.
+// Workgroup tile 64 x 64, 2 x 2 waves of 2 x 2 blocks; the double-double
+// accumulators wait in C between K chunks.
 // ---------------------------------------------------------------------
-constexpr int kOzLdsMaxS = 20;
+constexpr int kOzLdsMaxS = 8;
 
 template <int S>
 struct OzLdsShape {
-  static constexpr int BM = S <= 12 ? 64 : 32;
-  static constexpr int BN = S <= 9 ? 64 : 32;
+  static constexpr int BM = 64;
+  static constexpr int BN = 64;
   static constexpr int WM = BM / 32, WN = BN / 32;     // 16 x 16 blocks per wave
   static constexpr int NBA = BM / 16, NBB = BN / 16;   // blocks per slice and operand
   static constexpr int BLOCKS = S * (NBA + NBB);       // 1 KiB blocks per K step
@@ -779,43 +646,218 @@ __global__ __launch_bounds__(256, 1) void ozaki_lds_kernel(OzakiGemmArgs a, int 
   if (numK == 0) flush(true, true);  // empty K: C := 0
 }
 
-using OzRegFn = void (*)(OzakiGemmArgs, int, int, int);
+// ---------------------------------------------------------------------
+// INT8 MFMA product, band form (kOzLdsMaxS < slices <= kOzBandMaxS).
+//
+// With 2S - 1 diagonal accumulators live, a wavefront can own only one or
+// two 16 x 16 blocks, and a workgroup's digit blocks of two K steps no
+// longer fit LDS, so sharing operands between wavefronts has to come from
+// elsewhere.  Here the four wavefronts of a workgroup stack vertically:
+// wave w owns rows m0 + 16 w .. + 15 and the WN 16-column blocks of the
+// workgroup's 16 WN columns.  Each wave loads its own A fragments straight
+// into registers (no other wave uses those rows) and reloads each block of
+// slices for the next K step right after its last use; only the
+// workgroup's B blocks are moved into LDS by the load unit (double-buffered)
+// and shared by all four waves.  Slices are processed four at a time so each
+// B fragment read from LDS feeds 4 WN MFMAs.  Per K step a workgroup moves
+// (4 + WN) S KiB for 4 WN S^2 MFMAs; a wave loading both operands itself
+// would move 2S KiB for S^2.
+// ---------------------------------------------------------------------
+constexpr int kOzBandMinS = kOzLdsMaxS + 1, kOzBandMaxS = 24;
+// column blocks per wavefront: two while the 2S - 1 accumulators of both fit
+template <int S>
+constexpr int oz_band_wn() {
+  return S <= 20 ? 2 : 1;
+}
 
-struct OzRegKernels;
+template <int S, int WN>
+__device__ __forceinline__ void oz_band_issue(int8_t* __restrict__ dst, const OzakiGemmArgs& a,
+                                              int64_t n0, int kn, uint32_t lane_off, int wave) {
+  constexpr int NBLK = WN * S;  // B blocks per K step: slice t, column block bj
+#pragma unroll
+  for (int i = 0; i < (NBLK + 3) / 4; ++i) {
+    const int blk = wave + 4 * i;
+    if (blk < NBLK) {
+      const int t = blk / WN, bj = blk % WN;
+      const int8_t* src = a.B + t * a.planeB + (n0 + 16 * bj) * a.l_pad + (int64_t)kn * 64;
+      __builtin_amdgcn_global_load_lds(src + lane_off, (lds_ptr)(dst + blk * 1024), 16, 0, 0);
+    }
+  }
+}
+
+// One K step on the B blocks in `cur` and the A fragments in fa (slice s
+// of this wave's rows, all resident); starts moving step kn's B blocks into
+// `nxt` and reloads each block of A slices for step kn right after its last
+// use (the last step re-reads its own, still valid, step).
+template <int S, int WN, bool TRI>
+__device__ __forceinline__ void oz_band_step(int8_t* __restrict__ nxt, const int8_t* __restrict__ cur,
+                                             const OzakiGemmArgs& a, const int8_t* rowsA, int64_t n0,
+                                             int kn, bool more, uint32_t lane_off, int lane, int wave,
+                                             v4i (&fa)[S], v4i (&acc)[2 * S - 1][WN]) {
+  constexpr int SB = 4;  // slices per block of the s loop
+  if (more) oz_band_issue<S, WN>(nxt, a, n0, kn, lane_off, wave);
+  // the reloads below must not move above the B loads
+  __builtin_amdgcn_sched_barrier(0);
+  const int kr = more ? kn : kn - 1;
+  auto read_b = [&](int t, v4i (&f)[WN]) {
+#pragma unroll
+    for (int bj = 0; bj < WN; ++bj)
+      f[bj] = *reinterpret_cast<const v4i*>(cur + (WN * t + bj) * 1024 + 16 * lane);
+  };
+#pragma unroll
+  for (int s0 = 0; s0 < S; s0 += SB) {
+    // B fragments one slice ahead of their MFMAs; the scheduling barrier
+    // keeps later slices' reads from being hoisted (registers)
+    v4i fb[2][WN];
+    read_b(0, fb[0]);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      if (t + 1 < S) read_b(t + 1, fb[(t + 1) & 1]);
+#pragma unroll
+      for (int s2 = s0; s2 < s0 + SB && s2 < S; ++s2)
+        if (!TRI || s2 + t <= S - 1)
+#pragma unroll
+          for (int bj = 0; bj < WN; ++bj)
+            acc[s2 + t][bj] =
+                __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s2], fb[t & 1][bj], acc[s2 + t][bj], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int s2 = s0; s2 < s0 + SB && s2 < S; ++s2)
+      fa[s2] = *reinterpret_cast<const v4i*>(rowsA + s2 * a.planeA + (int64_t)kr * 64 + lane_off);
+    // keeps the reloads of this block of slices after its MFMAs (registers)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int S, int WN, bool TRI>
+__global__ __launch_bounds__(256, 1) void ozaki_band_kernel(OzakiGemmArgs a, int tiles_m,
+                                                            int tiles_n, int kchunk) {
+  constexpr int G = 2 * S - 1, NBLK = WN * S;
+  __shared__ __attribute__((aligned(16))) int8_t lds[2 * NBLK * 1024];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  int tm, tn;
+  {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    constexpr int GR = 8;
+    const int per_group = GR * tiles_n;
+    const int group = w / per_group;
+    const int first = group * GR;
+    const int gsize = min(tiles_m - first, GR);
+    const int in = w - group * per_group;
+    tm = first + in % gsize;
+    tn = in / gsize;
+  }
+  const int64_t m0 = (int64_t)tm * 64, n0 = (int64_t)tn * 16 * WN;
+  const int64_t r0 = m0 + 16 * wave, c0 = n0;
+  const uint32_t lane_off = (uint32_t)((lane % 16) * a.l_pad + 16 * (lane / 16));
+  const int8_t* rowsA = a.A + r0 * a.l_pad;  // this wave's 16 rows (uniform)
+
+  v4i acc[G][WN];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int bj = 0; bj < WN; ++bj) acc[g][bj] = v4i{0, 0, 0, 0};
+
+  // exact diagonal sums -> double-double (accumulators wait in C between K
+  // chunks), smallest weights first
+  auto flush = [&](bool first, bool last) {
+    int erow[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + 4 * (lane / 16) + i;
+      erow[i] = r < a.m ? a.e[r] : 0;
+    }
+#pragma unroll
+    for (int bj = 0; bj < WN; ++bj) {
+      const int64_t col = c0 + 16 * bj + lane % 16;
+      const int fcol = col < a.n ? a.f[col] : 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = r0 + 4 * (lane / 16) + i;
+        const bool inside = r < a.m && col < a.n;
+        double hi = 0.0, lo = 0.0;
+        if (!first && inside) {
+          hi = a.C_hi[r * a.ldc + col];
+          lo = a.C_lo[r * a.ldc + col];
+        }
+#pragma unroll
+        for (int g = G - 1; g >= 0; --g) {
+          const double x = ldexp((double)acc[g][bj][i], erow[i] + fcol - 7 * (g + 2));
+          double sum, err;
+          two_sum(hi, x, sum, err);
+          hi = sum;
+          lo = lo + err;
+        }
+        if (last) dd_renorm(hi, lo);
+        if (inside) {
+          a.C_hi[r * a.ldc + col] = hi;
+          a.C_lo[r * a.ldc + col] = lo;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc[g][bj] = v4i{0, 0, 0, 0};
+    }
+  };
+
+  const int numK = (int)(a.l_pad / 64);
+  v4i fa[S];
+  if (numK > 0) {
+    oz_band_issue<S, WN>(lds, a, n0, 0, lane_off, wave);
+#pragma unroll
+    for (int q = 0; q < S; ++q) fa[q] = *reinterpret_cast<const v4i*>(rowsA + q * a.planeA + lane_off);
+  }
+  for (int kc = 0; kc < numK; kc += kchunk) {
+    const int kend = min(numK, kc + kchunk);
+    for (int kt = kc; kt < kend; ++kt) {
+      int8_t* cur = lds + (kt & 1) * NBLK * 1024;
+      int8_t* nxt = lds + ((kt & 1) ^ 1) * NBLK * 1024;
+      // this thread's loads are done (B blocks of this step, A fragments);
+      // after the barrier everyone's are, and nobody reads `nxt` any more
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      __syncthreads();
+      oz_band_step<S, WN, TRI>(nxt, cur, a, rowsA, n0, kt + 1, kt + 1 < numK, lane_off, lane, wave, fa, acc);
+    }
+    flush(kc == 0, kend == numK);
+  }
+  if (numK == 0) flush(true, true);  // empty K: C := 0
+}
+
+struct OzKernels;
 
 template <int S>
-struct OzRegTable {
-  static void fill(OzRegKernels& k);
+struct OzTable {
+  static void fill(OzKernels& k);
 };
 template <>
-struct OzRegTable<0> {
-  static void fill(OzRegKernels&) {}
+struct OzTable<0> {
+  static void fill(OzKernels&) {}
 };
 
-// Kernel per slice count: LDS-staged up to kOzLdsMaxS, register-resident
-// above (its operand blocks would not fit LDS twice).
-struct OzRegKernels {
-  const void* all[kOzRegMaxS + 1] = {};
-  const void* tri[kOzRegMaxS + 1] = {};
-  int tile_m[kOzRegMaxS + 1] = {};  // workgroup tile rows / columns
-  int tile_n[kOzRegMaxS + 1] = {};
-  OzRegKernels() { OzRegTable<kOzRegMaxS>::fill(*this); }
+// Kernel per slice count: LDS-staged up to kOzLdsMaxS, band form up to
+// kOzBandMaxS.
+struct OzKernels {
+  const void* all[kOzBandMaxS + 1] = {};
+  const void* tri[kOzBandMaxS + 1] = {};
+  int tile_m[kOzBandMaxS + 1] = {};  // workgroup tile rows / columns
+  int tile_n[kOzBandMaxS + 1] = {};
+  OzKernels() { OzTable<kOzBandMaxS>::fill(*this); }
 };
 
 template <int S>
-void OzRegTable<S>::fill(OzRegKernels& k) {
+void OzTable<S>::fill(OzKernels& k) {
   if constexpr (S <= kOzLdsMaxS) {
     k.all[S] = reinterpret_cast<const void*>(&ozaki_lds_kernel<S, false>);
     k.tri[S] = reinterpret_cast<const void*>(&ozaki_lds_kernel<S, true>);
     k.tile_m[S] = OzLdsShape<S>::BM;
     k.tile_n[S] = OzLdsShape<S>::BN;
   } else {
-    k.all[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, false>);
-    k.tri[S] = reinterpret_cast<const void*>(&ozaki_reg_kernel<S, true>);
-    k.tile_m[S] = 32;
-    k.tile_n[S] = 32;
+    k.all[S] = reinterpret_cast<const void*>(&ozaki_band_kernel<S, oz_band_wn<S>(), false>);
+    k.tri[S] = reinterpret_cast<const void*>(&ozaki_band_kernel<S, oz_band_wn<S>(), true>);
+    k.tile_m[S] = 64;
+    k.tile_n[S] = 16 * oz_band_wn<S>();
   }
-  OzRegTable<S - 1>::fill(k);
+  OzTable<S - 1>::fill(k);
 }
 
 }  // namespace
@@ -879,11 +921,10 @@ hipError_t launch_ozaki_split_cols(const double* X, const double* Xlo, int64_t K
 }
 
 hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
-  if (a.S >= 1 && a.S <= kOzRegMaxS) {
-    // LDS-staged or register-resident kernel on tiles of 32 or 64 rows /
-    // columns (digit planes are padded to multiples of 64, so every tile
-    // reads inside them)
-    static const OzRegKernels table;
+  if (a.S >= 1 && a.S <= kOzBandMaxS) {
+    // LDS-staged or band kernel on tiles of 16 to 64 rows / columns (digit
+    // planes are padded to multiples of 64, so every tile reads inside them)
+    static const OzKernels table;
     const int tm_rows = table.tile_m[a.S], tn_cols = table.tile_n[a.S];
     const int64_t tiles_m = (a.m + tm_rows - 1) / tm_rows, tiles_n = (a.n + tn_cols - 1) / tn_cols;
     // diagonal sums: at most S pairs of 64 k per K step, each |d d'| <= 127^2
