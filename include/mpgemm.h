@@ -221,7 +221,8 @@ typedef enum {
   MPG_TUNE_EXHAUSTIVE = 0, /* time every candidate at full size */
   MPG_TUNE_PAPER = 1,      /* the paper's procedure: (1) predict the block time of
                               every tile from a slab product, keep the best tile;
-                              (2) time simple, block and Strassen over that tile;
+                              (2) time simple, block and Strassen over that tile
+                              (and, for DD, the MPG_OZAKI candidate);
                               (3) take the fastest */
   MPG_TUNE_MLP = 2         /* the run-time model ranks every candidate; only the
                               best `topk` are timed, the fastest measured wins */
@@ -229,7 +230,10 @@ typedef enum {
 
 /* Candidates for a shape: MPG_SIMPLE, MPG_BLOCK with every built tile,
  * MPG_STRASSEN with every tile and depth 1..3 (DD) / 1..2 (QD) while the
- * leaves keep at least 64 per side.  precision: 2 (DD) or 4 (QD). */
+ * leaves keep at least 64 per side, and last, for DD, MPG_OZAKI with
+ * slices = 0 (exact slice count, all pairs).  precision: 2 (DD) or 4 (QD).
+ * The tuner times them on its own buffers: limb 0 uniform in [-1, 1), each
+ * lower limb a uniform fraction of half an ulp of the limb above. */
 int mpg_num_candidates(int precision, int64_t m, int64_t n, int64_t l);
 int mpg_candidate(int precision, int64_t m, int64_t n, int64_t l, int index,
                   int* algo, mpg_tile* tile);
@@ -258,7 +262,8 @@ int mpg_predict_block(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t
 int mpg_tune(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l, int mode, int topk,
              int* best_algo, mpg_tile* best_tile, double* best_ms, double* seconds, int* trials);
 
-/* Put a choice into the table used by MPG_AUTO directly. */
+/* Put a choice into the table used by MPG_AUTO directly (MPG_OZAKI: DD
+ * only, tile->slices as for mpgemm_dd_ozaki). */
 int mpg_tune_table_set(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
                        int algo, const mpg_tile* tile);
 
@@ -266,9 +271,10 @@ int mpg_tune_table_set(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_
 
 /* Features of one candidate (MPG_MLP_FEATURES floats): log2 m, n, l / 12;
  * DD and QD indicators; simple / block / Strassen indicators; log2 bm / 8,
- * log2 bn / 8, log2 bk / 5, tm tn / 64, Strassen depth / 3, log2 batch / 10.
- * Target of the model: natural log of milliseconds. */
-#define MPG_MLP_FEATURES 14
+ * log2 bn / 8, log2 bk / 5, tm tn / 64, Strassen depth / 3, log2 batch / 10;
+ * split-precision indicator.  Target of the model: natural log of
+ * milliseconds. */
+#define MPG_MLP_FEATURES 15
 int mpg_mlp_features(int precision, int64_t m, int64_t n, int64_t l, int algo,
                      const mpg_tile* tile, int batch, float* out);
 

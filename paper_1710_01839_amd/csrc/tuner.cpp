@@ -3,9 +3,12 @@
 // Section 3: (1) predict the full-size block time of every tile from a
 // partial product (a slab of A's rows against the full B) and keep the best
 // tile, (2) time simple, block and Strassen at full size, (3) take the
-// fastest.  Also an exhaustive mode (every candidate timed) and a mode
-// where the run-time MLP ranks all candidates and only the best few are
-// timed.  Measurements are appended to a JSONL timing database.
+// fastest.  For DD the split-precision INT8 product with the exact slice
+// count (the same componentwise accuracy class as the block kernel) is one
+// more candidate, timed in step (2) beside the others.  Also an exhaustive
+// mode (every candidate timed) and a mode where the run-time MLP ranks all
+// candidates and only the best few are timed.  Measurements are appended to
+// a JSONL timing database.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -52,11 +55,20 @@ std::vector<Cand> candidates(int prec, int64_t m, int64_t n, int64_t l) {
       out.push_back(t);
     }
   }
+  if (prec == 2) {
+    Cand z{};
+    z.algo = MPG_OZAKI;
+    z.tile.slices = 0;  // exact digit expansions, every slice pair
+    out.push_back(z);
+  }
   return out;
 }
 
-// Timing buffers for one shape: inputs are canonical multi-limb values with
-// zero lower limbs (the kernels' run time does not depend on the values).
+// Timing buffers for one shape: canonical multi-limb values, limb 0 in
+// [-1, 1), each lower limb below half an ulp of the limb above.  The FP64
+// kernels' run time does not depend on the values; the split-precision
+// product's does (its exact slice count follows the lowest set bits), and
+// full lower limbs give it the count that general DD data needs.
 struct Scratch {
   int limbs = 0;
   int64_t m = 0, n = 0, l = 0;
@@ -65,17 +77,15 @@ struct Scratch {
   double* C[4] = {};
 };
 
-__global__ void fill_kernel(double* p, int64_t n, uint64_t seed, int zero) {
+__global__ void fill_kernel(double* p, const double* above, int64_t n, uint64_t seed) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    if (zero) {
-      p[i] = 0.0;
-      continue;
-    }
     uint64_t z = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
-    p[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+    const double u = (double)(z >> 11) * 0x1.0p-52 - 1.0;  // [-1, 1)
+    // |above| 2^-54 |u| < 2^(e-53) = half an ulp of `above` when 2^e <= |above|
+    p[i] = above ? above[i] * 0x1.0p-54 * u : u;
   }
 }
 
@@ -106,10 +116,10 @@ int make_scratch(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l, Scratch
                     (long long)n, (long long)l);
   }
   for (int q = 0; q < limbs; ++q) {
-    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c->stream, s.A[q], m * l,
-                       (uint64_t)(11 + q), q > 0);
-    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c->stream, s.B[q], l * n,
-                       (uint64_t)(23 + q), q > 0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c->stream, s.A[q],
+                       (const double*)(q ? s.A[q - 1] : nullptr), m * l, (uint64_t)(11 + q));
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c->stream, s.B[q],
+                       (const double*)(q ? s.B[q - 1] : nullptr), l * n, (uint64_t)(23 + q));
   }
   r = hipStreamSynchronize(c->stream);
   if (r != hipSuccess) {
@@ -161,10 +171,11 @@ void db_append(mpg_ctx* c, int prec, int64_t m, int64_t n, int64_t l, const Cand
   if (!f) return;
   std::fprintf(f,
                "{\"prec\":%d,\"m\":%lld,\"n\":%lld,\"l\":%lld,\"algo\":%d,\"bm\":%d,\"bn\":%d,"
-               "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"ms\":%.6f,\"kind\":\"%s\"}\n",
+               "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"slices\":%d,\"ms\":%.6f,"
+               "\"kind\":\"%s\"}\n",
                prec, (long long)m, (long long)n, (long long)l, cd.algo, cd.tile.bm, cd.tile.bn,
-               cd.tile.bk, cd.tile.tm, cd.tile.tn, cd.algo == MPG_STRASSEN ? cd.tile.depth : 0, ms,
-               kind);
+               cd.tile.bk, cd.tile.tm, cd.tile.tn, cd.algo == MPG_STRASSEN ? cd.tile.depth : 0,
+               cd.algo == MPG_OZAKI ? cd.tile.slices : 0, ms, kind);
   std::fclose(f);
 }
 
@@ -314,7 +325,8 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
         bt = cd.tile;
       }
     }
-    // (2) simple, block with that tile, and Strassen over it, at full size
+    // (2) simple, block with that tile, Strassen over it and (DD) the
+    // split-precision product, at full size
     if (st == MPG_OK) {
       std::vector<Cand> finals;
       Cand x{};
@@ -327,6 +339,8 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
         if (cd.algo == MPG_STRASSEN && cd.tile.bm == bt.bm && cd.tile.bn == bt.bn &&
             cd.tile.bk == bt.bk && cd.tile.tm == bt.tm && cd.tile.tn == bt.tn)
           finals.push_back(cd);
+      for (const auto& cd : cands)
+        if (cd.algo == MPG_OZAKI) finals.push_back(cd);
       // (3) the fastest of them
       for (const auto& cd : finals)
         if ((st = trial(cd)) != MPG_OK) break;
@@ -362,7 +376,8 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
 
 extern "C" int mpg_tune_table_set(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l,
                                   int algo, const mpg_tile* tile) {
-  if (!c || (precision != 2 && precision != 4) || algo < MPG_SIMPLE || algo > MPG_STRASSEN)
+  if (!c || (precision != 2 && precision != 4) || algo < MPG_SIMPLE || algo > MPG_OZAKI ||
+      (algo == MPG_OZAKI && precision != 2))
     return MPG_ERR_ARG;
   mpg_tile t{};
   if (tile) t = *tile;
@@ -380,17 +395,19 @@ extern "C" int mpg_mlp_train_db(mpg_ctx* c, const char* path, int epochs, float 
   std::vector<float> X, y;
   char line[1024];
   while (std::fgets(line, sizeof line, f)) {
-    int prec, algo, bm, bn, bk, tm, tn, depth;
+    int prec, algo, bm, bn, bk, tm, tn, depth, slices;
     long long m, n, l;
     double ms;
     char kind[32];
     if (std::sscanf(line,
                     "{\"prec\":%d,\"m\":%lld,\"n\":%lld,\"l\":%lld,\"algo\":%d,\"bm\":%d,\"bn\":%d,"
-                    "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"ms\":%lf,\"kind\":\"%31[a-z]\"",
-                    &prec, &m, &n, &l, &algo, &bm, &bn, &bk, &tm, &tn, &depth, &ms, kind) != 13)
+                    "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"slices\":%d,\"ms\":%lf,"
+                    "\"kind\":\"%31[a-z]\"",
+                    &prec, &m, &n, &l, &algo, &bm, &bn, &bk, &tm, &tn, &depth, &slices, &ms,
+                    kind) != 14)
       continue;
     if (std::strcmp(kind, "trial") != 0 || !(ms > 0.0)) continue;
-    mpg_tile t{bm, bn, bk, tm, tn, depth, 0};
+    mpg_tile t{bm, bn, bk, tm, tn, depth, slices};
     float feat[MPG_MLP_FEATURES];
     if (mpg_mlp_features(prec, m, n, l, algo, &t, 1, feat) != MPG_OK) continue;
     X.insert(X.end(), feat, feat + MPG_MLP_FEATURES);

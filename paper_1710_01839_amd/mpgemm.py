@@ -365,7 +365,7 @@ class BatchPlan:
             pass
 
 
-MLP_FEATURES = 14
+MLP_FEATURES = 15
 TUNE_MODES = {"exhaustive": 0, "paper": 1, "mlp": 2}
 PRECISION = {"dd": 2, "qd": 4}
 
@@ -440,6 +440,14 @@ class Tuner:
                                      ctypes.byref(ms), ctypes.byref(secs), ctypes.byref(trials)), "mpg_tune")
         return {"algo": a.value, "tile": t.as_dict(), "ms": ms.value, "seconds": secs.value,
                 "trials": trials.value}
+
+    def table_set(self, precision, m, n, l, algo, tile=None):
+        """Put a choice into the table MPG_AUTO follows."""
+        t = make_tile(tile)
+        self.ctx.check(_lib.mpg_tune_table_set(self.ctx.handle, _prec(precision), m, n, l,
+                                               ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
+                                               ctypes.byref(t) if t is not None else None),
+                       "mpg_tune_table_set")
 
 
 class MLP:

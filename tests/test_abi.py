@@ -56,12 +56,18 @@ def test_tuner_host_logic(lib):
     import numpy as np
     from paper_1710_01839_amd import mpgemm as M
     nv_dd, nv_qd = lib.mpg_num_variants(2), lib.mpg_num_variants(4)
-    # simple + every tile + every tile under each admissible Strassen depth
-    assert len(M.candidates("dd", 4096, 4096, 4096)) == 1 + nv_dd * 4
+    # simple + every tile + every tile under each admissible Strassen depth,
+    # and for DD the split-precision product with the exact slice count
+    assert len(M.candidates("dd", 4096, 4096, 4096)) == 1 + nv_dd * 4 + 1
     assert len(M.candidates("qd", 2048, 2048, 2048)) == 1 + nv_qd * 3
-    assert len(M.candidates("dd", 200, 200, 200)) == 1 + nv_dd * 2      # leaves >= 64: depth 1 only
-    assert len(M.candidates("dd", 100, 5000, 5000)) == 1 + nv_dd
+    assert len(M.candidates("dd", 200, 200, 200)) == 1 + nv_dd * 2 + 1  # leaves >= 64: depth 1 only
+    assert len(M.candidates("dd", 100, 5000, 5000)) == 1 + nv_dd + 1
+    algo, tile = M.candidates("dd", 512, 512, 512)[-1]
+    assert algo == M.MPG_OZAKI and tile["slices"] == 0
+    assert all(a != M.MPG_OZAKI for a, _ in M.candidates("qd", 512, 512, 512))
     f = M.mlp_features("qd", 256, 512, 1024, "block", M.variants(4)[0], batch=8)
     assert f.dtype == np.float32 and f.shape == (M.MLP_FEATURES,)
     assert np.allclose(f[:3], [8 / 12, 9 / 12, 10 / 12]) and f[4] == 1 and f[6] == 1
-    assert np.isclose(f[13], 0.3)
+    assert np.isclose(f[13], 0.3) and f[14] == 0
+    g = M.mlp_features("dd", 256, 512, 1024, "ozaki", {"slices": 0})
+    assert g[14] == 1 and g[3] == 1 and not g[5:8].any()

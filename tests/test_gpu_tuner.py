@@ -11,7 +11,7 @@ from paper_1710_01839_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-F, H = 14, 64
+F, H = 15, 64
 
 
 def _dataset(M, rows=300, seed=0):
@@ -138,7 +138,8 @@ def test_tuner_modes(gpu, tmp_path):
         pa = T.tune(prec, n, n, n, "paper")
         ml = T.tune(prec, n, n, n, "mlp", 3)
         assert ml["trials"] == 3 and ex["trials"] == len(M.candidates(prec, n, n, n))
-        assert pa["trials"] <= 1 + 1 + 3
+        # simple, block, up to three Strassen depths, and the split product for DD
+        assert pa["trials"] <= 1 + 1 + 3 + (prec == "dd")
         best = T.time(prec, n, n, n, ex["algo"], ex["tile"], reps=5)
         got = T.time(prec, n, n, n, ml["algo"], ml["tile"], reps=5)
         print(prec, n, "exhaustive", ex, "paper", pa, "mlp", ml)
@@ -156,7 +157,37 @@ def test_auto_uses_tuning_table(gpu):
     A, B = M.to_device(inputs.dd_uniform(n, n, 1)), M.to_device(inputs.dd_uniform(n, n, 2))
     C1, C2 = M.empty_like_limbs(n, n, 2), M.empty_like_limbs(n, n, 2)
     M.mpgemm_dd(ctx, A, B, C1, algo="auto")
-    algo = {1: "simple", 2: "block", 3: "strassen"}[r["algo"]]
+    algo = {1: "simple", 2: "block", 3: "strassen", 4: "ozaki"}[r["algo"]]
     M.mpgemm_dd(ctx, A, B, C2, algo=algo, tile=r["tile"])
     torch.cuda.synchronize()
     assert torch.equal(C1[0], C2[0]) and torch.equal(C1[1], C2[1])
+
+
+def test_auto_follows_split_product_entry(gpu):
+    """A table entry naming the split-precision product (exact slices) makes
+    MPG_AUTO run it: bit-identical to the explicit call; QD rejects it."""
+    M, ctx = gpu
+    T = M.Tuner(ctx)
+    m, n, l = 130, 70, 200
+    T.table_set("dd", m, n, l, "ozaki", {"slices": 0})
+    A, B = M.to_device(inputs.dd_uniform(m, l, 4)), M.to_device(inputs.dd_uniform(l, n, 5))
+    C1, C2 = M.empty_like_limbs(m, n, 2), M.empty_like_limbs(m, n, 2)
+    M.mpgemm_dd(ctx, A, B, C1, algo="auto")
+    M.mpgemm_dd(ctx, A, B, C2, algo="ozaki", tile={"slices": 0})
+    torch.cuda.synchronize()
+    assert torch.equal(C1[0], C2[0]) and torch.equal(C1[1], C2[1])
+    with pytest.raises(M.MpgemmError):
+        T.table_set("qd", m, n, l, "ozaki", {"slices": 0})
+
+
+def test_split_product_candidate_timed(gpu):
+    """The DD candidate list ends with the split-precision product; the tuner
+    times it on its own DD buffers (full lower limbs)."""
+    M, ctx = gpu
+    T = M.Tuner(ctx)
+    n = 512
+    algo, tile = M.candidates("dd", n, n, n)[-1]
+    assert algo == M.MPG_OZAKI
+    ms = T.time("dd", n, n, n, algo, tile, reps=3)
+    # lower limbs ~2^-54 below the upper ones, 53 bits each: > 100 bits per entry
+    assert ms > 0 and M.ozaki_last_slices(ctx) >= 15
