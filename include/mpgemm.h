@@ -215,6 +215,29 @@ int mpg_ozaki_split(mpg_ctx* ctx, int side, int64_t rows, int64_t cols,
 /* Slice count used by the context's last mpgemm_ozaki_dd / mpgemm_dd_ozaki call. */
 int mpg_ozaki_last_slices(const mpg_ctx* ctx);
 
+/* Fewest slices whose a-priori truncation bound meets a target of `bits`:
+ * |C - AB|_ij <= l 2^(e_i + f_j) 2^-bits before the double-double rounding
+ * of the recombination (e_i, f_j the row and column scales above).  The
+ * bound per unit of l 2^(e_i + f_j) is 2^-7S (2 + 2^-7S) with all pairs
+ * (pairs_mode 0) and that plus sum over g = S+2..2S of
+ * (2S - g + 1) 127^2 2^-7g with the triangle (pairs_mode 1).  Host only.
+ * Returns 0 for bits < 1, a bad pairs_mode, or a target that 40 slices do
+ * not reach. */
+int mpg_ozaki_slices_for_bits(int bits, int pairs_mode);
+
+/* Slice count and pair set of the split-precision product of FP64 inputs
+ * for an accuracy target of `bits` (as for mpg_ozaki_slices_for_bits),
+ * chosen by measured time.  Candidates: the fewest slices meeting the
+ * target with all pairs, and with the triangle; when A and B (device, as
+ * for mpgemm_ozaki_dd) are given, the exact slice count of that data with
+ * all pairs replaces the first when it is smaller (its product is exact
+ * before the recombination).  Each candidate is timed at full size (median
+ * of 3 after a warm-up) on library buffers; the fastest is returned in
+ * *slices, *pairs_mode, *ms (ms nullable).  Synchronises the stream. */
+int mpg_ozaki_tune(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l, int bits,
+                   const double* A, int64_t lda, const double* B, int64_t ldb,
+                   int* slices, int* pairs_mode, double* ms);
+
 /* ---- tuner (Section 3) ------------------------------------------------ */
 
 typedef enum {

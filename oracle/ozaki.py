@@ -178,17 +178,32 @@ def ozaki_dd(A, B, S: int, mode: str = "all"):
     return (hi, lo), (N, E0)
 
 
-def apriori_bound(A: np.ndarray, B: np.ndarray, S: int, mode: str = "all"):
-    """Per-entry bound on |C_S - AB|_ij from the truncated slices: every
-    remainder is below 2^(e - 7S) in magnitude, so with all pairs
-    |C_S - AB| <= l 2^(e_i + f_j) 2^-7S (2 + 2^-7S); with the triangle the
-    dropped pairs add l 2^(e_i + f_j) sum_{g > S+1} #pairs_g 127^2 2^-7g."""
-    l = A.shape[1]
-    e, f = row_exponents(A), col_exponents(B)
-    base = l * np.ldexp(1.0, (e[:, None] + f[None, :]).astype(np.int64))
+def apriori_unit(S: int, mode: str = "all") -> float:
+    """Bound on |x y - (kept digit products)| for scaled x, y in (-1, 1):
+    the remainders after S digits are below 2^-7S, so with all pairs the
+    error is at most 2^-7S (2 + 2^-7S); the triangle drops, on each diagonal
+    g = S+2 .. 2S, #pairs_g products of at most 127^2 2^-7g each."""
     b = 2.0 ** (-7 * S) * (2 + 2.0 ** (-7 * S))
     if mode == "triangle":
         for g in range(S + 2, 2 * S + 1):
             cnt = sum(1 for s in range(1, S + 1) if 1 <= g - s <= S)
             b += cnt * 127 * 127 * 2.0 ** (-7 * g)
-    return base * b
+    return b
+
+
+def apriori_bound(A: np.ndarray, B: np.ndarray, S: int, mode: str = "all"):
+    """Per-entry bound on |C_S - AB|_ij from the truncated slices:
+    l 2^(e_i + f_j) times apriori_unit(S, mode)."""
+    l = A.shape[1]
+    e, f = row_exponents(A), col_exponents(B)
+    base = l * np.ldexp(1.0, (e[:, None] + f[None, :]).astype(np.int64))
+    return base * apriori_unit(S, mode)
+
+
+def slices_for_bits(bits: int, mode: str = "all", max_slices: int = 40) -> int:
+    """Fewest slices whose a-priori bound is at most 2^-bits (per unit of
+    l 2^(e_i + f_j)); 0 if even max_slices do not reach it."""
+    for S in range(1, max_slices + 1):
+        if apriori_unit(S, mode) <= 2.0 ** -bits:
+            return S
+    return 0

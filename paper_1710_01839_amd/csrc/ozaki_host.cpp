@@ -1,5 +1,6 @@
 // Host side of the split-precision (INT8 MFMA) double-double product.
 #include <climits>
+#include <cmath>
 #include <cstring>
 
 #include "capi_internal.hpp"
@@ -205,3 +206,28 @@ extern "C" int mpgemm_dd_ozaki(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
 }
 
 extern "C" int mpg_ozaki_last_slices(const mpg_ctx* c) { return c ? c->last_slices : 0; }
+
+namespace {
+
+// Bound on |x y - (kept digit products)| for x, y scaled into (-1, 1) and
+// cut into S truncated 7-bit digits: both remainders are below 2^-7S, which
+// gives 2^-7S (2 + 2^-7S) with all pairs; the triangle s + t <= S + 1 also
+// drops, on each diagonal g = S+2 .. 2S, 2S - g + 1 products of at most
+// 127^2 2^-7g.
+double unit_bound(int S, int pairs_mode) {
+  const double u = std::ldexp(1.0, -7 * S);
+  double b = u * (2.0 + u);
+  if (pairs_mode == 1)
+    for (int g = S + 2; g <= 2 * S; ++g)
+      b += (double)(2 * S - g + 1) * (127.0 * 127.0) * std::ldexp(1.0, -7 * g);
+  return b;
+}
+
+}  // namespace
+
+extern "C" int mpg_ozaki_slices_for_bits(int bits, int pairs_mode) {
+  if (bits < 1 || (pairs_mode != 0 && pairs_mode != 1)) return 0;
+  for (int S = 1; S <= ozaki_max_slices(); ++S)
+    if (unit_bound(S, pairs_mode) <= std::ldexp(1.0, -bits)) return S;
+  return 0;
+}

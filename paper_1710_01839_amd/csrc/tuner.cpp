@@ -134,9 +134,10 @@ int run(mpg_ctx* c, Scratch& s, int64_t rows, const Cand& cd) {
                          (mpg_algo)cd.algo, &cd.tile);
 }
 
-// Median of `reps` event-timed runs after one warm-up run.
-int time_rows(mpg_ctx* c, Scratch& s, int64_t rows, const Cand& cd, int reps, double* ms) {
-  int st = run(c, s, rows, cd);
+// Median of `reps` event-timed calls of fn() after one warm-up call.
+template <class F>
+int time_median(mpg_ctx* c, int reps, F&& fn, double* ms) {
+  int st = fn();
   if (st != MPG_OK) return st;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return mpg_fail(c, MPG_ERR_HIP, "hipEventCreate");
@@ -147,7 +148,7 @@ int time_rows(mpg_ctx* c, Scratch& s, int64_t rows, const Cand& cd, int reps, do
   std::vector<double> t;
   for (int r = 0; r < reps && st == MPG_OK; ++r) {
     (void)hipEventRecord(a, c->stream);
-    st = run(c, s, rows, cd);
+    st = fn();
     (void)hipEventRecord(b, c->stream);
     if (st != MPG_OK) break;
     hipError_t e = hipEventSynchronize(b);
@@ -162,6 +163,10 @@ int time_rows(mpg_ctx* c, Scratch& s, int64_t rows, const Cand& cd, int reps, do
   std::sort(t.begin(), t.end());
   *ms = t[t.size() / 2];
   return MPG_OK;
+}
+
+int time_rows(mpg_ctx* c, Scratch& s, int64_t rows, const Cand& cd, int reps, double* ms) {
+  return time_median(c, reps, [&] { return run(c, s, rows, cd); }, ms);
 }
 
 void db_append(mpg_ctx* c, int prec, int64_t m, int64_t n, int64_t l, const Cand& cd, double ms,
@@ -421,6 +426,47 @@ extern "C" int mpg_mlp_train_db(mpg_ctx* c, const char* path, int epochs, float 
   if (final_loss) *final_loss = losses.back();
   if (rows_used) *rows_used = (int)y.size();
   return MPG_OK;
+}
+
+extern "C" int mpg_ozaki_tune(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int bits,
+                              const double* A, int64_t lda, const double* B, int64_t ldb,
+                              int* slices, int* pairs_mode, double* ms) {
+  if (!c) return MPG_ERR_ARG;
+  if (m <= 0 || n <= 0 || l <= 0 || !slices || !pairs_mode || (!A) != (!B))
+    return mpg_fail(c, MPG_ERR_ARG, "bad split-product tuning request");
+  int s_all = mpg_ozaki_slices_for_bits(bits, 0), s_tri = mpg_ozaki_slices_for_bits(bits, 1);
+  if (s_all == 0 || s_tri == 0)
+    return mpg_fail(c, MPG_ERR_ARG, "no slice count reaches %d bits", bits);
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  if (A) {
+    int se = 0;
+    if ((st = mpg_ozaki_slices_exact(c, m, n, l, A, lda, B, ldb, &se)) != MPG_OK) return st;
+    s_all = std::min(s_all, std::max(se, 1));
+  }
+  Scratch sc;
+  if ((st = make_scratch(c, 2, m, n, l, sc)) != MPG_OK) return st;
+  const int cand[2][2] = {{s_all, 0}, {s_tri, 1}};
+  double best = INFINITY;
+  for (const auto& cd : cand) {
+    double t = 0.0;
+    st = time_median(c, 3, [&] {
+      return mpgemm_ozaki_dd(c, m, n, l, sc.A[0], l, sc.B[0], n, sc.C[0], sc.C[1], n, cd[0], cd[1]);
+    }, &t);
+    if (st != MPG_OK) break;
+    Cand z{};
+    z.algo = MPG_OZAKI;
+    z.tile.slices = cd[0];
+    db_append(c, 1, m, n, l, z, t, cd[1] ? "splittri" : "split");
+    if (t < best) {
+      best = t;
+      *slices = cd[0];
+      *pairs_mode = cd[1];
+    }
+  }
+  free_scratch(sc);
+  if (st == MPG_OK && ms) *ms = best;
+  return st;
 }
 
 bool mpg_table_lookup(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l, int* algo,

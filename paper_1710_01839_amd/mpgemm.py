@@ -81,6 +81,9 @@ _sig("mpgemm_ozaki_dd", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, 
 _sig("mpgemm_dd_ozaki", [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _ci, _ci])
 _sig("mpg_ozaki_slices_exact", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(_ci)])
 _sig("mpg_ozaki_split", [_vp, _ci, _i64, _i64, _vp, _i64, _ci, _vp, _i64, _i64, _vp])
+_sig("mpg_ozaki_slices_for_bits", [_ci, _ci])
+_sig("mpg_ozaki_tune", [_vp, _i64, _i64, _i64, _ci, _vp, _i64, _vp, _i64, ctypes.POINTER(ctypes.c_int),
+                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)])
 _sig("mpg_ozaki_last_slices", [_vp])
 _sig("mpgemm_dd_batched", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile)])
 _sig("mpg_batch_plan_create", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile),
@@ -280,6 +283,11 @@ def ozaki_last_slices(ctx: Context) -> int:
     return int(_lib.mpg_ozaki_last_slices(ctx.handle))
 
 
+def ozaki_slices_for_bits(bits: int, mode: str = "all") -> int:
+    """Fewest slices whose a-priori bound meets 2^-bits (0: unreachable)."""
+    return int(_lib.mpg_ozaki_slices_for_bits(int(bits), 1 if mode in ("triangle", 1) else 0))
+
+
 def ozaki_slices_exact(ctx: Context, A, B) -> int:
     m, l, lda = _mat(A, "A")
     _, n, ldb = _mat(B, "B")
@@ -440,6 +448,18 @@ class Tuner:
                                      ctypes.byref(ms), ctypes.byref(secs), ctypes.byref(trials)), "mpg_tune")
         return {"algo": a.value, "tile": t.as_dict(), "ms": ms.value, "seconds": secs.value,
                 "trials": trials.value}
+
+    def tune_slices(self, m, n, l, bits, A=None, B=None):
+        """Slice count and pair set of the FP64-input split product for a
+        target of `bits`, by measured time; A, B (device tensors) let the
+        exact slice count of the data compete."""
+        S, pm, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self.ctx.bind_stream()
+        lda = _mat(A, "A")[2] if A is not None else 0
+        ldb = _mat(B, "B")[2] if B is not None else 0
+        self.ctx.check(_lib.mpg_ozaki_tune(self.ctx.handle, m, n, l, int(bits), _ptr(A), lda, _ptr(B), ldb,
+                                           ctypes.byref(S), ctypes.byref(pm), ctypes.byref(ms)), "mpg_ozaki_tune")
+        return {"slices": S.value, "pairs": "triangle" if pm.value else "all", "ms": ms.value}
 
     def table_set(self, precision, m, n, l, algo, tile=None):
         """Put a choice into the table MPG_AUTO follows."""

@@ -71,3 +71,14 @@ def test_tuner_host_logic(lib):
     assert np.isclose(f[13], 0.3) and f[14] == 0
     g = M.mlp_features("dd", 256, 512, 1024, "ozaki", {"slices": 0})
     assert g[14] == 1 and g[3] == 1 and not g[5:8].any()
+
+
+def test_slices_for_bits_matches_oracle(lib):
+    """Host-side slice count for an accuracy target equals the oracle's
+    (fewest slices whose a-priori bound meets 2^-bits), both pair sets."""
+    from oracle import ozaki
+    from paper_1710_01839_amd import mpgemm as M
+    for mode in ("all", "triangle"):
+        for bits in range(1, 285):
+            assert M.ozaki_slices_for_bits(bits, mode) == ozaki.slices_for_bits(bits, mode), (bits, mode)
+    assert M.ozaki_slices_for_bits(0) == 0 and lib.mpg_ozaki_slices_for_bits(50, 2) == 0

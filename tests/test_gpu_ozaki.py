@@ -220,3 +220,38 @@ def test_dd_inputs_zero_lo_reduce_to_fp64_path(gpu, S):
     C2 = run_ddoz(M, ctx, (A, np.zeros_like(A)), (B, np.zeros_like(B)), S)
     assert M.ozaki_last_slices(ctx) == S1
     assert np.array_equal(C1[0], C2[0]) and np.array_equal(C1[1], C2[1])
+
+
+@pytest.mark.parametrize("bits", [40, 106])
+def test_slice_tuner_meets_target(gpu, bits):
+    """The slice count and pair set the tuner picks for a target of `bits`
+    meet |C - AB|_ij <= l 2^(e_i + f_j) 2^-bits (plus the DD rounding of the
+    recombination) against the exact product."""
+    M, ctx = gpu
+    m, n, l = 96, 80, 300
+    A, B = inputs.fp64_wide(m, l, 12), inputs.fp64_wide(l, n, 13)
+    r = M.Tuner(ctx).tune_slices(m, n, l, bits)
+    print("bits", bits, r)
+    assert r["slices"] == ozaki.slices_for_bits(bits, r["pairs"]) and r["ms"] > 0
+    C = run_oz(M, ctx, A, B, r["slices"], r["pairs"])
+    Ce = cref.gemm_exact((A,), (B,), out_limbs=2)
+    d = np.abs(cref.exact_diff(C, Ce))
+    e, f = ozaki.row_exponents(A), ozaki.col_exponents(B)
+    target = l * np.ldexp(1.0, (e[:, None] + f[None, :]).astype(np.int64)) * 2.0 ** -bits
+    assert np.all(d <= target * (1 + 2.0 ** -40) + np.abs(Ce[0]) * 2.0 ** -100)
+
+
+def test_slice_tuner_exact_count_competes(gpu):
+    """With the data given, the exact slice count (8 for uniform [-1, 1)
+    data) replaces the all-pairs count of a 106-bit target (16)."""
+    M, ctx = gpu
+    n = 512
+    A, B = inputs.dd_uniform(n, n, 3)[0], inputs.dd_uniform(n, n, 4)[0]
+    S_exact = ozaki.slices_exact(A, B)
+    r = M.Tuner(ctx).tune_slices(n, n, n, 106, torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda())
+    print("exact", S_exact, r)
+    assert (r["pairs"], r["slices"]) in {("all", S_exact), ("triangle", ozaki.slices_for_bits(106, "triangle"))}
+    with pytest.raises(M.MpgemmError):
+        M.Tuner(ctx).tune_slices(n, n, n, 0)
+    with pytest.raises(M.MpgemmError):
+        M.Tuner(ctx).tune_slices(n, n, n, 300)

@@ -138,3 +138,20 @@ def test_dd_exact_slices_give_exact_product():
     Ci, s = exact.matmul_exact(A, B)
     for idx in np.ndindex(hi.shape):
         assert ozaki.to_fraction(N, E0, idx) == Fraction(int(Ci[idx]), 2 ** s)
+
+
+@pytest.mark.parametrize("S", [2, 4, 7])
+def test_triangle_bound_term_is_attained(S):
+    """x = sum_{s<=S} 127 2^-7s (every digit 127, no remainder): the triangle
+    drops exactly the pairs s + t > S + 1, so the error of x*x equals the
+    dropped-diagonal term of the a-priori bound, pair count included."""
+    x = sum(Fraction(127, 128 ** s) for s in range(1, S + 1))
+    assert float(x) == x                       # 7S <= 49 bits: exact in binary64
+    A = np.array([[float(x)]])
+    (_, _), (N, E0) = ozaki.ozaki_dd(A, A.copy(), S, "triangle")
+    err = x * x - ozaki.to_fraction(N, E0, (0, 0))
+    dropped = sum(Fraction(127 * 127, 128 ** (s + t)) for s in range(1, S + 1)
+                  for t in range(1, S + 1) if s + t > S + 1)
+    assert err == dropped
+    term = ozaki.apriori_unit(S, "triangle") - ozaki.apriori_unit(S, "all")
+    assert abs(float(dropped) - term) <= 2.0 ** -50 * term
