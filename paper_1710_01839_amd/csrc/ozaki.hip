@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256, 1) void ozaki_mfma_kernel(OzakiGemmArgs a) {
 // per wave, and the L2 -> CU path (about 15 bytes per clock and CU) then
 // bounds it.
 // Here the load unit moves the workgroup's digit blocks of one K step
-// straight into LDS (global_load_lds, 16 bytes per lane, no registers),
+// straight into LDS (buffer loads to LDS, 16 bytes per lane, no registers),
 // double-buffered, and the four wavefronts read their fragments from LDS,
 // so each block crosses from L2 once per workgroup.  A block is 16 rows (or
 // columns) x 64 k of one slice, stored in MFMA lane order: lane l's 16 bytes
@@ -484,9 +484,25 @@ struct OzLdsShape {
 
 using lds_ptr = __attribute__((address_space(3))) void*;
 
+// Moves one 1 KiB digit block into LDS: lane l's 16 bytes at base + voff
+// land at dst + 16 l (base and dst uniform).  The buffer form of the LDS
+// load is used, not the flat/global one: with a flat load pending the
+// compiler cannot order LDS reads and makes every fragment read wait for
+// all outstanding ones (lgkmcnt(0)), which removes the read-ahead.  The
+// buffer builtins exist only for the device; the host pass sees an empty
+// body.
+__device__ __forceinline__ void oz_dma(const int8_t* base, uint32_t voff, int8_t* dst) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // raw buffer over `base`: num_records only has to exceed every offset used
+  const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(base), (short)0, 0x7ffffff0,
+                                                    0x00020000);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)dst, 16, (int)voff, 0, 0, 0);
+#endif
+}
+
 // Moves step `kn`'s digit blocks of the workgroup tile into `dst`: block
 // `blk` (A: slice blk / NBA, rows 16 (blk % NBA) ..; then B likewise) is one
-// global_load_lds per wavefront, wavefronts taking blocks round-robin.
+// LDS load per wavefront, wavefronts taking blocks round-robin.
 template <int S>
 __device__ __forceinline__ void oz_lds_issue(int8_t* __restrict__ dst, const OzakiGemmArgs& a,
                                              int64_t m0, int64_t n0, int kn, uint32_t lane_off,
@@ -500,12 +516,12 @@ __device__ __forceinline__ void oz_lds_issue(int8_t* __restrict__ dst, const Oza
       const int8_t* src;
       if (blk < S * NBA) {
         const int s = blk / NBA, b = blk % NBA;
-        src = a.A + s * a.planeA + (m0 + 16 * b) * a.l_pad + (int64_t)kn * 64;
+        src = a.A + s * a.planeA + (m0 + 16 * b) * a.l_pad;
       } else {
         const int t = (blk - S * NBA) / NBB, b = (blk - S * NBA) % NBB;
-        src = a.B + t * a.planeB + (n0 + 16 * b) * a.l_pad + (int64_t)kn * 64;
+        src = a.B + t * a.planeB + (n0 + 16 * b) * a.l_pad;
       }
-      __builtin_amdgcn_global_load_lds(src + lane_off, (lds_ptr)(dst + blk * 1024), 16, 0, 0);
+      oz_dma(src, lane_off + (uint32_t)kn * 64, dst + blk * 1024);
     }
   }
 }
@@ -523,13 +539,8 @@ __device__ __forceinline__ void oz_lds_step(int8_t* __restrict__ nxt, const int8
   constexpr int WM = Sh::WM, WN = Sh::WN, NBA = Sh::NBA, NBB = Sh::NBB;
   if (more) oz_lds_issue<S>(nxt, a, m0, n0, kn, lane_off, wave);
   const int wr = wave / 2, wc = wave % 2;
-  v4i fb[S][WN];
-#pragma unroll
-  for (int t = 0; t < S; ++t)
-#pragma unroll
-    for (int bj = 0; bj < WN; ++bj)
-      fb[t][bj] = *reinterpret_cast<const v4i*>(cur + (S * NBA + t * NBB + wc * WN + bj) * 1024 + 16 * lane);
-  // A fragments one slice ahead of the MFMAs that use them
+  // fragment reads in order of first use: A slice 0, the B slices, then
+  // each A slice one slice ahead of the MFMAs that use it
   v4i fa[2][WM];
   auto read_a = [&](int s2, v4i (&f)[WM]) {
 #pragma unroll
@@ -537,6 +548,12 @@ __device__ __forceinline__ void oz_lds_step(int8_t* __restrict__ nxt, const int8
       f[bi] = *reinterpret_cast<const v4i*>(cur + (s2 * NBA + wr * WM + bi) * 1024 + 16 * lane);
   };
   read_a(0, fa[0]);
+  v4i fb[S][WN];
+#pragma unroll
+  for (int t = 0; t < S; ++t)
+#pragma unroll
+    for (int bj = 0; bj < WN; ++bj)
+      fb[t][bj] = *reinterpret_cast<const v4i*>(cur + (S * NBA + t * NBB + wc * WN + bj) * 1024 + 16 * lane);
 #pragma unroll
   for (int s2 = 0; s2 < S; ++s2) {
     if (s2 + 1 < S) read_a(s2 + 1, fa[(s2 + 1) & 1]);
@@ -561,7 +578,9 @@ __global__ __launch_bounds__(256, 1) void ozaki_lds_kernel(OzakiGemmArgs a, int 
   constexpr int G = 2 * S - 1;
   constexpr int BM = Sh::BM, BN = Sh::BN, WM = Sh::WM, WN = Sh::WN, NBLK = Sh::BLOCKS;
   __shared__ __attribute__((aligned(16))) int8_t lds[2 * NBLK * 1024];
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  // the wave index is uniform; saying so keeps block addresses in scalar
+  // registers (a buffer resource must be)
+  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   int tm, tn;
   {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -679,8 +698,7 @@ __device__ __forceinline__ void oz_band_issue(int8_t* __restrict__ dst, const Oz
     const int blk = wave + 4 * i;
     if (blk < NBLK) {
       const int t = blk / WN, bj = blk % WN;
-      const int8_t* src = a.B + t * a.planeB + (n0 + 16 * bj) * a.l_pad + (int64_t)kn * 64;
-      __builtin_amdgcn_global_load_lds(src + lane_off, (lds_ptr)(dst + blk * 1024), 16, 0, 0);
+      oz_dma(a.B + t * a.planeB + (n0 + 16 * bj) * a.l_pad, lane_off + (uint32_t)kn * 64, dst + blk * 1024);
     }
   }
 }
@@ -706,20 +724,22 @@ __device__ __forceinline__ void oz_band_step(int8_t* __restrict__ nxt, const int
   };
 #pragma unroll
   for (int s0 = 0; s0 < S; s0 += SB) {
-    // B fragments one slice ahead of their MFMAs; the scheduling barrier
-    // keeps later slices' reads from being hoisted (registers)
-    v4i fb[2][WN];
+    // B fragments two slices ahead of their MFMAs (one slice's MFMAs,
+    // 4 WN of them, can be shorter than an LDS read); the scheduling
+    // barrier keeps later slices' reads from being hoisted (registers)
+    v4i fb[3][WN];
     read_b(0, fb[0]);
+    if (S > 1) read_b(1, fb[1]);
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-      if (t + 1 < S) read_b(t + 1, fb[(t + 1) & 1]);
+      if (t + 2 < S) read_b(t + 2, fb[(t + 2) % 3]);
 #pragma unroll
       for (int s2 = s0; s2 < s0 + SB && s2 < S; ++s2)
         if (!TRI || s2 + t <= S - 1)
 #pragma unroll
           for (int bj = 0; bj < WN; ++bj)
             acc[s2 + t][bj] =
-                __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s2], fb[t & 1][bj], acc[s2 + t][bj], 0, 0, 0);
+                __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s2], fb[t % 3][bj], acc[s2 + t][bj], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
@@ -735,7 +755,9 @@ __global__ __launch_bounds__(256, 1) void ozaki_band_kernel(OzakiGemmArgs a, int
                                                             int tiles_n, int kchunk) {
   constexpr int G = 2 * S - 1, NBLK = WN * S;
   __shared__ __attribute__((aligned(16))) int8_t lds[2 * NBLK * 1024];
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  // the wave index is uniform; saying so keeps block addresses in scalar
+  // registers (a buffer resource must be)
+  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   int tm, tn;
   {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
