@@ -468,19 +468,28 @@ __global__ __launch_bounds__(256, 1) void ozaki_mfma_kernel(OzakiGemmArgs a) {
 // columns) x 64 k of one slice, stored in MFMA lane order: lane l's 16 bytes
 // (row l % 16, k chunk l / 16) at byte 16 l, so both the load and the
 // fragment read are one contiguous 1 KiB per wavefront.
-// Workgroup tile 64 x 64, 2 x 2 waves of 2 x 2 blocks; the double-double
-// accumulators wait in C between K chunks.
+// Workgroup tile 64 x 64 over NW wavefronts: 2 x 2 waves of 2 x 2 blocks
+// (NW = 4, one wave per SIMD) or 2 x 4 waves of 2 x 1 blocks (NW = 8: two
+// waves per SIMD, so one issues MFMAs while the other waits for LDS reads or
+// the barrier); the double-double accumulators wait in C between K chunks.
 // ---------------------------------------------------------------------
 constexpr int kOzLdsMaxS = 8;
 
-template <int S>
+template <int S, int NW>
 struct OzLdsShape {
   static constexpr int BM = 64;
   static constexpr int BN = 64;
-  static constexpr int WM = BM / 32, WN = BN / 32;     // 16 x 16 blocks per wave
+  static constexpr int WAVES_M = 2, WAVES_N = NW / 2;
+  static constexpr int WM = BM / 16 / WAVES_M, WN = BN / 16 / WAVES_N;  // 16 x 16 blocks per wave
   static constexpr int NBA = BM / 16, NBB = BN / 16;   // blocks per slice and operand
   static constexpr int BLOCKS = S * (NBA + NBB);       // 1 KiB blocks per K step
 };
+
+// wavefronts per workgroup of the LDS-staged kernel
+template <int S>
+constexpr int oz_lds_waves() {
+  return 8;
+}
 
 using lds_ptr = __attribute__((address_space(3))) void*;
 
@@ -503,15 +512,15 @@ __device__ __forceinline__ void oz_dma(const int8_t* base, uint32_t voff, int8_t
 // Moves step `kn`'s digit blocks of the workgroup tile into `dst`: block
 // `blk` (A: slice blk / NBA, rows 16 (blk % NBA) ..; then B likewise) is one
 // LDS load per wavefront, wavefronts taking blocks round-robin.
-template <int S>
+template <int S, int NW>
 __device__ __forceinline__ void oz_lds_issue(int8_t* __restrict__ dst, const OzakiGemmArgs& a,
                                              int64_t m0, int64_t n0, int kn, uint32_t lane_off,
                                              int wave) {
-  using Sh = OzLdsShape<S>;
+  using Sh = OzLdsShape<S, NW>;
   constexpr int NBA = Sh::NBA, NBB = Sh::NBB, NBLK = Sh::BLOCKS;
 #pragma unroll
-  for (int i = 0; i < (NBLK + 3) / 4; ++i) {
-    const int blk = wave + 4 * i;
+  for (int i = 0; i < (NBLK + NW - 1) / NW; ++i) {
+    const int blk = wave + NW * i;
     if (blk < NBLK) {
       const int8_t* src;
       if (blk < S * NBA) {
@@ -530,15 +539,15 @@ __device__ __forceinline__ void oz_lds_issue(int8_t* __restrict__ dst, const Oza
 // then the MFMAs on the fragments in `cur`.  The two buffers are distinct
 // restrict pointers, so the compiler knows the fragment reads need not wait
 // for the loads into the other buffer.
-template <int S, bool TRI>
+template <int S, bool TRI, int NW>
 __device__ __forceinline__ void oz_lds_step(int8_t* __restrict__ nxt, const int8_t* __restrict__ cur,
                                             const OzakiGemmArgs& a, int64_t m0, int64_t n0, int kn,
                                             bool more, uint32_t lane_off, int lane, int wave,
-                                            v4i (&acc)[2 * S - 1][OzLdsShape<S>::WM][OzLdsShape<S>::WN]) {
-  using Sh = OzLdsShape<S>;
+                                            v4i (&acc)[2 * S - 1][OzLdsShape<S, NW>::WM][OzLdsShape<S, NW>::WN]) {
+  using Sh = OzLdsShape<S, NW>;
   constexpr int WM = Sh::WM, WN = Sh::WN, NBA = Sh::NBA, NBB = Sh::NBB;
-  if (more) oz_lds_issue<S>(nxt, a, m0, n0, kn, lane_off, wave);
-  const int wr = wave / 2, wc = wave % 2;
+  if (more) oz_lds_issue<S, NW>(nxt, a, m0, n0, kn, lane_off, wave);
+  const int wr = wave / Sh::WAVES_N, wc = wave % Sh::WAVES_N;
   // fragment reads in order of first use: A slice 0, the B slices, then
   // each A slice one slice ahead of the MFMAs that use it
   v4i fa[2][WM];
@@ -571,10 +580,10 @@ __device__ __forceinline__ void oz_lds_step(int8_t* __restrict__ nxt, const int8
   }
 }
 
-template <int S, bool TRI>
-__global__ __launch_bounds__(256, 1) void ozaki_lds_kernel(OzakiGemmArgs a, int tiles_m,
-                                                           int tiles_n, int kchunk) {
-  using Sh = OzLdsShape<S>;
+template <int S, bool TRI, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void ozaki_lds_kernel(OzakiGemmArgs a, int tiles_m,
+                                                               int tiles_n, int kchunk) {
+  using Sh = OzLdsShape<S, NW>;
   constexpr int G = 2 * S - 1;
   constexpr int BM = Sh::BM, BN = Sh::BN, WM = Sh::WM, WN = Sh::WN, NBLK = Sh::BLOCKS;
   __shared__ __attribute__((aligned(16))) int8_t lds[2 * NBLK * 1024];
@@ -594,7 +603,7 @@ __global__ __launch_bounds__(256, 1) void ozaki_lds_kernel(OzakiGemmArgs a, int 
     tn = in / gsize;
   }
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int64_t r0 = m0 + 16 * WM * (wave / 2), c0 = n0 + 16 * WN * (wave % 2);
+  const int64_t r0 = m0 + 16 * WM * (wave / Sh::WAVES_N), c0 = n0 + 16 * WN * (wave % Sh::WAVES_N);
   // this lane's row / column inside a block and its 16-byte k chunk
   const uint32_t lane_off = (uint32_t)((lane % 16) * a.l_pad + 16 * (lane / 16));
 
@@ -648,7 +657,7 @@ __global__ __launch_bounds__(256, 1) void ozaki_lds_kernel(OzakiGemmArgs a, int 
 
   const int numK = (int)(a.l_pad / 64);
   // step 0's blocks into buffer 0 (the issue half of a step, no MFMAs)
-  if (numK > 0) oz_lds_issue<S>(lds, a, m0, n0, 0, lane_off, wave);
+  if (numK > 0) oz_lds_issue<S, NW>(lds, a, m0, n0, 0, lane_off, wave);
   for (int kc = 0; kc < numK; kc += kchunk) {
     const int kend = min(numK, kc + kchunk);
     for (int kt = kc; kt < kend; ++kt) {
@@ -658,7 +667,7 @@ __global__ __launch_bounds__(256, 1) void ozaki_lds_kernel(OzakiGemmArgs a, int 
       // everyone's are, and nobody reads `nxt` any more
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       __syncthreads();
-      oz_lds_step<S, TRI>(nxt, cur, a, m0, n0, kt + 1, kt + 1 < numK, lane_off, lane, wave, acc);
+      oz_lds_step<S, TRI, NW>(nxt, cur, a, m0, n0, kt + 1, kt + 1 < numK, lane_off, lane, wave, acc);
     }
     flush(kc == 0, kend == numK);
   }
@@ -863,21 +872,25 @@ struct OzKernels {
   const void* tri[kOzBandMaxS + 1] = {};
   int tile_m[kOzBandMaxS + 1] = {};  // workgroup tile rows / columns
   int tile_n[kOzBandMaxS + 1] = {};
+  int threads[kOzBandMaxS + 1] = {};
   OzKernels() { OzTable<kOzBandMaxS>::fill(*this); }
 };
 
 template <int S>
 void OzTable<S>::fill(OzKernels& k) {
   if constexpr (S <= kOzLdsMaxS) {
-    k.all[S] = reinterpret_cast<const void*>(&ozaki_lds_kernel<S, false>);
-    k.tri[S] = reinterpret_cast<const void*>(&ozaki_lds_kernel<S, true>);
-    k.tile_m[S] = OzLdsShape<S>::BM;
-    k.tile_n[S] = OzLdsShape<S>::BN;
+    constexpr int NW = oz_lds_waves<S>();
+    k.all[S] = reinterpret_cast<const void*>(&ozaki_lds_kernel<S, false, NW>);
+    k.tri[S] = reinterpret_cast<const void*>(&ozaki_lds_kernel<S, true, NW>);
+    k.tile_m[S] = OzLdsShape<S, NW>::BM;
+    k.tile_n[S] = OzLdsShape<S, NW>::BN;
+    k.threads[S] = 64 * NW;
   } else {
     k.all[S] = reinterpret_cast<const void*>(&ozaki_band_kernel<S, oz_band_wn<S>(), false>);
     k.tri[S] = reinterpret_cast<const void*>(&ozaki_band_kernel<S, oz_band_wn<S>(), true>);
     k.tile_m[S] = 64;
     k.tile_n[S] = 16 * oz_band_wn<S>();
+    k.threads[S] = 256;
   }
   OzTable<S - 1>::fill(k);
 }
@@ -956,7 +969,7 @@ hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
     int tm = (int)tiles_m, tn = (int)tiles_n;
     void* kargs[] = {(void*)&args, (void*)&tm, (void*)&tn, (void*)&kchunk};
     return hipLaunchKernel(a.triangle ? table.tri[a.S] : table.all[a.S],
-                           dim3((unsigned)(tiles_m * tiles_n)), dim3(256), kargs, 0, s);
+                           dim3((unsigned)(tiles_m * tiles_n)), dim3(table.threads[a.S]), kargs, 0, s);
   }
   const int64_t tiles = ((a.m + kOzTile - 1) / kOzTile) * ((a.n + kOzTile - 1) / kOzTile);
   if (tiles <= 0) return hipSuccess;

@@ -92,7 +92,10 @@ def test_single_slice_integer_product_exact(gpu):
     assert np.array_equal(C[0], want.astype(float)) and not C[1].any()
 
 
-@pytest.mark.parametrize("S,mode", [(3, "all"), (7, "all"), (10, "triangle"), (13, "all")])
+# one case per kernel shape: LDS-staged (1..8), band with two column blocks
+# (9..20) and one (21..24), and the general kernel above 24, both pair sets
+@pytest.mark.parametrize("S,mode", [(1, "all"), (3, "all"), (7, "all"), (8, "triangle"), (10, "triangle"),
+                                    (13, "all"), (20, "all"), (24, "triangle"), (26, "all")])
 def test_matches_oracle_truncated_product(gpu, S, mode):
     M, ctx = gpu
     m, n, l = 77, 69, 150
