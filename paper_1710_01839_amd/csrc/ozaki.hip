@@ -715,15 +715,23 @@ __device__ __forceinline__ void oz_band_issue(int8_t* __restrict__ dst, const Oz
 // One K step on the B blocks in `cur` and the A fragments in fa (slice s
 // of this wave's rows, all resident); starts moving step kn's B blocks into
 // `nxt` and reloads each block of A slices for step kn right after its last
-// use (the last step re-reads its own, still valid, step).
+// use (the last step re-reads its own, still valid, step).  The last block
+// is the exception: reloaded at the end of a step, it would be waited for
+// at the step boundary; instead each step loads its own last block at its
+// start, a whole step before the MFMAs that use it.
 template <int S, int WN, bool TRI>
 __device__ __forceinline__ void oz_band_step(int8_t* __restrict__ nxt, const int8_t* __restrict__ cur,
                                              const OzakiGemmArgs& a, const int8_t* rowsA, int64_t n0,
                                              int kn, bool more, uint32_t lane_off, int lane, int wave,
                                              v4i (&fa)[S], v4i (&acc)[2 * S - 1][WN]) {
   constexpr int SB = 4;  // slices per block of the s loop
+  constexpr int LAST = (S - 1) / SB * SB;  // first slice of the last block
   if (more) oz_band_issue<S, WN>(nxt, a, n0, kn, lane_off, wave);
-  // the reloads below must not move above the B loads
+  // the loads below must not move above the B loads
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int s2 = LAST; s2 < S; ++s2)
+    fa[s2] = *reinterpret_cast<const v4i*>(rowsA + s2 * a.planeA + (int64_t)(kn - 1) * 64 + lane_off);
   __builtin_amdgcn_sched_barrier(0);
   const int kr = more ? kn : kn - 1;
   auto read_b = [&](int t, v4i (&f)[WN]) {
@@ -751,9 +759,11 @@ __device__ __forceinline__ void oz_band_step(int8_t* __restrict__ nxt, const int
                 __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s2], fb[t % 3][bj], acc[s2 + t][bj], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
+    if (s0 != LAST) {
 #pragma unroll
-    for (int s2 = s0; s2 < s0 + SB && s2 < S; ++s2)
-      fa[s2] = *reinterpret_cast<const v4i*>(rowsA + s2 * a.planeA + (int64_t)kr * 64 + lane_off);
+      for (int s2 = s0; s2 < s0 + SB; ++s2)
+        fa[s2] = *reinterpret_cast<const v4i*>(rowsA + s2 * a.planeA + (int64_t)kr * 64 + lane_off);
+    }
     // keeps the reloads of this block of slices after its MFMAs (registers)
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -835,8 +845,10 @@ __global__ __launch_bounds__(256, 1) void ozaki_band_kernel(OzakiGemmArgs a, int
   v4i fa[S];
   if (numK > 0) {
     oz_band_issue<S, WN>(lds, a, n0, 0, lane_off, wave);
+    // step 0's A slices but the last block (each step loads that itself)
 #pragma unroll
-    for (int q = 0; q < S; ++q) fa[q] = *reinterpret_cast<const v4i*>(rowsA + q * a.planeA + lane_off);
+    for (int q = 0; q < (S - 1) / 4 * 4; ++q)
+      fa[q] = *reinterpret_cast<const v4i*>(rowsA + q * a.planeA + lane_off);
   }
   for (int kc = 0; kc < numK; kc += kchunk) {
     const int kend = min(numK, kc + kchunk);
