@@ -131,7 +131,7 @@ def batch_shapes(count: int = 512, lo: int = 16, hi: int = 512, seed_offset: int
     return [tuple(int(v) for v in row) for row in np.rint(x).astype(np.int64)]
 
 
-def mlp_init(features: int = 14, hidden: int = 64, seed_offset: int = 11):
+def mlp_init(features: int = 15, hidden: int = 64, seed_offset: int = 11):
     """He-uniform float32 weights, zero biases, for features->hidden->hidden->1."""
     g = rng(seed_offset)
 
