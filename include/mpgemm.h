@@ -255,8 +255,9 @@ typedef enum {
  * MPG_STRASSEN with every tile and depth 1..3 (DD) / 1..2 (QD) while the
  * leaves keep at least 64 per side, and last, for DD, MPG_OZAKI with
  * slices = 0 (exact slice count, all pairs).  precision: 2 (DD) or 4 (QD).
- * The tuner times them on its own buffers: limb 0 uniform in [-1, 1), each
- * lower limb a uniform fraction of half an ulp of the limb above. */
+ * The tuner times them on its own buffers: limb 0 uniform in (-1, 1), each
+ * lower limb a uniform fraction of half an ulp of the limb above (the next
+ * 53 bits of a random significand). */
 int mpg_num_candidates(int precision, int64_t m, int64_t n, int64_t l);
 int mpg_candidate(int precision, int64_t m, int64_t n, int64_t l, int index,
                   int* algo, mpg_tile* tile);

@@ -65,10 +65,12 @@ std::vector<Cand> candidates(int prec, int64_t m, int64_t n, int64_t l) {
 }
 
 // Timing buffers for one shape: canonical multi-limb values, limb 0 in
-// [-1, 1), each lower limb below half an ulp of the limb above.  The FP64
-// kernels' run time does not depend on the values; the split-precision
-// product's does (its exact slice count follows the lowest set bits), and
-// full lower limbs give it the count that general DD data needs.
+// (-1, 1), each lower limb a uniform fraction of half an ulp of the limb
+// above on a fixed grid of 2^-52 of that half-ulp (the next bits of a
+// random significand).  The FP64 kernels' run time does not depend on the
+// values; the split-precision product's does (its exact slice count
+// follows the lowest set bits), and such limbs give it the count that
+// general DD data needs.
 struct Scratch {
   int limbs = 0;
   int64_t m = 0, n = 0, l = 0;
@@ -83,9 +85,15 @@ __global__ void fill_kernel(double* p, const double* above, int64_t n, uint64_t 
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
-    const double u = (double)(z >> 11) * 0x1.0p-52 - 1.0;  // [-1, 1)
-    // |above| 2^-54 |u| < 2^(e-53) = half an ulp of `above` when 2^e <= |above|
-    p[i] = above ? above[i] * 0x1.0p-54 * u : u;
+    double u = (double)(z >> 11) * 0x1.0p-52 - 1.0;  // [-1, 1), grid 2^-52
+    if (u == -1.0) u = 0.0;                            // (-1, 1): canonical pairs
+    if (!above) {
+      p[i] = u;
+    } else {
+      // half an ulp of x = 2^(ilogb x - 53)
+      const double x = above[i];
+      p[i] = x == 0.0 ? 0.0 : ldexp(u, ilogb(x) - 53);
+    }
   }
 }
 
