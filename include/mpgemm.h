@@ -161,36 +161,38 @@ int mpg_batch_plan_destroy(mpg_batch_plan* plan);
 /* C := A B to double-double accuracy from FP64 inputs A (m x l) and B
  * (l x n) through INT8 matrix cores (error-free splitting of Ozaki, Ogita,
  * Oishi and Rump; INT8 form of Ootomo, Ozaki and Yokota).  Each row of A is
- * scaled by 2^-e_i and each column of B by 2^-f_j into (-1, 1) (e_i the
- * smallest integer with max_k |a_ik| < 2^e_i) and cut by truncation into
- * `slices` digit planes of 7 bits (INT8 values in [-127, 127], exact); the
- * products of digit planes s and t are exact INT32 sums, grouped by
- * diagonal g = s + t, scaled by 2^(e_i + f_j - 7g) and added in
- * double-double.
- *   slices     1..40, or 0 = as many as make every digit expansion exact
- *              (found by a device scan; synchronises the stream).  With the
- *              exact count and pairs_mode 0 the only rounding is the
- *              double-double recombination, so the result meets the DD bound
- *              8 l 2^-104 (|A||B|)_ij.
+ * scaled by 2^-(e_i + 2) and each column of B by 2^-(f_j + 2) into
+ * (-1/4, 1/4) (e_i the smallest integer with max_k |a_ik| < 2^e_i) and cut
+ * into `slices` radix-256 digit planes of signed bytes: digits by
+ * truncation toward zero (exact), then a carry from the least significant
+ * digit up brings each into [-128, 127].  The products of digit planes s
+ * and t are exact INT32 sums, grouped by diagonal g = s + t, scaled by
+ * 2^(e_i + f_j + 4 - 8g) and added in double-double.
+ *   slices     1..40, or 0 = as many as make every digit expansion exact,
+ *              ceil((e_i + 2 - lowest set bit) / 8) over all rows and
+ *              columns (found by a device scan; synchronises the stream).
+ *              With the exact count and pairs_mode 0 the only rounding is
+ *              the double-double recombination, so the result meets the
+ *              DD bound 8 l 2^-104 (|A||B|)_ij.
  *   pairs_mode 0: all slices^2 digit-plane pairs; 1: only s + t <= slices + 1.
- * With fewer slices the truncation error is at most
- * l 2^(e_i + f_j) 2^(-7 slices)(2 + 2^(-7 slices)) per entry (pairs_mode 0).
- * Requires l <= 33280 (INT32 headroom).  C_hi/C_lo must not overlap A, B. */
+ * With fewer slices the truncation error is below
+ * l 2^(e_i + f_j) 2^(3 - 8 slices) per entry (pairs_mode 0).
+ * Requires l <= 32704 (INT32 headroom).  C_hi/C_lo must not overlap A, B. */
 int mpgemm_ozaki_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
                     const double* A, int64_t lda, const double* B, int64_t ldb,
                     double* C_hi, double* C_lo, int64_t ldc, int slices, int pairs_mode);
 
 /* C := A B for double-double inputs (A_hi + A_lo, B_hi + B_lo) through the
  * same INT8 path.  Each element's two limbs are split together as one
- * exact value: the scaled remainder is kept as a renormalised pair (a
- * TwoSum after each multiplication by 128), the digit is the truncation of
- * its leading part.  The scales e_i, f_j come from the hi limbs; the exact
- * slice count (slices = 0) covers the lowest set bit of either limb, so the
- * result is the exact product of the limb sums up to the double-double
- * recombination (inside the DD bound 8 l 2^-104 (|A||B|)_ij).  Arguments,
- * limits and errors as for mpgemm_ozaki_dd; the lo limbs share the leading
- * dimension of their hi limbs.  mpgemm_dd with MPG_OZAKI calls this with
- * tile->slices and pairs_mode 0. */
+ * exact value: the scaled remainder is kept as a renormalised pair and
+ * each digit is the truncation toward zero of its exact value.  The scales
+ * e_i, f_j come from the hi limbs; the exact slice count (slices = 0)
+ * covers the lowest set bit of either limb, so the result is the exact
+ * product of the limb sums up to the double-double recombination (inside
+ * the DD bound 8 l 2^-104 (|A||B|)_ij).  Arguments, limits and errors as
+ * for mpgemm_ozaki_dd; the lo limbs share the leading dimension of their
+ * hi limbs.  mpgemm_dd with MPG_OZAKI calls this with tile->slices and
+ * pairs_mode 0. */
 int mpgemm_dd_ozaki(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
                     const double* A_hi, const double* A_lo, int64_t lda,
                     const double* B_hi, const double* B_lo, int64_t ldb,
@@ -206,8 +208,9 @@ int mpg_ozaki_slices_exact(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
  * exps[rows] and digit planes out[s][r][k]; side 1: columns of X get
  * exps[cols] and planes out[s][c][k] (transposed, K contiguous).  Lines are
  * padded to a multiple of 64 and K to a multiple of 64 with zero digits:
- * ld_out >= round64(K) (a multiple of 8) and plane >= round64(lines) *
- * ld_out bytes.  out and exps are device buffers owned by the caller. */
+ * ld_out >= round64(K) and plane >= round64(lines) * ld_out bytes, both
+ * multiples of 8, out 8-byte aligned.  out and exps are device buffers
+ * owned by the caller. */
 int mpg_ozaki_split(mpg_ctx* ctx, int side, int64_t rows, int64_t cols,
                     const double* X, int64_t ldx, int slices,
                     int8_t* out, int64_t ld_out, int64_t plane, int32_t* exps);
@@ -218,11 +221,11 @@ int mpg_ozaki_last_slices(const mpg_ctx* ctx);
 /* Fewest slices whose a-priori truncation bound meets a target of `bits`:
  * |C - AB|_ij <= l 2^(e_i + f_j) 2^-bits before the double-double rounding
  * of the recombination (e_i, f_j the row and column scales above).  The
- * bound per unit of l 2^(e_i + f_j) is 2^-7S (2 + 2^-7S) with all pairs
+ * bound per unit of l 2^(e_i + f_j) is 2^(3 - 8S) with all pairs
  * (pairs_mode 0) and that plus sum over g = S+2..2S of
- * (2S - g + 1) 127^2 2^-7g with the triangle (pairs_mode 1).  Host only.
- * Returns 0 for bits < 1, a bad pairs_mode, or a target that 40 slices do
- * not reach. */
+ * (2S - g + 1) 128^2 2^(4 - 8g) with the triangle (pairs_mode 1).  Host
+ * only.  Returns 0 for bits < 1, a bad pairs_mode, or a target that 40
+ * slices do not reach. */
 int mpg_ozaki_slices_for_bits(int bits, int pairs_mode);
 
 /* Slice count and pair set of the split-precision product of FP64 inputs

@@ -4,23 +4,30 @@ TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark CPU baseline).
 
 The method (Ozaki, Ogita, Oishi and Rump's error-free splitting, in the
 INT8 form of Ootomo, Ozaki and Yokota) reaches double-double accuracy from
-products of small integers:
+products of small integers.  The digits here are radix-256 signed bytes:
 
 1. row scale e_i: the smallest integer with max_k |a_ik| < 2^e_i (0 for a
    zero row); column scale f_j of B likewise;
-2. x = a_ik 2^-e_i lies in (-1, 1); its digits are taken by truncation,
-   y_0 = x, y_s = 128 y_{s-1} - D_s with D_s = trunc(128 y_{s-1}) in
-   [-127, 127] -- every step exact in binary64 -- so
-   a_ik = 2^e_i (sum_s D_s 2^-7s + 2^-7S y_S);
-3. for each kept pair of digit planes (s, t) the integer product
+2. y = a_ik 2^-(e_i + 2) lies in (-1/4, 1/4); digits by truncation toward
+   zero, T_1 = trunc(256 y) in [-63, 63], r_1 = 256 y - T_1,
+   T_s = trunc(256 r_{s-1}) in [-255, 255], r_s = 256 r_{s-1} - T_s (every
+   r_s has the sign of y and |r_s| < 1; each step is exact in binary64), so
+   y = sum_s T_s 256^-s + 256^-S r_S;
+3. the kept digits are made signed bytes by a carry from the least
+   significant up: with c = 0, for s = S .. 2: u = T_s + c,
+   c = [u >= 128] - [u < -128], D_s = u - 256 c; D_1 = T_1 + c in [-64, 64].
+   The sum of the kept digits is unchanged; every D_s is in [-128, 127];
+4. for each kept pair of digit planes (s, t) the integer product
    D_A^(s) D_B^(t) is exact; pairs on one diagonal g = s + t share the
-   weight 2^(e_i + f_j - 7g);
-4. C_ij = sum_g 2^(e_i + f_j - 7g) G_g[i, j].
+   weight 2^(e_i + f_j + 4 - 8g);
+5. C_ij = sum_g 2^(e_i + f_j + 4 - 8g) G_g[i, j].
 
-Double-double inputs (hi + lo) are split as one exact value: with the
-exact remainder r_0 = (hi + lo) 2^-e_i, D_s = trunc(RN(128 r_{s-1})) and
-r_s = 128 r_{s-1} - D_s, RN the rounding of the exact value to binary64
-(for lo = 0 this is step 2 again); the scale e_i comes from the hi limbs.
+Every element whose lowest set bit is at or above 2^(e_i + 2 - 8S) is held
+exactly by S digits: S = ceil((e_i + 2 - lowest bit) / 8).
+
+Double-double inputs (hi + lo) are split as one exact value (steps 2-3 on
+the exact y = (hi + lo) 2^-(e_i + 2)); the scale e_i comes from the hi
+limbs.
 
 Pairs kept: all S^2 ('all') or the triangle s + t <= S + 1 ('triangle').
 This module forms the digit planes exactly, the diagonal sums with int64
@@ -46,17 +53,34 @@ def col_exponents(B: np.ndarray) -> np.ndarray:
     return row_exponents(np.ascontiguousarray(B.T))
 
 
+def signed_bytes(T):
+    """Step 3: truncated digits T (list of int64 arrays, most significant
+    first) -> signed-byte digits with the same sum, carrying from the least
+    significant digit up."""
+    D = [np.array(x, dtype=np.int64) for x in T]
+    c = np.zeros_like(D[0]) if D else None
+    for s in range(len(D) - 1, 0, -1):
+        u = D[s] + c
+        c = (u >= 128).astype(np.int64) - (u < -128).astype(np.int64)
+        D[s] = u - 256 * c
+    if D:
+        D[0] = D[0] + c
+    return [x.astype(np.int8) for x in D]
+
+
 def split_rows(X: np.ndarray, e: np.ndarray, S: int):
-    """Digit planes (S arrays of int8, same shape as X) of X scaled by 2^-e_i
-    per row, and the scaled remainder y_S."""
-    y = np.ldexp(X, -e[:, None])
-    digits = []
+    """Digit planes (S arrays of int8, same shape as X) of X scaled by
+    2^-(e_i + 2) per row, and the scaled remainder r_S (|r_S| < 1, units of
+    the last digit, the sign of x).  Multiplying by 256 and removing the
+    integer part toward zero are exact in binary64."""
+    y = np.ldexp(X, -(e[:, None] + 2))
+    T = []
     for _ in range(S):
-        y = y * 128.0
-        d = np.trunc(y)
-        y = y - d
-        digits.append(d.astype(np.int8))
-    return digits, y
+        v = y * 256.0
+        t = np.trunc(v)
+        y = v - t
+        T.append(t.astype(np.int64))
+    return signed_bytes(T), y
 
 
 def split_cols(X: np.ndarray, f: np.ndarray, S: int):
@@ -65,24 +89,24 @@ def split_cols(X: np.ndarray, f: np.ndarray, S: int):
 
 
 def split_rows_dd(Xhi: np.ndarray, Xlo: np.ndarray, e: np.ndarray, S: int):
-    """Digit planes of the double-double values hi + lo scaled by 2^-e_i per
-    row: D_s = trunc(RN(128 r_{s-1})), r_s = 128 r_{s-1} - D_s from the exact
-    r_0 = (hi + lo) 2^-e_i, in exact rational arithmetic (small inputs only).
-    Returns the planes and the exact remainders r_S (object array)."""
+    """Digit planes of the double-double values hi + lo scaled by
+    2^-(e_i + 2) per row, steps 2-3 in exact rational arithmetic (small
+    inputs only).  Returns the planes and the exact remainders r_S (object
+    array)."""
     R, K = Xhi.shape
-    D = [np.zeros((R, K), dtype=np.int8) for _ in range(S)]
+    T = [np.zeros((R, K), dtype=np.int64) for _ in range(S)]
     rem = np.empty((R, K), dtype=object)
     for i in range(R):
-        scale = Fraction(2) ** int(-e[i])
+        scale = Fraction(2) ** int(-(e[i] + 2))
         for k in range(K):
             r = (Fraction(float(Xhi[i, k])) + Fraction(float(Xlo[i, k]))) * scale
             for s in range(S):
-                v = 128 * r
-                d = int(float(v))      # float() rounds to nearest, int() truncates
-                D[s][i, k] = d
+                v = 256 * r
+                d = int(v)             # toward zero
+                T[s][i, k] = d
                 r = v - d
             rem[i, k] = r
-    return D, rem
+    return signed_bytes(T), rem
 
 
 def split_cols_dd(Xhi: np.ndarray, Xlo: np.ndarray, f: np.ndarray, S: int):
@@ -92,7 +116,7 @@ def split_cols_dd(Xhi: np.ndarray, Xlo: np.ndarray, f: np.ndarray, S: int):
 
 def slices_needed_rows(X: np.ndarray, e: np.ndarray) -> int:
     """Smallest S for which split_rows reproduces every entry exactly:
-    ceil((e_i - exponent of the lowest set bit of x) / 7), maximised."""
+    ceil((e_i + 2 - exponent of the lowest set bit of x) / 8), maximised."""
     M, E = exact._mant_exp(X)
     nz = M != 0
     if not nz.any():
@@ -103,8 +127,8 @@ def slices_needed_rows(X: np.ndarray, e: np.ndarray) -> int:
         tz += ((Mabs >> b) & 1 == 0) & (tz == b)
     low = E[nz] + tz                           # x = odd * 2^low
     eb = np.broadcast_to(e[:, None], X.shape)[nz]
-    bits = eb - low
-    return int(max(0, np.ceil(bits.max() / 7)))
+    bits = eb + 2 - low
+    return int(max(0, np.ceil(bits.max() / 8)))
 
 
 def slices_exact(A, B) -> int:
@@ -139,15 +163,15 @@ def group_sums(DA, DB, S: int, mode: str = "all"):
 
 
 def combine_exact(G, e: np.ndarray, f: np.ndarray):
-    """Exact C_ij = sum_g 2^(e_i + f_j - 7 g) G_g[i, j], returned as an
+    """Exact C_ij = sum_g 2^(e_i + f_j + 4 - 8 g) G_g[i, j], returned as an
     object array of integers N and the exponent E0 with C = N 2^E0, where
-    the common exponent is per entry: E0_ij = e_i + f_j - 7 gmax."""
+    the common exponent is per entry: E0_ij = e_i + f_j + 4 - 8 gmax."""
     gmax = max(G)
     N = None
     for g, Gg in G.items():
-        term = Gg.astype(object) * (1 << (7 * (gmax - g)))
+        term = Gg.astype(object) * (1 << (8 * (gmax - g)))
         N = term if N is None else N + term
-    E0 = (e[:, None] + f[None, :] - 7 * gmax).astype(np.int64)
+    E0 = (e[:, None] + f[None, :] + 4 - 8 * gmax).astype(np.int64)
     return N, E0
 
 
@@ -179,15 +203,17 @@ def ozaki_dd(A, B, S: int, mode: str = "all"):
 
 
 def apriori_unit(S: int, mode: str = "all") -> float:
-    """Bound on |x y - (kept digit products)| for scaled x, y in (-1, 1):
-    the remainders after S digits are below 2^-7S, so with all pairs the
-    error is at most 2^-7S (2 + 2^-7S); the triangle drops, on each diagonal
-    g = S+2 .. 2S, #pairs_g products of at most 127^2 2^-7g each."""
-    b = 2.0 ** (-7 * S) * (2 + 2.0 ** (-7 * S))
+    """Bound on |a b - (kept digit products)|, in units of 2^(e_i + f_j), for
+    |a| < 2^e_i, |b| < 2^f_j cut into S digits: each remainder is below
+    2^(e + 2 - 8S) and each kept part, a truncation, is below 2^e, so with
+    all pairs the error is below 2^(3 - 8S); the triangle also drops, on
+    each diagonal g = S+2 .. 2S, #pairs_g products of at most
+    128^2 2^(4 - 8g) each."""
+    b = 2.0 ** (3 - 8 * S)
     if mode == "triangle":
         for g in range(S + 2, 2 * S + 1):
             cnt = sum(1 for s in range(1, S + 1) if 1 <= g - s <= S)
-            b += cnt * 127 * 127 * 2.0 ** (-7 * g)
+            b += cnt * 128 * 128 * 2.0 ** (4 - 8 * g)
     return b
 
 

@@ -1,11 +1,13 @@
 // Split-precision double-double product on INT8 MFMA (gfx950).
 //
-// FP64 inputs are scaled per row of A (2^-e_i) and per column of B
-// (2^-f_j) into (-1, 1) and cut by truncation into S exact 7-bit digit
-// planes (INT8, values in [-127, 127]).  Products of digit planes run on
-// v_mfma_i32_16x16x64_i8 with exact INT32 sums; the sums of one diagonal
-// g = s + t of the (s, t) pair grid share the weight 2^(e_i + f_j - 7g) and
-// are added, scaled exactly, into double-double accumulators.
+// FP64 inputs are scaled per row of A (2^-(e_i + 2)) and per column of B
+// (2^-(f_j + 2)) into (-1/4, 1/4) and cut into S exact radix-256 digit
+// planes of signed bytes (digits by truncation toward zero, then a carry
+// from the least significant digit up that brings every digit into
+// [-128, 127]).  Products of digit planes run on v_mfma_i32_16x16x64_i8
+// with exact INT32 sums; the sums of one diagonal g = s + t of the (s, t)
+// pair grid share the weight 2^(e_i + f_j + 4 - 8g) and are added, scaled
+// exactly, into double-double accumulators.
 #include <climits>
 
 #include "mp_arith.hpp"
@@ -59,11 +61,11 @@ __device__ __forceinline__ int wave_min_int(int v) {
   return v;
 }
 
-// Digits of 7 bits that hold every element of a line exactly once it is
-// scaled by 2^-e: ceil((e - lowest set bit) / 7).
+// Radix-256 digits that hold every element of a line exactly once it is
+// scaled by 2^-(e + 2): ceil((e + 2 - lowest set bit) / 8).
 __device__ __forceinline__ int line_digits(int e, int low) {
-  const int d = e - low;
-  return d > 0 ? (d + 6) / 7 : 0;
+  const int d = e + 2 - low;
+  return d > 0 ? (d + 7) / 8 : 0;
 }
 
 // Rows of X (R x K): one workgroup per row writes e[r] = 1 + max ilogb over
@@ -186,12 +188,55 @@ __global__ __launch_bounds__(256) void col_finish_kernel(int* top_e, const int* 
 // ---------------------------------------------------------------------
 // digit slicing
 // ---------------------------------------------------------------------
+// One digit of the remainder r = (y, yl): t = trunc(256 r) toward zero, in
+// [-255, 255], and r becomes 256 r - t (same sign as the element, |r| < 1).
+// FP64: multiplying by 256 and removing the integer part are exact.  DD: r
+// is a renormalised pair, so 256 r is one too; its truncation is that of
+// the leading part unless the leading part is an integer and the trailing
+// part pulls toward zero (then one less in magnitude); the new remainder
+// is renormalised by an exact TwoSum.
+template <bool DD>
+__device__ __forceinline__ int digit_step(double& y, double& yl) {
+  const double sh = y * 256.0;
+  if (!DD) {
+    const double t = trunc(sh);
+    y = sh - t;
+    return (int)t;
+  }
+  const double sl = yl * 256.0;
+  double t = trunc(sh);
+  if (t == sh && sh != 0.0 && sl != 0.0 && ((sl < 0.0) != (sh < 0.0))) t -= sh > 0.0 ? 1.0 : -1.0;
+  two_sum(sh - t, sl, y, yl);
+  return (int)t;
+}
+
+// The carry that turns truncated digits into signed bytes, on one 8-byte
+// word of a plane (8 elements): `word` holds the digits t mod 256 (their
+// signs are the elements', bit q of `neg`), `c` the carries from the plane
+// below (in: carries into this plane; out: carries into the plane above).
+// The top plane (top = true) takes the carry and keeps no new one.
+__device__ __forceinline__ unsigned long long carry_word(unsigned long long word, unsigned neg, int (&c)[8],
+                                                         bool top) {
+  unsigned long long o = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int b = (int)((word >> (8 * q)) & 0xFF);
+    int u = ((neg >> q) & 1) && b != 0 ? b - 256 : b;
+    u += c[q];
+    if (!top) {
+      c[q] = (u >= 128) - (u < -128);
+      u -= 256 * c[q];
+    }
+    o |= (unsigned long long)(uint8_t)(int8_t)u << (8 * q);
+  }
+  return o;
+}
+
 // Rows of X (R x K) -> planes out[s][r][k] (r < Rp, k < Kp, zero padded).
-// Each thread handles 8 consecutive k of one row and writes 8 bytes per
-// plane.  With DD the value is X + Xlo, split as one exact value: the
-// scaled remainder is kept as a renormalised pair (TwoSum after each
-// multiplication by 128, both exact), the digit is the truncation of its
-// leading part, and subtracting the digit from that part is exact.
+// Each thread handles 8 consecutive k of one row: it writes the truncated
+// digits of each plane (8 bytes per plane, top plane first), then reads
+// its words back from the lowest plane up and applies the carry.  With DD
+// the value is X + Xlo, split as one exact value.
 template <bool DD>
 __global__ __launch_bounds__(256) void split_rows_kernel(const double* X, const double* Xlo, int64_t R,
                                                          int64_t K, int64_t ld, const int* e, int S,
@@ -203,38 +248,35 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const double* X, const 
   const int64_t r = idx / per_row, k0 = (idx % per_row) * 8;
   double y[8], yl[8];
   const int er = r < R ? e[r] : 0;
+  unsigned neg = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int64_t k = k0 + q;
     const bool ok = r < R && k < K;
-    y[q] = ldexp(ok ? X[r * ld + k] : 0.0, -er);
-    yl[q] = DD ? ldexp(ok ? Xlo[r * ld + k] : 0.0, -er) : 0.0;
+    y[q] = ldexp(ok ? X[r * ld + k] : 0.0, -(er + 2));
+    yl[q] = 0.0;
+    if (DD) two_sum(y[q], ldexp(ok ? Xlo[r * ld + k] : 0.0, -(er + 2)), y[q], yl[q]);
+    neg |= (unsigned)(y[q] < 0.0) << q;
   }
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(out + r * ld_out + k0);
   for (int s = 0; s < S; ++s) {
     unsigned long long word = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      if (DD) {
-        double sh, sl;
-        two_sum(y[q] * 128.0, yl[q] * 128.0, sh, sl);
-        y[q] = sh;
-        yl[q] = sl;
-      } else {
-        y[q] = y[q] * 128.0;
-      }
-      const double d = trunc(y[q]);
-      y[q] = y[q] - d;
-      word |= (unsigned long long)(uint8_t)(int8_t)(int)d << (8 * q);
-    }
-    *reinterpret_cast<unsigned long long*>(out + s * plane + r * ld_out + k0) = word;
+    for (int q = 0; q < 8; ++q)
+      word |= (unsigned long long)(uint8_t)digit_step<DD>(y[q], yl[q]) << (8 * q);
+    w[s * plane / 8] = word;
   }
+  int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int s = S - 1; s >= 0; --s) w[s * plane / 8] = carry_word(w[s * plane / 8], neg, c, s == 0);
 }
 
 // Columns of X (K x C, row-major) -> planes out[s][c][k] (transposed, c < Cp,
 // k < Kp, zero padded).  A 32 (k) x 64 (c) tile is read coalesced along c
 // (each thread keeps 8 remainders in registers); for each digit plane the
-// digits pass through LDS and are written back as 8-byte runs along k.
-// DD as in split_rows_kernel.
+// digits pass through LDS and are written back as 8-byte runs along k; the
+// thread that wrote a run applies the carry to it afterwards, lowest plane
+// first (the elements' signs pass through LDS once).  DD as in
+// split_rows_kernel.
 constexpr int kColTileK = 32;
 constexpr int kMaxSlices = 40;
 template <bool DD>
@@ -242,7 +284,8 @@ __global__ __launch_bounds__(256) void split_cols_kernel(const double* X, const 
                                                          int64_t C, int64_t ld, const int* f, int S,
                                                          int8_t* out, int64_t ld_out,
                                                          int64_t plane, int64_t Cp, int64_t Kp) {
-  __shared__ int8_t dig[64][kColTileK + 8];
+  __shared__ uint8_t dig[64][kColTileK + 8];
+  __shared__ uint8_t negs[64][kColTileK + 8];
   const int64_t c0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * kColTileK;
   const int tc = threadIdx.x % 64, tk = threadIdx.x / 64;  // 64 columns x 4
   const int64_t c = c0 + tc;
@@ -252,33 +295,30 @@ __global__ __launch_bounds__(256) void split_cols_kernel(const double* X, const 
   for (int q = 0; q < kColTileK / 4; ++q) {
     const int64_t k = k0 + tk + 4 * q;
     const bool ok = c < C && k < K;
-    y[q] = ldexp(ok ? X[k * ld + c] : 0.0, -fc);
-    yl[q] = DD ? ldexp(ok ? Xlo[k * ld + c] : 0.0, -fc) : 0.0;
+    y[q] = ldexp(ok ? X[k * ld + c] : 0.0, -(fc + 2));
+    yl[q] = 0.0;
+    if (DD) two_sum(y[q], ldexp(ok ? Xlo[k * ld + c] : 0.0, -(fc + 2)), y[q], yl[q]);
+    negs[tc][tk + 4 * q] = y[q] < 0.0;
   }
   const int wc = threadIdx.x / 4, wk = (threadIdx.x % 4) * 8;
   const int64_t cc = c0 + wc;
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(out + cc * ld_out + k0 + wk);
   for (int s = 0; s < S; ++s) {
 #pragma unroll
-    for (int q = 0; q < kColTileK / 4; ++q) {
-      if (DD) {
-        double sh, sl;
-        two_sum(y[q] * 128.0, yl[q] * 128.0, sh, sl);
-        y[q] = sh;
-        yl[q] = sl;
-      } else {
-        y[q] = y[q] * 128.0;
-      }
-      const double d = trunc(y[q]);
-      y[q] = y[q] - d;
-      dig[tc][tk + 4 * q] = (int8_t)(int)d;
-    }
+    for (int q = 0; q < kColTileK / 4; ++q) dig[tc][tk + 4 * q] = (uint8_t)digit_step<DD>(y[q], yl[q]);
     __syncthreads();
     unsigned long long word = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) word |= (unsigned long long)(uint8_t)dig[wc][wk + q] << (8 * q);
-    if (cc < Cp)
-      *reinterpret_cast<unsigned long long*>(out + s * plane + cc * ld_out + k0 + wk) = word;
+    for (int q = 0; q < 8; ++q) word |= (unsigned long long)dig[wc][wk + q] << (8 * q);
+    if (cc < Cp) w[s * plane / 8] = word;
     __syncthreads();
+  }
+  if (cc < Cp) {
+    unsigned neg = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) neg |= (unsigned)negs[wc][wk + q] << q;
+    int cy[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = S - 1; s >= 0; --s) w[s * plane / 8] = carry_word(w[s * plane / 8], neg, cy, s == 0);
   }
 }
 
@@ -428,7 +468,7 @@ __global__ __launch_bounds__(256, 1) void ozaki_mfma_kernel(OzakiGemmArgs a) {
             for (int i = 0; i < 4; ++i) {
               const int v = acc[gl][rb][cb][i];
               if (v == 0) continue;
-              const double x = ldexp((double)v, erow[rb][i] + fcol[cb] - 7 * g);
+              const double x = ldexp((double)v, erow[rb][i] + fcol[cb] + 4 - 8 * g);
               double s, err;
               two_sum(hi[rb][cb][i], x, s, err);
               hi[rb][cb][i] = s;
@@ -637,7 +677,7 @@ __global__ __launch_bounds__(64 * NW, 1) void ozaki_lds_kernel(OzakiGemmArgs a, 
           }
 #pragma unroll
           for (int g = G - 1; g >= 0; --g) {
-            const double x = ldexp((double)acc[g][bi][bj][i], erow + fcol - 7 * (g + 2));
+            const double x = ldexp((double)acc[g][bi][bj][i], erow + fcol + 4 - 8 * (g + 2));
             double sum, err;
             two_sum(hi, x, sum, err);
             hi = sum;
@@ -824,7 +864,7 @@ __global__ __launch_bounds__(256, 1) void ozaki_band_kernel(OzakiGemmArgs a, int
         }
 #pragma unroll
         for (int g = G - 1; g >= 0; --g) {
-          const double x = ldexp((double)acc[g][bj][i], erow[i] + fcol - 7 * (g + 2));
+          const double x = ldexp((double)acc[g][bj][i], erow[i] + fcol + 4 - 8 * (g + 2));
           double sum, err;
           two_sum(hi, x, sum, err);
           hi = sum;
@@ -974,8 +1014,8 @@ hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
     static const OzKernels table;
     const int tm_rows = table.tile_m[a.S], tn_cols = table.tile_n[a.S];
     const int64_t tiles_m = (a.m + tm_rows - 1) / tm_rows, tiles_n = (a.n + tn_cols - 1) / tn_cols;
-    // diagonal sums: at most S pairs of 64 k per K step, each |d d'| <= 127^2
-    const double per_step = (double)a.S * 64.0 * 127.0 * 127.0;
+    // diagonal sums: at most S pairs of 64 k per K step, each |d d'| <= 128^2
+    const double per_step = (double)a.S * 64.0 * 128.0 * 128.0;
     const int kchunk = std::max(1, (int)(2147483647.0 / per_step));
     OzakiGemmArgs args = a;
     int tm = (int)tiles_m, tn = (int)tiles_n;

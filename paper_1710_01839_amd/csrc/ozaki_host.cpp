@@ -90,9 +90,9 @@ extern "C" int mpg_ozaki_split(mpg_ctx* c, int side, int64_t rows, int64_t cols,
   if (!X || !out || !exps) return mpg_fail(c, MPG_ERR_ARG, "NULL pointer");
   const int64_t lines = side == 0 ? rows : cols, len = side == 0 ? cols : rows;
   const int64_t lines_p = round_up(lines, 64), len_p = round_up(len, 64);
-  if (ld_out < len_p || ld_out % 8 || plane < lines_p * ld_out)
-    return mpg_fail(c, MPG_ERR_ARG, "digit plane too small: need ld_out >= %lld (multiple of 8), "
-                    "plane >= %lld", (long long)len_p, (long long)(lines_p * ld_out));
+  if (ld_out < len_p || ld_out % 8 || plane < lines_p * ld_out || plane % 8 || (uintptr_t)out % 8)
+    return mpg_fail(c, MPG_ERR_ARG, "digit planes: need ld_out >= %lld and plane >= %lld, both multiples "
+                    "of 8, and out 8-byte aligned", (long long)len_p, (long long)(lines_p * ld_out));
   int st = mpg_device_guard(c);
   if (st != MPG_OK) return st;
   return mpg_launch(c, MPG_KCLASS_AUX, [&] {
@@ -143,7 +143,7 @@ int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, 
   }
   const int64_t lp = round_up(l, 64), mp = round_up(m, 64), np = round_up(n, 64);
   // INT32 headroom: at most SB pairs share a diagonal accumulator per block
-  if ((double)ozaki_block_slices() * (double)lp * 127.0 * 127.0 >= 2147483647.0)
+  if ((double)ozaki_block_slices() * (double)lp * 128.0 * 128.0 >= 2147483647.0)
     return mpg_fail(c, MPG_ERR_UNSUPPORTED, "l = %lld too large for exact INT32 sums", (long long)l);
   int *e, *f, *counter;
   if ((st = exponents(c, m, n, l, A, A_lo, lda, B, B_lo, ldb, slices == 0, &e, &f, &counter)) != MPG_OK)
@@ -209,17 +209,17 @@ extern "C" int mpg_ozaki_last_slices(const mpg_ctx* c) { return c ? c->last_slic
 
 namespace {
 
-// Bound on |x y - (kept digit products)| for x, y scaled into (-1, 1) and
-// cut into S truncated 7-bit digits: both remainders are below 2^-7S, which
-// gives 2^-7S (2 + 2^-7S) with all pairs; the triangle s + t <= S + 1 also
-// drops, on each diagonal g = S+2 .. 2S, 2S - g + 1 products of at most
-// 127^2 2^-7g.
+// Bound on |x y - (kept digit products)|, in units of 2^(e + f), for
+// |x| < 2^e, |y| < 2^f cut into S radix-256 digits: both remainders are
+// below 2^(e or f + 2 - 8S) and the kept parts (truncations) below 2^e,
+// 2^f, which gives 2^(3 - 8S) with all pairs; the triangle s + t <= S + 1
+// also drops, on each diagonal g = S+2 .. 2S, 2S - g + 1 products of at
+// most 128^2 2^(4 - 8g).
 double unit_bound(int S, int pairs_mode) {
-  const double u = std::ldexp(1.0, -7 * S);
-  double b = u * (2.0 + u);
+  double b = std::ldexp(1.0, 3 - 8 * S);
   if (pairs_mode == 1)
     for (int g = S + 2; g <= 2 * S; ++g)
-      b += (double)(2 * S - g + 1) * (127.0 * 127.0) * std::ldexp(1.0, -7 * g);
+      b += (double)(2 * S - g + 1) * (128.0 * 128.0) * std::ldexp(1.0, 4 - 8 * g);
   return b;
 }
 

@@ -78,15 +78,17 @@ def test_slices_exact_matches_oracle(gpu, kind):
 
 
 def test_single_slice_integer_product_exact(gpu):
-    """Integer entries in [-127, 127], row/column maxima >= 64: one digit
-    plane holds them, the MFMA sums are exact, C == AB."""
+    """Integer entries in [-63, 63], row/column maxima >= 32 (scale 2^6, one
+    radix-256 digit of weight 1): one digit plane holds them, the MFMA sums
+    are exact, C == AB."""
     M, ctx = gpu
     g = np.random.default_rng(3)
     m, n, l = 100, 90, 300
-    A = g.integers(-127, 128, size=(m, l)).astype(float)
-    B = g.integers(-127, 128, size=(l, n)).astype(float)
-    A[:, 5] = 127.0
-    B[7, :] = -120.0
+    A = g.integers(-63, 64, size=(m, l)).astype(float)
+    B = g.integers(-63, 64, size=(l, n)).astype(float)
+    A[:, 5] = 63.0
+    B[7, :] = -40.0
+    assert ozaki.slices_exact(A, B) == 1
     C = run_oz(M, ctx, A, B, 1)
     want = A.astype(np.int64) @ B.astype(np.int64)
     assert np.array_equal(C[0], want.astype(float)) and not C[1].any()
@@ -245,8 +247,8 @@ def test_slice_tuner_meets_target(gpu, bits):
 
 
 def test_slice_tuner_exact_count_competes(gpu):
-    """With the data given, the exact slice count (8 for uniform [-1, 1)
-    data) replaces the all-pairs count of a 106-bit target (16)."""
+    """With the data given, the exact slice count (7 for uniform [-1, 1)
+    data) replaces the all-pairs count of a 106-bit target (14)."""
     M, ctx = gpu
     n = 512
     A, B = inputs.dd_uniform(n, n, 3)[0], inputs.dd_uniform(n, n, 4)[0]
@@ -257,4 +259,33 @@ def test_slice_tuner_exact_count_competes(gpu):
     with pytest.raises(M.MpgemmError):
         M.Tuner(ctx).tune_slices(n, n, n, 0)
     with pytest.raises(M.MpgemmError):
-        M.Tuner(ctx).tune_slices(n, n, n, 300)
+        M.Tuner(ctx).tune_slices(n, n, n, 400)     # beyond 40 slices
+
+
+def test_dd_inputs_carry_patterns(gpu):
+    """Elements just inside a power of two, of both signs, have digit
+    expansions that are long runs of 255 and carry from the lowest digit
+    into the top one.  Double-double inputs (power-of-two hi, lo of the
+    opposite sign) with the exact slice count give the exact product up to
+    the recombination; FP64 inputs with all-ones mantissas split into the
+    oracle's digit planes bit for bit."""
+    M, ctx = gpu
+    g = np.random.default_rng(9)
+    m, n, l = 40, 36, 70
+    sign = np.where(g.random((m, l)) < 0.5, -1.0, 1.0)
+    hi = sign * np.ldexp(1.0, g.integers(-6, 1, (m, l)) - 1)
+    lo = -sign * np.ldexp(np.abs(hi), -53 - g.integers(1, 20, (m, l)))
+    A, B = (hi, lo), inputs.dd_uniform(l, n, 10)
+    Ct = run_ddoz(M, ctx, A, B, 0)
+    S = M.ozaki_last_slices(ctx)
+    assert S == ozaki.slices_exact(A, B)
+    r, _ = error_ratio_full(Ct, A, B, -104)
+    print("carry patterns: exact slices", S, "ratio", r)
+    assert r <= 8.0
+    X = sign * (np.ldexp(1.0, g.integers(-6, 1, (m, l))) * (1.0 - 2.0 ** -53))
+    planes, exps = M.ozaki_split(ctx, torch.as_tensor(X).cuda(), 9, 0)
+    torch.cuda.synchronize()
+    D, _ = ozaki.split_rows(X, ozaki.row_exponents(X), 9)
+    assert any(int(d.min()) < 0 for d in D[1:]) and any(int(d.max()) > 0 for d in D[1:])
+    for s_ in range(9):
+        assert np.array_equal(planes.cpu().numpy()[s_, :m, :l], D[s_])

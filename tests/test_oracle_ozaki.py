@@ -25,25 +25,45 @@ def test_split_reconstructs_and_digits_in_range():
     assert np.all(y == 0.0)
     for i in range(20):
         for k in range(30):
-            v = sum(Fraction(int(D[s][i, k]), 128 ** (s + 1)) for s in range(S))
-            assert v * Fraction(2) ** int(e[i]) == Fraction(float(A[i, k]))
+            v = sum(Fraction(int(D[s][i, k]), 256 ** (s + 1)) for s in range(S))
+            assert v * Fraction(2) ** int(e[i] + 2) == Fraction(float(A[i, k]))
+            assert -64 <= int(D[0][i, k]) <= 64
+            assert D[0][i, k] == 0 or (D[0][i, k] > 0) == (A[i, k] > 0)
             for s in range(S):
-                d = int(D[s][i, k])
-                assert -127 <= d <= 127
-                assert d == 0 or (d > 0) == (A[i, k] > 0)
+                assert -128 <= int(D[s][i, k]) <= 127
     # one slice fewer leaves a remainder somewhere
     D2, y2 = ozaki.split_rows(A, e, S - 1)
-    assert np.any(y2 != 0.0)
+    assert np.any(y2 != 0.0) and np.all(np.abs(y2) < 1.0) and np.all(y2 * A >= 0.0)
+
+
+def test_signed_bytes_carry():
+    """Truncated digits 31, 255, 255, 252 (value 31/256 + 255/256^2 +
+    255/256^3 + 252/256^4) become 32, 0, 0, -4, and their negatives -32, 0,
+    0, 4: the same values in signed bytes."""
+    F = [np.array([31, -31]), np.array([255, -255]), np.array([255, -255]), np.array([252, -252])]
+    D = ozaki.signed_bytes(F)
+    assert [int(d[0]) for d in D] == [32, 0, 0, -4] and [int(d[1]) for d in D] == [-32, 0, 0, 4]
+    g = np.random.default_rng(5)
+    sign = np.where(g.random(200) < 0.5, -1, 1)
+    F = [sign * g.integers(0, 64, 200)] + [sign * g.integers(0, 256, 200) for _ in range(6)]
+    D = ozaki.signed_bytes(F)
+    for j in range(200):
+        assert sum(Fraction(int(F[s][j]), 256 ** s) for s in range(7)) == \
+            sum(Fraction(int(D[s][j]), 256 ** s) for s in range(7))
+    assert all(-128 <= int(x) <= 127 for d in D[1:] for x in d)
+    assert all(-64 <= int(x) <= 64 for x in D[0])
 
 
 def test_single_slice_integer_product_exact():
-    """Integer entries in [-127, 127] with every row / column maximum >= 64:
-    one slice holds them exactly, so the result is exactly AB."""
+    """Integer entries in [-63, 63] with every row / column maximum >= 32
+    (scale 2^6, so 256 y = x / 2^0 ... one digit of weight 2^0): one slice
+    holds them exactly, so the result is exactly AB."""
     g = np.random.default_rng(3)
-    A = g.integers(-127, 128, size=(9, 40)).astype(float)
-    B = g.integers(-127, 128, size=(40, 7)).astype(float)
-    A[:, 0] = 127.0
-    B[0, :] = -100.0
+    A = g.integers(-63, 64, size=(9, 40)).astype(float)
+    B = g.integers(-63, 64, size=(40, 7)).astype(float)
+    A[:, 0] = 63.0
+    B[0, :] = -40.0
+    assert ozaki.slices_exact(A, B) == 1
     (hi, lo), (N, E0) = ozaki.ozaki_dd(A, B, 1)
     want = A.astype(np.int64) @ B.astype(np.int64)
     for idx in np.ndindex(want.shape):
@@ -96,36 +116,41 @@ def test_dd_split_reduces_to_fp64_split():
 
 
 def test_dd_split_reconstructs_exactly():
-    """hi + lo = 2^e sum_s D_s 128^-s once S covers the lowest set bit of
-    either limb; digits stay in [-127, 127]; one slice fewer leaves a
+    """hi + lo = 2^(e + 2) sum_s D_s 256^-s once S covers the lowest set bit
+    of either limb; digits stay signed bytes; one slice fewer leaves a
     nonzero remainder (the count is the smallest exact one)."""
     hi, lo = inputs.dd_uniform(6, 9, 5)
     e = ozaki.row_exponents(hi)
     S = ozaki.slices_exact((hi, lo), (hi.T.copy(), lo.T.copy()))
-    assert S >= 16                      # ~106 bits below the row scale
+    assert S >= 14                      # ~106 bits below the row scale
     D, rem = ozaki.split_rows_dd(hi, lo, e, S)
     for i in range(6):
         for k in range(9):
-            v = sum(Fraction(int(D[s][i, k]), 128 ** (s + 1)) for s in range(S))
-            assert v * Fraction(2) ** int(e[i]) == Fraction(float(hi[i, k])) + Fraction(float(lo[i, k]))
+            v = sum(Fraction(int(D[s][i, k]), 256 ** (s + 1)) for s in range(S))
+            assert v * Fraction(2) ** int(e[i] + 2) == Fraction(float(hi[i, k])) + Fraction(float(lo[i, k]))
             assert rem[i, k] == 0
-            assert all(-127 <= int(D[s][i, k]) <= 127 for s in range(S))
+            assert all(-128 <= int(D[s][i, k]) <= 127 for s in range(S))
     need_rows = max(ozaki.slices_needed_rows(hi, e), ozaki.slices_needed_rows(lo, e))
     _, rem2 = ozaki.split_rows_dd(hi, lo, e, need_rows - 1)
     assert any(r != 0 for r in rem2.flat)
 
 
 def test_dd_split_signed_digits_worked_example():
-    """hi = 1/2, lo = -2^-60 (value just below 1/2, e = 0): 128 r_0 =
-    64 - 2^-53 rounds to 64, so D_1 = 64 and the remainder r_1 = -2^-53 is
-    carried by a negative digit: r grows by 128 per step until
-    128 r_8 = -2^-53 128^8 = -8, so D_9 = -8 (8 128^-9 = 2^-60)."""
+    """hi = 1/2, lo = -2^-60 (value just below 1/2, e = 0): y = 1/8 - 2^-62,
+    256 y = 32 - 2^-54 gives the digit 31 and remainder 1 - 2^-54, which
+    grows by 256 per step (digits 255) until
+    256 (1 - 2^-6) = 252; the carry from the bottom turns 31, 255 x 6, 252
+    into 32, 0 x 6, -4 (4 256^-8 = 2^-62)."""
     hi = np.array([[0.5]])
     lo = np.array([[-2.0 ** -60]])
     D, rem = ozaki.split_rows_dd(hi, lo, np.array([0]), 10)
     got = [int(D[s][0, 0]) for s in range(10)]
-    assert got == [64, 0, 0, 0, 0, 0, 0, 0, -8, 0]
+    assert got == [32, 0, 0, 0, 0, 0, 0, -4, 0, 0]
     assert rem[0, 0] == 0
+    assert ozaki.slices_exact((hi, lo), (hi.copy(), lo.copy())) == 8
+    # the mirror image: truncation toward zero gives the negated digits
+    D, rem = ozaki.split_rows_dd(-hi, -lo, np.array([0]), 10)
+    assert [int(D[s][0, 0]) for s in range(10)] == [-32, 0, 0, 0, 0, 0, 0, 4, 0, 0]
 
 
 def test_dd_exact_slices_give_exact_product():
@@ -140,17 +165,22 @@ def test_dd_exact_slices_give_exact_product():
         assert ozaki.to_fraction(N, E0, idx) == Fraction(int(Ci[idx]), 2 ** s)
 
 
-@pytest.mark.parametrize("S", [2, 4, 7])
+@pytest.mark.parametrize("S", [2, 4, 6])
 def test_triangle_bound_term_is_attained(S):
-    """x = sum_{s<=S} 127 2^-7s (every digit 127, no remainder): the triangle
-    drops exactly the pairs s + t > S + 1, so the error of x*x equals the
+    """y = 40/256 + sum_{s=2}^{S-1} 127/256^s + 128/256^S (x = 4 y in [1/2, 1),
+    scale 2^0): truncated digits 40, 127, ..., 127, 128 carry into signed bytes
+    41, -128, ..., -128, so every pair the triangle drops is (-128)^2 =
+    2^14, the per-pair maximum of the bound: the error of x*x equals the
     dropped-diagonal term of the a-priori bound, pair count included."""
-    x = sum(Fraction(127, 128 ** s) for s in range(1, S + 1))
-    assert float(x) == x                       # 7S <= 49 bits: exact in binary64
+    y = Fraction(40, 256) + sum(Fraction(127, 256 ** s) for s in range(2, S)) + Fraction(128, 256 ** S)
+    x = 4 * y
+    assert float(x) == x                       # 8S <= 48 bits: exact in binary64
     A = np.array([[float(x)]])
+    D, _ = ozaki.split_rows(A, ozaki.row_exponents(A), S)
+    assert [int(d[0, 0]) for d in D] == [41] + [-128] * (S - 1)
     (_, _), (N, E0) = ozaki.ozaki_dd(A, A.copy(), S, "triangle")
     err = x * x - ozaki.to_fraction(N, E0, (0, 0))
-    dropped = sum(Fraction(127 * 127, 128 ** (s + t)) for s in range(1, S + 1)
+    dropped = sum(Fraction(2 ** 14 * 16, 256 ** (s + t)) for s in range(1, S + 1)
                   for t in range(1, S + 1) if s + t > S + 1)
     assert err == dropped
     term = ozaki.apriori_unit(S, "triangle") - ozaki.apriori_unit(S, "all")
