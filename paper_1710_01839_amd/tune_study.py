@@ -10,7 +10,7 @@ the paper's procedure and over exhaustive search.
    counts; printed rule: two block rows scaled linearly).
 2. Training data: exhaustive tuning of training shapes (every candidate
    timed) into a JSONL timing database; the MLP is trained on it on the GPU.
-3. Held-out shapes: exhaustive, paper and MLP-pruned (top 3) tuning; each
+3. Held-out shapes: exhaustive, paper and MLP-pruned (the default top-k) tuning; each
    pick is re-timed (median of 5) and its regret against the exhaustive pick
    reported with the wall-clock tuning time of each mode.
 
@@ -76,7 +76,7 @@ def main():
 
     summary = {"paper": [], "mlp": [], "paper_time": [], "mlp_time": []}
     for prec, m, n, l in HELD_OUT:
-        res = {mode: T.tune(prec, m, n, l, mode, 3) for mode in ("exhaustive", "paper", "mlp")}
+        res = {mode: T.tune(prec, m, n, l, mode, 0) for mode in ("exhaustive", "paper", "mlp")}
         ret = {mode: T.time(prec, m, n, l, r["algo"], r["tile"], reps=5) for mode, r in res.items()}
         rec = {"kind": "held_out", "prec": prec, "shape": [m, n, l]}
         for mode in res:
