@@ -289,3 +289,32 @@ def test_dd_inputs_carry_patterns(gpu):
     assert any(int(d.min()) < 0 for d in D[1:]) and any(int(d.max()) > 0 for d in D[1:])
     for s_ in range(9):
         assert np.array_equal(planes.cpu().numpy()[s_, :m, :l], D[s_])
+
+
+# K longer than one INT32 chunk (2048 / S steps of 64): the double-double
+# partial results wait in C between chunks.  One case per kernel family,
+# and the largest K the INT32 headroom admits (32704); one more is refused.
+@pytest.mark.parametrize("kind,l", [("uniform", 20480), ("dd", 8192), ("wide", 8192), ("uniform", 32704)])
+def test_multi_chunk_k(gpu, kind, l):
+    M, ctx = gpu
+    m, n = 48, 40
+    if kind == "dd":
+        A, B = inputs.dd_uniform(m, l, 21), inputs.dd_uniform(l, n, 22)
+        C = run_ddoz(M, ctx, A, B, 0)
+    else:
+        gen = inputs.fp64_wide if kind == "wide" else (lambda r, c, s: inputs.dd_uniform(r, c, s)[0])
+        A, B = (gen(m, l, 21),), (gen(l, n, 22),)
+        C = run_oz(M, ctx, A[0], B[0], 0)
+    S = M.ozaki_last_slices(ctx)
+    assert (l // 64) > 2048 // S                    # more than one chunk
+    r, _ = error_ratio_full(C, A, B, -104, threads=8)
+    print(kind, "l", l, "slices", S, "chunks", -(-(l // 64) // (2048 // S)), "ratio", r)
+    assert r <= 8.0
+
+
+def test_k_beyond_headroom_refused(gpu):
+    M, ctx = gpu
+    A = torch.ones(4, 32705, dtype=torch.float64, device="cuda")
+    B = torch.ones(32705, 4, dtype=torch.float64, device="cuda")
+    with pytest.raises(M.MpgemmError):
+        M.mpgemm_ozaki_dd(ctx, A, B, M.empty_like_limbs(4, 4, 2), 0)
