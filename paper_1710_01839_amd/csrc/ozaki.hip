@@ -323,7 +323,8 @@ __global__ __launch_bounds__(256) void split_cols_kernel(const double* X, const 
 }
 
 // ---------------------------------------------------------------------
-// INT8 MFMA product with diagonal grouping.
+// INT8 MFMA product with diagonal grouping, general form (used above
+// kOzBandMaxS slices).
 //
 // Workgroup: 256 threads, C tile 64 x 64; wave w owns the 32 x 32 sub-tile
 // (32 (w / 2), 32 (w % 2)) as 2 x 2 blocks of 16 x 16 MFMA outputs.  The
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(256) void split_cols_kernel(const double* X, const 
 // 16-byte fragment reads of 8 lanes hit distinct banks) in LDS,
 // double-buffered, and every kept pair adds into the INT32 accumulator of
 // its diagonal (2 SB - 1 live diagonals).  At the end of the block each
-// diagonal sum is converted to FP64 (exact), scaled by 2^(e_i + f_j - 7g)
+// diagonal sum is converted to FP64 (exact), scaled by 2^(e_i + f_j + 4 - 8g)
 // (exact) and added to the entry's double-double accumulator.
 //
 // MFMA operand layout (16 x 16 x 64, i8): lane l supplies row (l % 16) of

@@ -25,10 +25,10 @@ int ozaki_max_slices();
 int ozaki_block_slices();
 // Exponents e of the rows (by_col 0) or columns (by_col 1) of X (R x K):
 // 1 + max ilogb, 0 for an all-zero line.  When `need` is given it is raised
-// to the largest number of 7-bit digits any line needs to hold its
-// elements exactly after scaling by 2^-e (columns then use `low`, K ints of
-// scratch); with Xlo (double-double input) the lo limbs' lowest set bits
-// count too, the scale comes from X.  One pass over X (and Xlo).
+// to the largest number of radix-256 digits any line needs to hold its
+// elements exactly after scaling by 2^-(e + 2) (columns then use `low`, K
+// ints of scratch); with Xlo (double-double input) the lo limbs' lowest
+// set bits count too, the scale comes from X.  One pass over X (and Xlo).
 hipError_t launch_ozaki_scan(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                              int by_col, int* e, int* low, int* need, hipStream_t s);
 // Digit planes of the rows (columns) of X, or of X + Xlo split as one
