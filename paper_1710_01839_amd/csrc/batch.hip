@@ -1,21 +1,32 @@
 // Persistent kernel for a batch of uneven double-double products: a fixed
-// grid walks one global tile index space (problem tiles laid end to end)
-// with a static stride, each tile computed by the block-algorithm tile
-// routine of the single-problem kernel (bitwise identical results).
+// grid draws tiles from one global tile index space (problem tiles laid end
+// to end, problems by decreasing l, so the most expensive tiles go first)
+// through an atomic queue, each tile computed by the block-algorithm tile
+// routine of the single-problem kernel (bitwise identical results).  A
+// workgroup leaves when it draws an index past the last tile.
 #include "batch_internal.hpp"
 #include "gemm_kernels.hpp"
 
 namespace mpg {
 namespace {
 
+__global__ void queue_reset_kernel(int* next) {
+  if (threadIdx.x == 0) *next = 0;
+}
+
 template <int BM, int BN, int BK, int TM, int TN, int MINW>
 __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void persistent_kernel(
-    const BatchProblem* desc) {
+    const BatchProblem* desc, int* next) {
   __shared__ kern::BlockSmem<2, BM, BN, BK> sm;
+  __shared__ int s_w;
   const int64_t total = desc[0].tile_start;
   const int count = (int)desc[0].tiles_n;
   const BatchProblem* probs = desc + 1;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  for (;;) {
+    if (threadIdx.x == 0) s_w = atomicAdd(next, 1);
+    __syncthreads();
+    const int64_t w = s_w;
+    if (w >= total) break;
     // last problem whose first tile is <= w
     int lo = 0, hi = count - 1;
     while (lo < hi) {
@@ -68,9 +79,18 @@ int batch_blocks_per_cu(int v) {
   return blocks > 0 ? blocks : 1;
 }
 
-hipError_t launch_batch_persistent(int v, const BatchProblem* d_desc, int grid, hipStream_t s) {
+size_t batch_desc_bytes(int count) { return (size_t)(count + 1) * sizeof(BatchProblem) + sizeof(int); }
+
+int* batch_queue(BatchProblem* d_desc, int count) { return reinterpret_cast<int*>(d_desc + count + 1); }
+
+hipError_t launch_batch_persistent(int v, BatchProblem* d_desc, int count, int grid, hipStream_t s) {
   if (v < 0 || v >= kN) return hipErrorInvalidValue;
-  void* args[] = {(void*)&d_desc};
+  int* next = batch_queue(d_desc, count);
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, s, next);
+  hipError_t r = hipGetLastError();
+  if (r != hipSuccess) return r;
+  const BatchProblem* desc = d_desc;
+  void* args[] = {(void*)&desc, (void*)&next};
   return hipLaunchKernel(kEntries[v].fn, dim3(grid), dim3(kEntries[v].threads), args, 0, s);
 }
 

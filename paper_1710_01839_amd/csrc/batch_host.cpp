@@ -2,6 +2,7 @@
 // construction, the persistent launch, and plans that capture that launch
 // once in a HIP graph and replay it.
 #include <algorithm>
+#include <climits>
 #include <numeric>
 #include <vector>
 
@@ -63,6 +64,9 @@ int build_desc(mpg_ctx* c, int count, const mpg_dd_problem* P, int variant,
     d.tile_start = start;
     start += tm * tn;
   }
+  // the tile queue is an int that every workgroup advances once past the end
+  if (start > (int64_t)INT_MAX / 2)
+    return mpg_fail(c, MPG_ERR_UNSUPPORTED, "%lld tiles: too many for one batch", (long long)start);
   out[0].tile_start = start;
   out[0].tiles_n = count;
   return MPG_OK;
@@ -96,13 +100,13 @@ extern "C" int mpgemm_dd_batched(mpg_ctx* c, int count, const mpg_dd_problem* pr
   hipError_t r = hipStreamSynchronize(c->stream);
   if (r != hipSuccess) return mpg_hip_fail(c, r, "hipStreamSynchronize (batch descriptors)");
   void* d = nullptr;
-  if ((st = mpg_workspace(c, 2, desc.size() * sizeof(BatchProblem), &d)) != MPG_OK) return st;
+  if ((st = mpg_workspace(c, 2, batch_desc_bytes(count), &d)) != MPG_OK) return st;
   c->batch_host.assign((const char*)desc.data(), (const char*)(desc.data() + desc.size()));
   r = hipMemcpyAsync(d, c->batch_host.data(), c->batch_host.size(), hipMemcpyHostToDevice, c->stream);
   if (r != hipSuccess) return mpg_hip_fail(c, r, "descriptor upload");
   const int grid = grid_for(c, v, desc[0].tile_start);
   return mpg_launch(c, MPG_KCLASS_GEMM,
-                    [&] { return launch_batch_persistent(v, (const BatchProblem*)d, grid, c->stream); },
+                    [&] { return launch_batch_persistent(v, (BatchProblem*)d, count, grid, c->stream); },
                     "persistent batch kernel");
 }
 
@@ -122,14 +126,14 @@ extern "C" int mpg_batch_plan_create(mpg_ctx* c, int count, const mpg_dd_problem
   // the grid is fixed at capture; size it for the largest total tile count
   // any later update may bring (the kernel reads the count at run time)
   p->grid = (int)((int64_t)c->num_cu * batch_blocks_per_cu(v));
-  hipError_t r = hipMalloc(&p->d_desc, desc.size() * sizeof(BatchProblem));
+  hipError_t r = hipMalloc(&p->d_desc, batch_desc_bytes(count));
   if (r == hipSuccess)
     r = hipMemcpy(p->d_desc, desc.data(), desc.size() * sizeof(BatchProblem), hipMemcpyHostToDevice);
   hipStream_t cs = nullptr;
   if (r == hipSuccess) r = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (r == hipSuccess) r = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (r == hipSuccess) {
-    hipError_t lr = launch_batch_persistent(v, p->d_desc, p->grid, cs);
+    hipError_t lr = launch_batch_persistent(v, p->d_desc, count, p->grid, cs);
     r = hipStreamEndCapture(cs, &p->graph);
     if (lr != hipSuccess) r = lr;
   }
