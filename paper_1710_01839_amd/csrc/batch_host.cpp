@@ -3,6 +3,7 @@
 // once in a HIP graph and replay it.
 #include <algorithm>
 #include <climits>
+#include <cstring>
 #include <numeric>
 #include <vector>
 
@@ -96,18 +97,41 @@ extern "C" int mpgemm_dd_batched(mpg_ctx* c, int count, const mpg_dd_problem* pr
   if ((st = build_desc(c, count, problems, v, desc)) != MPG_OK) return st;
   if (count == 0 || desc[0].tile_start == 0) return MPG_OK;
   if ((st = mpg_device_guard(c)) != MPG_OK) return st;
-  // the previous call's descriptors may still be read by the device
-  hipError_t r = hipStreamSynchronize(c->stream);
-  if (r != hipSuccess) return mpg_hip_fail(c, r, "hipStreamSynchronize (batch descriptors)");
+  // Descriptors alternate between two slots (pinned host staging + device
+  // copy), so the host does not wait for the previous call: only for the
+  // call before it, which used the same slot.
+  const int k = c->batch_next;
+  hipError_t r = hipSuccess;
+  if (!c->batch_done[k]) r = hipEventCreateWithFlags(&c->batch_done[k], hipEventDisableTiming);
+  else r = hipEventSynchronize(c->batch_done[k]);
+  if (r != hipSuccess) return mpg_hip_fail(c, r, "batch descriptor slot");
+  const size_t bytes = batch_desc_bytes(count);
+  if (bytes > c->batch_pin_size[k]) {
+    if (c->batch_pin[k]) (void)hipHostFree(c->batch_pin[k]);
+    c->batch_pin[k] = nullptr;
+    c->batch_pin_size[k] = 0;
+    if ((r = hipHostMalloc(&c->batch_pin[k], bytes, hipHostMallocDefault)) != hipSuccess) {
+      c->batch_pin[k] = nullptr;
+      (void)hipGetLastError();
+      return mpg_fail(c, MPG_ERR_NOMEM, "pinned staging of %zu bytes failed", bytes);
+    }
+    c->batch_pin_size[k] = bytes;
+  }
   void* d = nullptr;
-  if ((st = mpg_workspace(c, 2, batch_desc_bytes(count), &d)) != MPG_OK) return st;
-  c->batch_host.assign((const char*)desc.data(), (const char*)(desc.data() + desc.size()));
-  r = hipMemcpyAsync(d, c->batch_host.data(), c->batch_host.size(), hipMemcpyHostToDevice, c->stream);
+  if ((st = mpg_workspace(c, 2 + k, bytes, &d)) != MPG_OK) return st;
+  std::memcpy(c->batch_pin[k], desc.data(), desc.size() * sizeof(BatchProblem));
+  r = hipMemcpyAsync(d, c->batch_pin[k], desc.size() * sizeof(BatchProblem), hipMemcpyHostToDevice,
+                     c->stream);
   if (r != hipSuccess) return mpg_hip_fail(c, r, "descriptor upload");
   const int grid = grid_for(c, v, desc[0].tile_start);
-  return mpg_launch(c, MPG_KCLASS_GEMM,
-                    [&] { return launch_batch_persistent(v, (BatchProblem*)d, count, grid, c->stream); },
-                    "persistent batch kernel");
+  st = mpg_launch(c, MPG_KCLASS_GEMM,
+                  [&] { return launch_batch_persistent(v, (BatchProblem*)d, count, grid, c->stream); },
+                  "persistent batch kernel");
+  if (st != MPG_OK) return st;
+  if ((r = hipEventRecord(c->batch_done[k], c->stream)) != hipSuccess)
+    return mpg_hip_fail(c, r, "batch descriptor slot");
+  c->batch_next = k ^ 1;
+  return MPG_OK;
 }
 
 extern "C" int mpg_batch_plan_create(mpg_ctx* c, int count, const mpg_dd_problem* problems,

@@ -210,6 +210,10 @@ extern "C" int mpg_destroy(mpg_ctx* c) {
   mpg_destroy_cached(c);
   for (int s = 0; s < mpg_ctx::kSlots; ++s)
     if (c->ws[s]) (void)hipFree(c->ws[s]);
+  for (int k = 0; k < 2; ++k) {
+    if (c->batch_pin[k]) (void)hipHostFree(c->batch_pin[k]);
+    if (c->batch_done[k]) (void)hipEventDestroy(c->batch_done[k]);
+  }
   for (auto& r : c->prof_recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

@@ -22,11 +22,17 @@ struct mpg_ctx {
 
   // workspace slots (grow-only, freed with the context): 0 = large operand
   // workspace (Strassen blocks, digit planes), 1 = small (exponents, counters)
-  // 2 = batch descriptors
-  static constexpr int kSlots = 3;
-  void* ws[kSlots] = {nullptr, nullptr, nullptr};
-  size_t ws_size[kSlots] = {0, 0, 0};
-  std::string batch_host;  // host copy of the last batch descriptors (upload source)
+  // 2, 3 = batch descriptors (two calls in flight)
+  static constexpr int kSlots = 4;
+  void* ws[kSlots] = {nullptr, nullptr, nullptr, nullptr};
+  size_t ws_size[kSlots] = {0, 0, 0, 0};
+  // batch descriptor uploads: pinned host staging per descriptor slot, and
+  // an event after the launch that read it (the slot is free again once it
+  // has completed)
+  void* batch_pin[2] = {nullptr, nullptr};
+  size_t batch_pin_size[2] = {0, 0};
+  hipEvent_t batch_done[2] = {nullptr, nullptr};
+  int batch_next = 0;
   bool alloc_hook_fail = false;  // test seam: make the next allocations fail
 
   // kernel timing

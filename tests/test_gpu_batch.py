@@ -56,6 +56,20 @@ def test_persistent_matches_single_kernels(gpu, variant):
         assert r <= 8.0
 
 
+def test_back_to_back_calls(gpu):
+    """Several batched calls queued without host synchronisation (descriptor
+    slots alternate; the third call reuses the first call's slot): every
+    batch equals the single-problem kernels bit for bit."""
+    M, ctx = gpu
+    batches = [make_batch(M, SHAPES[k:] + SHAPES[:k], 200 + 50 * k)[0] for k in range(4)]
+    for probs in batches:
+        M.mpgemm_dd_batched(ctx, probs, None)
+    torch.cuda.synchronize()
+    for probs in batches:
+        got = [M.to_host(C) for _, _, C in probs]
+        assert same(got, reference(M, ctx, probs, M.variants(2)[1]))
+
+
 def test_graph_replays_and_updates(gpu):
     M, ctx = gpu
     probs, host = make_batch(M, SHAPES, 200)
