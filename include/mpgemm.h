@@ -135,11 +135,13 @@ typedef struct {
 typedef struct mpg_batch_plan mpg_batch_plan;
 
 /* All problems in one persistent launch: a grid of (CUs x resident
- * workgroups) walks the tiles of every problem, laid end to end, with the
- * block algorithm (Eq. 2) of tile variant `tile` (NULL: 32 x 32 tiles);
- * results are bitwise those of mpgemm_dd(MPG_BLOCK) with that tile.
- * `problems` is a host array; the descriptors are uploaded on the context
- * stream (the call waits for the context's previous batch to finish). */
+ * workgroups) draws the tiles of every problem, laid end to end (problems
+ * by decreasing l), from an atomic queue, with the block algorithm (Eq. 2)
+ * of tile variant `tile` (NULL: 32 x 32 tiles); results are bitwise those
+ * of mpgemm_dd(MPG_BLOCK) with that tile.  `problems` is a host array; the
+ * descriptors are staged in pinned memory and uploaded on the context
+ * stream in one of two alternating slots (the call waits only for the
+ * context's batch before the previous one).  Asynchronous otherwise. */
 int mpgemm_dd_batched(mpg_ctx* ctx, int count, const mpg_dd_problem* problems,
                       const mpg_tile* tile);
 
