@@ -179,7 +179,9 @@ int mpg_batch_plan_destroy(mpg_batch_plan* plan);
  *   pairs_mode 0: all slices^2 digit-plane pairs; 1: only s + t <= slices + 1.
  * With fewer slices the truncation error is below
  * l 2^(e_i + f_j) 2^(3 - 8 slices) per entry (pairs_mode 0).
- * Requires l <= 32704 (INT32 headroom).  C_hi/C_lo must not overlap A, B. */
+ * Up to 24 slices any l (the INT32 sums are flushed every 2048 / slices
+ * K steps of 64); above 24 slices l <= 32704.  C_hi/C_lo must not overlap
+ * A, B. */
 int mpgemm_ozaki_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
                     const double* A, int64_t lda, const double* B, int64_t ldb,
                     double* C_hi, double* C_lo, int64_t ldc, int slices, int pairs_mode);

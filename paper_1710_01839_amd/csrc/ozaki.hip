@@ -952,6 +952,7 @@ void OzTable<S>::fill(OzKernels& k) {
 
 int ozaki_max_slices() { return kMaxSlices; }
 int ozaki_block_slices() { return 4; }
+int ozaki_chunked_max_slices() { return kOzBandMaxS; }
 
 hipError_t launch_ozaki_scan(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                              int by_col, int* e, int* low, int* need, hipStream_t s) {

@@ -142,9 +142,6 @@ int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, 
                       "zero C");
   }
   const int64_t lp = round_up(l, 64), mp = round_up(m, 64), np = round_up(n, 64);
-  // INT32 headroom: at most SB pairs share a diagonal accumulator per block
-  if ((double)ozaki_block_slices() * (double)lp * 128.0 * 128.0 >= 2147483647.0)
-    return mpg_fail(c, MPG_ERR_UNSUPPORTED, "l = %lld too large for exact INT32 sums", (long long)l);
   int *e, *f, *counter;
   if ((st = exponents(c, m, n, l, A, A_lo, lda, B, B_lo, ldb, slices == 0, &e, &f, &counter)) != MPG_OK)
     return st;
@@ -156,6 +153,13 @@ int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, 
       return mpg_fail(c, MPG_ERR_UNSUPPORTED, "exact slicing needs %d slices (max %d)", S,
                       ozaki_max_slices());
   }
+  // INT32 headroom of the general kernel (above ozaki_chunked_max_slices()
+  // slices): SB pairs share a diagonal accumulator over the whole of K; the
+  // other kernels flush their sums every 2^31 / (S 2^20) K steps
+  if (S > ozaki_chunked_max_slices() &&
+      (double)ozaki_block_slices() * (double)lp * 128.0 * 128.0 >= 2147483647.0)
+    return mpg_fail(c, MPG_ERR_UNSUPPORTED, "l = %lld too large for exact INT32 sums with %d slices",
+                    (long long)l, S);
   c->last_slices = S;
   void* big = nullptr;
   const int64_t planeA = mp * lp, planeB = np * lp;

@@ -22,7 +22,10 @@ struct OzakiGemmArgs {
 };
 
 int ozaki_max_slices();
+// Slices per pair block of the general kernel, and the largest slice count
+// served by the kernels that split K into INT32-safe chunks.
 int ozaki_block_slices();
+int ozaki_chunked_max_slices();
 // Exponents e of the rows (by_col 0) or columns (by_col 1) of X (R x K):
 // 1 + max ilogb, 0 for an all-zero line.  When `need` is given it is raised
 // to the largest number of radix-256 digits any line needs to hold its

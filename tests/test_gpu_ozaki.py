@@ -293,7 +293,7 @@ def test_dd_inputs_carry_patterns(gpu):
 
 # K longer than one INT32 chunk (2048 / S steps of 64): the double-double
 # partial results wait in C between chunks.  One case per kernel family,
-# and the largest K the INT32 headroom admits (32704); one more is refused.
+# and K = 32704 (the general kernel's limit, here with 7 slices).
 @pytest.mark.parametrize("kind,l", [("uniform", 20480), ("dd", 8192), ("wide", 8192), ("uniform", 32704)])
 def test_multi_chunk_k(gpu, kind, l):
     M, ctx = gpu
@@ -313,8 +313,18 @@ def test_multi_chunk_k(gpu, kind, l):
 
 
 def test_k_beyond_headroom_refused(gpu):
+    """Up to 24 slices K is cut into INT32-safe chunks, so any l works (all
+    ones: C = l exactly); above 24 slices the general kernel keeps each
+    diagonal sum over the whole of K, and l > 32704 is refused."""
     M, ctx = gpu
-    A = torch.ones(4, 32705, dtype=torch.float64, device="cuda")
-    B = torch.ones(32705, 4, dtype=torch.float64, device="cuda")
+    l = 40000
+    A = torch.ones(4, l, dtype=torch.float64, device="cuda")
+    B = torch.ones(l, 4, dtype=torch.float64, device="cuda")
+    C = M.empty_like_limbs(4, 4, 2)
+    M.mpgemm_ozaki_dd(ctx, A, B, C, 0)
+    torch.cuda.synchronize()
+    assert torch.all(C[0] == float(l)) and torch.all(C[1] == 0.0)
+    A[:, 1] = 2.0 ** -200                       # 26 slices for these rows
+    assert M.ozaki_slices_exact(ctx, A, B) > 24
     with pytest.raises(M.MpgemmError):
-        M.mpgemm_ozaki_dd(ctx, A, B, M.empty_like_limbs(4, 4, 2), 0)
+        M.mpgemm_ozaki_dd(ctx, A, B, C, 0)
