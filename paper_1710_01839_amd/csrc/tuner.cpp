@@ -309,9 +309,12 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
   int ntrials = 0;
   Cand best{};
   double bms = INFINITY;
+  // a candidate the shape does not admit (MPG_ERR_UNSUPPORTED, e.g. the
+  // split product's K limit above 24 slices) is skipped, not a failure
   auto trial = [&](const Cand& cd) -> int {
     double ms = 0.0;
     int r = time_rows(c, s, m, cd, 3, &ms);
+    if (r == MPG_ERR_UNSUPPORTED) return MPG_OK;
     if (r != MPG_OK) return r;
     ++ntrials;
     db_append(c, precision, m, n, l, cd, ms, "trial");
@@ -380,6 +383,7 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   free_scratch(s);
   if (st != MPG_OK) return st;
+  if (ntrials == 0) return mpg_fail(c, MPG_ERR_UNSUPPORTED, "no candidate ran for this shape");
   if (best_algo) *best_algo = best.algo;
   if (best_tile) *best_tile = best.tile;
   if (best_ms) *best_ms = bms;
