@@ -299,6 +299,42 @@ int mpg_tune(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l, int m
 int mpg_tune_table_set(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
                        int algo, const mpg_tile* tile);
 
+/* ---- method choice by accuracy target ---------------------------------- */
+
+/* Normwise a-priori bound of a method for C := A B, per entry of C, in units
+ * of l max|A| max|B| (returns +inf for a combination that does not exist):
+ *   DD / QD simple and block (precision 2 / 4): 8 l u, u = 2^-104 / 2^-208
+ *     (the componentwise bound 8 l u (|A||B|)_ij with (|A||B|)_ij <=
+ *     l max|A| max|B|); QD inputs (in_limbs 4) rounded to DD add 2^-105;
+ *   Winograd-Strassen depth 1..3 (square m = n = l only, padded to N, a
+ *     multiple of 2^depth): [18^d (N0^2 + 6 N0) - 6 N] 8 u / l, N0 = N / 2^d
+ *     (Higham's bound for the Winograd recursion);
+ *   MPG_OZAKI (precision 2, in_limbs 1 or 2; tile->slices, pairs_mode):
+ *     4 x the truncation bound of mpg_ozaki_slices_for_bits (the row and
+ *     column scales are below 2 max|a_i.| and 2 max|b_.j|) plus
+ *     (4.1 T^2 + 2) 2^-105, T = (2S - 1) x chunks of K, for the
+ *     double-double recombination.
+ * Host only. */
+double mpg_method_bound(int in_limbs, int precision, int algo, const mpg_tile* tile,
+                        int pairs_mode, int64_t m, int64_t n, int64_t l);
+
+/* Chooses how to compute C := A B for an accuracy target (the closing
+ * proposal of the paper: pick the precision from the accuracy the user
+ * needs): max_ij |C - AB|_ij <= 2^-bits l max|A| max|B|, for inputs of
+ * in_limbs limbs (1 FP64, 2 DD, 4 QD).  Candidates: DD and QD block (default
+ * tile), Winograd-Strassen depth 1..3 (DD) / 1..2 (QD) for square shapes,
+ * and the split INT8 product (FP64 or DD inputs) with the fewest slices
+ * whose bound meets the target, all pairs and triangle.  Every candidate
+ * whose mpg_method_bound is within the target is timed at full size on
+ * library buffers (median of 3); the fastest is returned: *precision (2:
+ * call mpgemm_dd, or mpgemm_ozaki_dd / mpgemm_dd_ozaki for MPG_OZAKI with
+ * tile->slices and *pairs_mode; 4: mpgemm_qd), *algo, *tile, *pairs_mode,
+ * and (nullable) the bits its bound guarantees and its time.  A target
+ * that no candidate meets gives MPG_ERR_UNSUPPORTED. */
+int mpg_select_method(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l, int in_limbs, int bits,
+                      int* precision, int* algo, mpg_tile* tile, int* pairs_mode,
+                      double* bound_bits, double* ms);
+
 /* ---- run-time model (MLP) -------------------------------------------- */
 
 /* Features of one candidate (MPG_MLP_FEATURES floats): log2 m, n, l / 12;

@@ -211,15 +211,13 @@ extern "C" int mpgemm_dd_ozaki(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
 
 extern "C" int mpg_ozaki_last_slices(const mpg_ctx* c) { return c ? c->last_slices : 0; }
 
-namespace {
-
 // Bound on |x y - (kept digit products)|, in units of 2^(e + f), for
 // |x| < 2^e, |y| < 2^f cut into S radix-256 digits: both remainders are
 // below 2^(e or f + 2 - 8S) and the kept parts (truncations) below 2^e,
 // 2^f, which gives 2^(3 - 8S) with all pairs; the triangle s + t <= S + 1
 // also drops, on each diagonal g = S+2 .. 2S, 2S - g + 1 products of at
 // most 128^2 2^(4 - 8g).
-double unit_bound(int S, int pairs_mode) {
+double mpg::ozaki_unit_bound(int S, int pairs_mode) {
   double b = std::ldexp(1.0, 3 - 8 * S);
   if (pairs_mode == 1)
     for (int g = S + 2; g <= 2 * S; ++g)
@@ -227,11 +225,15 @@ double unit_bound(int S, int pairs_mode) {
   return b;
 }
 
-}  // namespace
+int mpg::ozaki_chunks(int S, int64_t l) {
+  const int64_t steps = (l + 63) / 64;
+  const int64_t kchunk = std::max<int64_t>(1, (int64_t)(2147483647.0 / ((double)S * 64.0 * 128.0 * 128.0)));
+  return S > ozaki_chunked_max_slices() ? 1 : (int)((steps + kchunk - 1) / kchunk);
+}
 
 extern "C" int mpg_ozaki_slices_for_bits(int bits, int pairs_mode) {
   if (bits < 1 || (pairs_mode != 0 && pairs_mode != 1)) return 0;
   for (int S = 1; S <= ozaki_max_slices(); ++S)
-    if (unit_bound(S, pairs_mode) <= std::ldexp(1.0, -bits)) return S;
+    if (ozaki_unit_bound(S, pairs_mode) <= std::ldexp(1.0, -bits)) return S;
   return 0;
 }

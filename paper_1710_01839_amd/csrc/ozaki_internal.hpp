@@ -26,6 +26,11 @@ int ozaki_max_slices();
 // served by the kernels that split K into INT32-safe chunks.
 int ozaki_block_slices();
 int ozaki_chunked_max_slices();
+// A-priori truncation bound per unit of 2^(e_i + f_j) per product term
+// (S slices; pairs_mode 0 all pairs, 1 the triangle), and the number of
+// INT32 chunks K is cut into (1 for the general kernel).
+double ozaki_unit_bound(int S, int pairs_mode);
+int ozaki_chunks(int S, int64_t l);
 // Exponents e of the rows (by_col 0) or columns (by_col 1) of X (R x K):
 // 1 + max ilogb, 0 for an all-zero line.  When `need` is given it is raised
 // to the largest number of radix-256 digits any line needs to hold its

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "capi_internal.hpp"
+#include "ozaki_internal.hpp"
 
 using namespace mpg;
 
@@ -481,6 +482,132 @@ extern "C" int mpg_ozaki_tune(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int b
   free_scratch(sc);
   if (st == MPG_OK && ms) *ms = best;
   return st;
+}
+
+namespace {
+
+// Normwise a-priori bound of a method for C := A B, per entry of C in units
+// of l max|A| max|B|.  DD / QD simple and block: the componentwise bound
+// 8 l u (|A||B|)_ij (u = 2^-104, 2^-208) with (|A||B|)_ij <= l max|A| max|B|;
+// Winograd-Strassen of depth d on a square product padded to N: Higham's
+// [18^d (N0^2 + 6 N0) - 6 N] 8 u max|A| max|B|, N0 = N / 2^d; QD inputs
+// rounded to DD add 2^-105 (|A||B|).  The split product: the truncation
+// bound times 2^(e_i + f_j) <= 4 max|a_i.| max|b_.j|, plus the
+// double-double recombination of its T = (2S - 1) x chunks exactly scaled
+// terms: every TwoSum into the high limb is exact, the error terms are
+// below 2^-53 of the running sum, so their sum in the low limb rounds off
+// at most T^2/2 2^-106 of the largest running sum; the running sums are
+// below the sum of the terms' magnitudes, at most 16.2 l max|A| max|B|
+// (signed-byte digits: sum_s |D_s| 256^-s <= 128/255, scales below
+// 4 max|a|, 4 max|b|); and the final rounding adds 2^-106 |C|.
+double method_bound(int in_limbs, int prec, int algo, const mpg_tile& t, int pairs, int64_t m,
+                    int64_t l) {
+  const double L = (double)l;
+  if (algo == MPG_OZAKI) {
+    if (in_limbs > 2 || t.slices < 1) return INFINITY;
+    const int S = t.slices;
+    const double T = (double)(2 * S - 1) * ozaki_chunks(S, l);
+    const double recomb = (4.1 * T * T + 2.0) * std::ldexp(1.0, -105);
+    return 4.0 * ozaki_unit_bound(S, pairs) + recomb;
+  }
+  const double u8 = 8.0 * std::ldexp(1.0, prec == 2 ? -104 : -208);
+  double b;
+  if (algo == MPG_STRASSEN) {
+    const int64_t q = (int64_t)1 << t.depth, N = (m + q - 1) / q * q;
+    const double N0 = (double)(N / q);
+    b = (std::pow(18.0, t.depth) * (N0 * N0 + 6.0 * N0) - 6.0 * (double)N) * u8 / L;
+  } else {
+    b = u8 * L;
+  }
+  if (prec == 2 && in_limbs == 4) b += std::ldexp(1.0, -105);
+  return b;
+}
+
+}  // namespace
+
+extern "C" double mpg_method_bound(int in_limbs, int precision, int algo, const mpg_tile* tile,
+                                   int pairs_mode, int64_t m, int64_t n, int64_t l) {
+  if ((in_limbs != 1 && in_limbs != 2 && in_limbs != 4) || (precision != 2 && precision != 4) ||
+      m <= 0 || n <= 0 || l <= 0 || (algo == MPG_STRASSEN && (!tile || tile->depth < 1 || tile->depth > 3 ||
+                                                              m != n || n != l)) ||
+      (algo == MPG_OZAKI && (precision != 2 || !tile)) || algo < MPG_SIMPLE || algo > MPG_OZAKI)
+    return INFINITY;
+  mpg_tile t{};
+  if (tile) t = *tile;
+  return method_bound(in_limbs, precision, algo, t, pairs_mode, m, l);
+}
+
+extern "C" int mpg_select_method(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int in_limbs, int bits,
+                                 int* precision, int* algo, mpg_tile* tile, int* pairs_mode,
+                                 double* bound_bits, double* ms) {
+  if (!c) return MPG_ERR_ARG;
+  if (m <= 0 || n <= 0 || l <= 0 || (in_limbs != 1 && in_limbs != 2 && in_limbs != 4) || bits < 1 ||
+      !precision || !algo || !tile || !pairs_mode)
+    return mpg_fail(c, MPG_ERR_ARG, "bad method selection request");
+  struct Choice {
+    int prec, algo, pairs;
+    mpg_tile tile;
+  };
+  const double target = std::ldexp(1.0, -bits);
+  std::vector<Choice> feasible;
+  auto consider = [&](int prec, int a, mpg_tile t, int pairs) {
+    if (method_bound(in_limbs, prec, a, t, pairs, m, l) <= target) feasible.push_back({prec, a, pairs, t});
+  };
+  const bool square = m == n && n == l;
+  for (int prec : {2, 4}) {
+    consider(prec, MPG_BLOCK, mpg_tile{}, 0);
+    for (int d = 1; d <= (prec == 2 ? 3 : 2) && square && m >= (int64_t)64 << d; ++d) {
+      mpg_tile t{};
+      t.depth = d;
+      consider(prec, MPG_STRASSEN, t, 0);
+    }
+  }
+  for (int pairs : {0, 1})
+    for (int S = 1; S <= ozaki_max_slices(); ++S) {
+      mpg_tile t{};
+      t.slices = S;
+      if (method_bound(in_limbs, 2, MPG_OZAKI, t, pairs, m, l) <= target) {
+        consider(2, MPG_OZAKI, t, pairs);
+        break;
+      }
+    }
+  if (feasible.empty())
+    return mpg_fail(c, MPG_ERR_UNSUPPORTED, "no method's bound reaches %d bits", bits);
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  Scratch s;
+  if ((st = make_scratch(c, 4, m, n, l, s)) != MPG_OK) return st;
+  double best = INFINITY;
+  for (const Choice& ch : feasible) {
+    double t = 0.0;
+    st = time_median(c, 3, [&] {
+      if (ch.algo == MPG_OZAKI)
+        return in_limbs == 1
+                   ? mpgemm_ozaki_dd(c, m, n, l, s.A[0], l, s.B[0], n, s.C[0], s.C[1], n, ch.tile.slices,
+                                     ch.pairs)
+                   : mpgemm_dd_ozaki(c, m, n, l, s.A[0], s.A[1], l, s.B[0], s.B[1], n, s.C[0], s.C[1], n,
+                                     ch.tile.slices, ch.pairs);
+      return mpg_gemm_common(c, ch.prec, m, n, l, s.A, l, s.B, n, s.C, n, (mpg_algo)ch.algo, &ch.tile);
+    }, &t);
+    if (st == MPG_ERR_UNSUPPORTED) {
+      st = MPG_OK;
+      continue;
+    }
+    if (st != MPG_OK) break;
+    if (t < best) {
+      best = t;
+      *precision = ch.prec;
+      *algo = ch.algo;
+      *tile = ch.tile;
+      *pairs_mode = ch.pairs;
+      if (bound_bits) *bound_bits = -std::log2(method_bound(in_limbs, ch.prec, ch.algo, ch.tile, ch.pairs, m, l));
+    }
+  }
+  free_scratch(s);
+  if (st != MPG_OK) return st;
+  if (!(best < INFINITY)) return mpg_fail(c, MPG_ERR_UNSUPPORTED, "no feasible method ran");
+  if (ms) *ms = best;
+  return MPG_OK;
 }
 
 bool mpg_table_lookup(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l, int* algo,

@@ -81,6 +81,10 @@ _sig("mpgemm_ozaki_dd", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, 
 _sig("mpgemm_dd_ozaki", [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _ci, _ci])
 _sig("mpg_ozaki_slices_exact", [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(_ci)])
 _sig("mpg_ozaki_split", [_vp, _ci, _i64, _i64, _vp, _i64, _ci, _vp, _i64, _i64, _vp])
+_sig("mpg_method_bound", [_ci, _ci, _ci, ctypes.POINTER(mpg_tile), _ci, _i64, _i64, _i64], ctypes.c_double)
+_sig("mpg_select_method", [_vp, _i64, _i64, _i64, _ci, _ci, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                           ctypes.POINTER(mpg_tile), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double)])
 _sig("mpg_ozaki_slices_for_bits", [_ci, _ci])
 _sig("mpg_ozaki_tune", [_vp, _i64, _i64, _i64, _ci, _vp, _i64, _vp, _i64, ctypes.POINTER(ctypes.c_int),
                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)])
@@ -283,6 +287,15 @@ def ozaki_last_slices(ctx: Context) -> int:
     return int(_lib.mpg_ozaki_last_slices(ctx.handle))
 
 
+def method_bound(in_limbs, precision, algo, tile=None, mode="all", m=1, n=1, l=1) -> float:
+    """A-priori normwise bound of a method (units of l max|A| max|B|)."""
+    t = make_tile(tile)
+    return float(_lib.mpg_method_bound(int(in_limbs), _prec(precision),
+                                       ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
+                                       ctypes.byref(t) if t is not None else None,
+                                       1 if mode in ("triangle", 1) else 0, m, n, l))
+
+
 def ozaki_slices_for_bits(bits: int, mode: str = "all") -> int:
     """Fewest slices whose a-priori bound meets 2^-bits (0: unreachable)."""
     return int(_lib.mpg_ozaki_slices_for_bits(int(bits), 1 if mode in ("triangle", 1) else 0))
@@ -460,6 +473,19 @@ class Tuner:
         self.ctx.check(_lib.mpg_ozaki_tune(self.ctx.handle, m, n, l, int(bits), _ptr(A), lda, _ptr(B), ldb,
                                            ctypes.byref(S), ctypes.byref(pm), ctypes.byref(ms)), "mpg_ozaki_tune")
         return {"slices": S.value, "pairs": "triangle" if pm.value else "all", "ms": ms.value}
+
+    def select(self, m, n, l, bits, in_limbs=2):
+        """Fastest method whose a-priori normwise bound meets 2^-bits
+        (max |C - AB| <= 2^-bits l max|A| max|B|) for inputs of in_limbs."""
+        p, a, pm = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        t = mpg_tile()
+        bb, ms = ctypes.c_double(), ctypes.c_double()
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_select_method(self.ctx.handle, m, n, l, int(in_limbs), int(bits), ctypes.byref(p),
+                                              ctypes.byref(a), ctypes.byref(t), ctypes.byref(pm), ctypes.byref(bb),
+                                              ctypes.byref(ms)), "mpg_select_method")
+        return {"precision": p.value, "algo": a.value, "tile": t.as_dict(),
+                "pairs": "triangle" if pm.value else "all", "bound_bits": bb.value, "ms": ms.value}
 
     def table_set(self, precision, m, n, l, algo, tile=None):
         """Put a choice into the table MPG_AUTO follows."""

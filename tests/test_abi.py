@@ -82,3 +82,24 @@ def test_slices_for_bits_matches_oracle(lib):
         for bits in range(1, 285):
             assert M.ozaki_slices_for_bits(bits, mode) == ozaki.slices_for_bits(bits, mode), (bits, mode)
     assert M.ozaki_slices_for_bits(0) == 0 and lib.mpg_ozaki_slices_for_bits(50, 2) == 0
+
+
+def test_method_bounds_host_only(lib):
+    """The a-priori normwise bounds behind the accuracy-targeted choice (in
+    units of l max|A| max|B|), host only."""
+    import math
+    from paper_1710_01839_amd import mpgemm as M
+    inf = float("inf")
+    assert M.method_bound(2, "dd", "block", None, m=1024, n=1024, l=1024) == 2.0 ** -91
+    assert M.method_bound(2, "qd", "block", None, m=1024, n=1024, l=1024) == 2.0 ** -195
+    assert M.method_bound(4, "dd", "block", None, m=64, n=64, l=64) == 2.0 ** -95 + 2.0 ** -105
+    s1 = (18 * (128 ** 2 + 6 * 128) - 6 * 256) * 8 * 2.0 ** -104 / 256
+    assert math.isclose(M.method_bound(2, "dd", "strassen", {"depth": 1}, m=256, n=256, l=256), s1, rel_tol=1e-15)
+    assert M.method_bound(2, "dd", "strassen", {"depth": 1}, m=256, n=128, l=256) == inf   # square only
+    oz = 4 * 2.0 ** (3 - 8 * 14) + (4.1 * 27 * 27 + 2) * 2.0 ** -105
+    assert math.isclose(M.method_bound(2, "dd", "ozaki", {"slices": 14}, "all", 4096, 4096, 4096), oz, rel_tol=1e-15)
+    assert M.method_bound(4, "dd", "ozaki", {"slices": 14}, "all", 64, 64, 64) == inf        # no QD split
+    # truncation falls by 2^-8 per slice until the recombination term (which
+    # grows with the square of the 2S - 1 diagonals) takes over near 2^-94
+    b = [M.method_bound(1, "dd", "ozaki", {"slices": S}, "all", 512, 512, 512) for S in range(1, 16)]
+    assert all(x > y for x, y in zip(b[:11], b[1:11])) and 2.0 ** -96 < min(b) < 2.0 ** -92
