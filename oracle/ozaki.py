@@ -88,18 +88,18 @@ def split_cols(X: np.ndarray, f: np.ndarray, S: int):
     return [np.ascontiguousarray(x.T) for x in d], np.ascontiguousarray(y.T)
 
 
-def split_rows_dd(Xhi: np.ndarray, Xlo: np.ndarray, e: np.ndarray, S: int):
-    """Digit planes of the double-double values hi + lo scaled by
-    2^-(e_i + 2) per row, steps 2-3 in exact rational arithmetic (small
-    inputs only).  Returns the planes and the exact remainders r_S (object
-    array)."""
-    R, K = Xhi.shape
+def split_rows_limbs(X, e: np.ndarray, S: int):
+    """Digit planes of the multi-limb values X[0] + X[1] + ... (double-
+    double or quad-double) scaled by 2^-(e_i + 2) per row, steps 2-3 in
+    exact rational arithmetic (small inputs only).  Returns the planes and
+    the exact remainders r_S (object array)."""
+    R, K = X[0].shape
     T = [np.zeros((R, K), dtype=np.int64) for _ in range(S)]
     rem = np.empty((R, K), dtype=object)
     for i in range(R):
         scale = Fraction(2) ** int(-(e[i] + 2))
         for k in range(K):
-            r = (Fraction(float(Xhi[i, k])) + Fraction(float(Xlo[i, k]))) * scale
+            r = sum(Fraction(float(x[i, k])) for x in X) * scale
             for s in range(S):
                 v = 256 * r
                 d = int(v)             # toward zero
@@ -109,9 +109,18 @@ def split_rows_dd(Xhi: np.ndarray, Xlo: np.ndarray, e: np.ndarray, S: int):
     return signed_bytes(T), rem
 
 
-def split_cols_dd(Xhi: np.ndarray, Xlo: np.ndarray, f: np.ndarray, S: int):
-    D, rem = split_rows_dd(np.ascontiguousarray(Xhi.T), np.ascontiguousarray(Xlo.T), f, S)
+def split_rows_dd(Xhi: np.ndarray, Xlo: np.ndarray, e: np.ndarray, S: int):
+    """split_rows_limbs for double-double values hi + lo."""
+    return split_rows_limbs((Xhi, Xlo), e, S)
+
+
+def split_cols_limbs(X, f: np.ndarray, S: int):
+    D, rem = split_rows_limbs(tuple(np.ascontiguousarray(x.T) for x in X), f, S)
     return [np.ascontiguousarray(x.T) for x in D], rem.T
+
+
+def split_cols_dd(Xhi: np.ndarray, Xlo: np.ndarray, f: np.ndarray, S: int):
+    return split_cols_limbs((Xhi, Xlo), f, S)
 
 
 def slices_needed_rows(X: np.ndarray, e: np.ndarray) -> int:
@@ -133,8 +142,8 @@ def slices_needed_rows(X: np.ndarray, e: np.ndarray) -> int:
 
 def slices_exact(A, B) -> int:
     """Slices that make every digit expansion exact.  A, B: FP64 arrays or
-    (hi, lo) pairs; a pair needs the lowest set bit of either limb, against
-    the scale of the hi limbs."""
+    limb tuples (double-double, quad-double); a tuple needs the lowest set
+    bit of any limb, against the scale of the leading limbs."""
     Ap = A if isinstance(A, tuple) else (A,)
     Bp = B if isinstance(B, tuple) else (B,)
     e, f = row_exponents(Ap[0]), col_exponents(Bp[0])
@@ -180,26 +189,26 @@ def to_fraction(N, E0, idx) -> Fraction:
     return Fraction(int(N[idx])) * (Fraction(2) ** k)
 
 
-def ozaki_dd(A, B, S: int, mode: str = "all"):
-    """The split-precision product rounded to double-double, plus the exact
-    pieces (N, E0) of the value before rounding.  A, B: FP64 arrays or
-    (hi, lo) double-double pairs."""
+def ozaki_dd(A, B, S: int, mode: str = "all", out_limbs: int = 2):
+    """The split-precision product rounded to `out_limbs` limbs (2: double-
+    double, 4: quad-double), plus the exact pieces (N, E0) of the value
+    before rounding.  A, B: FP64 arrays or limb tuples."""
     if isinstance(A, tuple):
         e, f = row_exponents(A[0]), col_exponents(B[0])
-        DA, _ = split_rows_dd(A[0], A[1], e, S)
-        DB, _ = split_cols_dd(B[0], B[1], f, S)
+        DA, _ = split_rows_limbs(A, e, S)
+        DB, _ = split_cols_limbs(B, f, S)
     else:
         e, f = row_exponents(A), col_exponents(B)
         DA, _ = split_rows(A, e, S)
         DB, _ = split_cols(B, f, S)
     G = group_sums(DA, DB, S, mode)
     N, E0 = combine_exact(G, e, f)
-    hi = np.zeros(N.shape)
-    lo = np.zeros(N.shape)
+    C = tuple(np.zeros(N.shape) for _ in range(out_limbs))
     for idx in np.ndindex(N.shape):
-        h, l_ = exact.round_to_limbs(to_fraction(N, E0, idx), 2)
-        hi[idx], lo[idx] = h, l_
-    return (hi, lo), (N, E0)
+        limbs = exact.round_to_limbs(to_fraction(N, E0, idx), out_limbs)
+        for q in range(out_limbs):
+            C[q][idx] = limbs[q]
+    return C, (N, E0)
 
 
 def apriori_unit(S: int, mode: str = "all") -> float:

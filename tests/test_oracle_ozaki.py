@@ -185,3 +185,36 @@ def test_triangle_bound_term_is_attained(S):
     assert err == dropped
     term = ozaki.apriori_unit(S, "triangle") - ozaki.apriori_unit(S, "all")
     assert abs(float(dropped) - term) <= 2.0 ** -50 * term
+
+
+def test_qd_split_reduces_to_dd_split():
+    """Quad-double values whose limbs 2 and 3 are zero split digit for digit
+    like the double-double values of their first two limbs."""
+    hi, lo = inputs.dd_uniform(5, 7, 8)
+    e = ozaki.row_exponents(hi)
+    S = ozaki.slices_exact((hi, lo), (hi.T.copy(), lo.T.copy()))
+    D1, r1 = ozaki.split_rows_dd(hi, lo, e, S)
+    D2, r2 = ozaki.split_rows_limbs((hi, lo, np.zeros_like(hi), np.zeros_like(hi)), e, S)
+    assert all(np.array_equal(a, b) for a, b in zip(D1, D2))
+    assert all(x == y for x, y in zip(r1.flat, r2.flat))
+
+
+def test_qd_split_and_product_exact():
+    """Quad-double inputs: the exact slice count (about 212 bits below the
+    row scale, so 27 or more slices) reconstructs every element, and the
+    combination is exactly AB (against the integer definition)."""
+    A = inputs.qd_uniform(4, 6, 9)
+    B = inputs.qd_uniform(6, 3, 10)
+    S = ozaki.slices_exact(A, B)
+    assert S >= 27
+    e = ozaki.row_exponents(A[0])
+    D, rem = ozaki.split_rows_limbs(A, e, S)
+    for i in range(4):
+        for k in range(6):
+            v = sum(Fraction(int(D[s][i, k]), 256 ** (s + 1)) for s in range(S))
+            assert v * Fraction(2) ** int(e[i] + 2) == sum(Fraction(float(x[i, k])) for x in A)
+            assert rem[i, k] == 0
+    C, (N, E0) = ozaki.ozaki_dd(A, B, S, "all", out_limbs=4)
+    Ci, s = exact.matmul_exact(A, B)
+    for idx in np.ndindex(C[0].shape):
+        assert ozaki.to_fraction(N, E0, idx) == Fraction(int(Ci[idx]), 2 ** s)
