@@ -123,6 +123,56 @@ int mpgemm_qd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
               double* const C[4], int64_t ldc,
               mpg_algo algo, const mpg_tile* tile);
 
+/* ---- BLAS-style form: transposes, alpha / beta, complex DD ------------- */
+
+/* op(X): X, its transpose, or its conjugate transpose (the transpose for
+ * real matrices). */
+typedef enum { MPG_OP_N = 0, MPG_OP_T = 1, MPG_OP_C = 2 } mpg_op;
+
+/* C := alpha op(A) op(B) + beta C, the xGEMM form of the BLAS around the
+ * product of Eq. (1), in DD (precision 2) or QD (precision 4).  op(A) is
+ * m x k and op(B) is k x n: A is stored m x k (lda >= k) for MPG_OP_N and
+ * k x m (lda >= m) otherwise; B is stored k x n (ldb >= n) or n x k
+ * (ldb >= k).  A, B and C are arrays of `precision` limb-plane DEVICE
+ * pointers (leading limb first); alpha and beta are HOST arrays of
+ * `precision` limbs.  algo and tile choose the product as for mpgemm_dd /
+ * mpgemm_qd (MPG_OZAKI with precision 2 only).
+ *   - beta == 0: C is not read (NaN in C does not propagate).
+ *   - alpha == 0 or k == 0: A and B are not read; C := beta C.
+ *   - transposed operands are copied to workspace by an O(mk + kn) pack
+ *     kernel; unless alpha == 1 and beta == 0 the product goes to workspace
+ *     and an element-wise kernel forms alpha T + beta C.
+ * Error (SIMPLE, BLOCK): |C' - (alpha op(A) op(B) + beta C)|_ij <=
+ *   2^-104 [(8k + 16) |alpha| (|op(A)||op(B)|)_ij + 16 |beta| |C_ij|]
+ * with 2^-208 for QD; other algorithms add their own product bound scaled
+ * by |alpha|.  C must not overlap A or B (MPG_ERR_ALIAS). */
+int mpg_rgemm(mpg_ctx* ctx, int precision, mpg_op transa, mpg_op transb,
+              int64_t m, int64_t n, int64_t k, const double* alpha,
+              const double* const* A, int64_t lda,
+              const double* const* B, int64_t ldb, const double* beta,
+              double* const* C, int64_t ldc, mpg_algo algo, const mpg_tile* tile);
+
+/* Complex double-double C := alpha op(A) op(B) + beta C (op: MPG_OP_N,
+ * MPG_OP_T, MPG_OP_C).  Each complex matrix is four limb-plane DEVICE
+ * pointers {re hi, re lo, im hi, im lo} with one leading dimension; alpha and
+ * beta are HOST arrays in the same order.  Storage shapes and leading
+ * dimensions as for mpg_rgemm; m, n, k <= 2^30.
+ * The four real products are formed in one real DD product of the embedding
+ *   [Re op(A)  Im op(A)] . [[Re op(B), Im op(B)], [-Im op(B), Re op(B)]]
+ * (m x 2k times 2k x 2n, packed in workspace, conjugation folded into the
+ * pack), so each real and imaginary part accumulates its 2k terms in one DD
+ * accumulator; algo and tile apply to that product (MPG_OZAKI allowed).
+ * An element-wise kernel forms alpha P + beta C.  beta == 0: C not read;
+ * alpha == 0 or k == 0: C := beta C.
+ * Error (SIMPLE, BLOCK), both parts:
+ *   2^-104 [(16k + 32)(|ar| + |ai|) ((|Ar| + |Ai|)(|Br| + |Bi|))_ij
+ *           + 32 (|br| + |bi|)(|Cr| + |Ci|)_ij]. */
+int mpg_zgemm_dd(mpg_ctx* ctx, mpg_op transa, mpg_op transb,
+                 int64_t m, int64_t n, int64_t k, const double alpha[4],
+                 const double* const A[4], int64_t lda,
+                 const double* const B[4], int64_t ldb, const double beta[4],
+                 double* const C[4], int64_t ldc, mpg_algo algo, const mpg_tile* tile);
+
 /* ---- batches of uneven DD products ------------------------------------ */
 
 /* One problem C := A B of a batch (same conventions as mpgemm_dd). */

@@ -117,7 +117,7 @@ int mpg_launch(mpg_ctx* c, int kclass, const std::function<hipError_t()>& fn, co
   return MPG_OK;
 }
 
-static bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+bool mpg_overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
   if (!a || !b || abytes == 0 || bbytes == 0) return false;
   const char* x = (const char*)a;
   const char* y = (const char*)b;
@@ -150,9 +150,9 @@ int mpg_check_gemm_args(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
                sc = mpg_span_bytes(m, n, ldc);
   for (int q = 0; q < limbs; ++q)
     for (int r = 0; r < limbs; ++r) {
-      if (overlaps(C[q], sc, A[r], sa) || overlaps(C[q], sc, B[r], sb))
+      if (mpg_overlaps(C[q], sc, A[r], sa) || mpg_overlaps(C[q], sc, B[r], sb))
         return mpg_fail(c, MPG_ERR_ALIAS, "C limb %d overlaps an input", q);
-      if (q < r && overlaps(C[q], sc, C[r], sc))
+      if (q < r && mpg_overlaps(C[q], sc, C[r], sc))
         return mpg_fail(c, MPG_ERR_ALIAS, "C limbs %d and %d overlap", q, r);
     }
   return MPG_OK;

@@ -22,10 +22,11 @@ struct mpg_ctx {
 
   // workspace slots (grow-only, freed with the context): 0 = large operand
   // workspace (Strassen blocks, digit planes), 1 = small (exponents, counters)
-  // 2, 3 = batch descriptors (two calls in flight)
-  static constexpr int kSlots = 4;
-  void* ws[kSlots] = {nullptr, nullptr, nullptr, nullptr};
-  size_t ws_size[kSlots] = {0, 0, 0, 0};
+  // 2, 3 = batch descriptors (two calls in flight), 4, 5 = packed operands
+  // of the BLAS-style calls, 6 = their product before scaling
+  static constexpr int kSlots = 7;
+  void* ws[kSlots] = {};
+  size_t ws_size[kSlots] = {};
   // batch descriptor uploads: pinned host staging per descriptor slot, and
   // an event after the launch that read it (the slot is free again once it
   // has completed)
@@ -65,6 +66,7 @@ int mpg_device_guard(mpg_ctx* c);
 int mpg_workspace(mpg_ctx* c, int slot, size_t bytes, void** out);
 int mpg_launch(mpg_ctx* c, int kclass, const std::function<hipError_t()>& fn, const char* what);
 size_t mpg_span_bytes(int64_t rows, int64_t cols, int64_t ld);
+bool mpg_overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
 int mpg_check_gemm_args(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
                         const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
                         double* const* C, int64_t ldc);

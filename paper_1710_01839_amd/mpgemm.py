@@ -57,6 +57,7 @@ _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _ci = ctypes.c_int
 _pp = ctypes.POINTER(ctypes.c_void_p)
+_pd = ctypes.POINTER(ctypes.c_double)
 
 
 def _sig(name, args, res=ctypes.c_int):
@@ -89,6 +90,10 @@ _sig("mpg_ozaki_slices_for_bits", [_ci, _ci])
 _sig("mpg_ozaki_tune", [_vp, _i64, _i64, _i64, _ci, _vp, _i64, _vp, _i64, ctypes.POINTER(ctypes.c_int),
                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)])
 _sig("mpg_ozaki_last_slices", [_vp])
+_sig("mpg_rgemm", [_vp, _ci, _ci, _ci, _i64, _i64, _i64, _pd, _pp, _i64, _pp, _i64, _pd, _pp, _i64,
+                   _ci, ctypes.POINTER(mpg_tile)])
+_sig("mpg_zgemm_dd", [_vp, _ci, _ci, _i64, _i64, _i64, _pd, _pp, _i64, _pp, _i64, _pd, _pp, _i64,
+                      _ci, ctypes.POINTER(mpg_tile)])
 _sig("mpgemm_dd_batched", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile)])
 _sig("mpg_batch_plan_create", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile),
                                ctypes.POINTER(_vp)])
@@ -246,6 +251,83 @@ def mpgemm_qd(ctx: Context, A, B, C, algo="block", tile=None):
                         ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
                         ctypes.byref(t) if t is not None else None)
     ctx.check(st, "mpgemm_qd")
+    return C
+
+
+OPS = {"N": 0, "T": 1, "C": 2}
+
+
+def _planes(X, count: int, name: str):
+    """Shape and common leading dimension of `count` limb planes."""
+    if len(X) != count:
+        raise MpgemmError(MPG_ERR_ARG, f"{name} needs {count} planes")
+    r, c, ld = _mat(X[0], f"{name}[0]")
+    for q in range(1, count):
+        if _mat(X[q], f"{name}[{q}]") != (r, c, ld):
+            raise MpgemmError(MPG_ERR_ARG, f"{name} planes differ in shape or leading dimension")
+    return r, c, ld
+
+
+def _scalar(x, count: int):
+    v = [float(x)] if isinstance(x, (int, float)) else [float(y) for y in x]
+    v = (v + [0.0] * count)[:count]
+    return (ctypes.c_double * count)(*v)
+
+
+def _op_shape(r, c, trans):
+    return (r, c) if trans == "N" else (c, r)
+
+
+def rgemm(ctx: Context, A, B, C, alpha=1.0, beta=0.0, transa="N", transb="N", algo="block",
+          tile=None):
+    """C := alpha op(A) op(B) + beta C in DD (2-tuples of planes) or QD
+    (4-tuples).  alpha, beta: a float or a sequence of limbs.  transa,
+    transb: 'N', 'T' or 'C' (the transpose for real matrices)."""
+    L = len(C)
+    mc, nc, ldc = _planes(C, L, "C")
+    ar, ac, lda = _planes(A, L, "A")
+    br, bc, ldb = _planes(B, L, "B")
+    m, k = _op_shape(ar, ac, transa)
+    k2, n = _op_shape(br, bc, transb)
+    if (m, n) != (mc, nc) or k != k2:
+        raise MpgemmError(MPG_ERR_ARG, "shape mismatch")
+    pa, ka = _limb_array(A)
+    pb, kb = _limb_array(B)
+    pc, kc = _limb_array(C)
+    t = make_tile(tile)
+    ctx.bind_stream()
+    st = _lib.mpg_rgemm(ctx.handle, L, OPS[transa], OPS[transb], m, n, k,
+                        ctypes.cast(_scalar(alpha, L), _pd), pa, lda, pb, ldb,
+                        ctypes.cast(_scalar(beta, L), _pd), pc, ldc,
+                        ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
+                        ctypes.byref(t) if t is not None else None)
+    ctx.check(st, "mpg_rgemm")
+    return C
+
+
+def zgemm_dd(ctx: Context, A, B, C, alpha=(1.0, 0.0, 0.0, 0.0), beta=(0.0, 0.0, 0.0, 0.0),
+             transa="N", transb="N", algo="block", tile=None):
+    """Complex DD C := alpha op(A) op(B) + beta C.  Each matrix is a 4-tuple
+    (re hi, re lo, im hi, im lo) of planes; alpha, beta are 4 limbs in the
+    same order.  transa, transb: 'N', 'T' or 'C' (conjugate transpose)."""
+    mc, nc, ldc = _planes(C, 4, "C")
+    ar, ac, lda = _planes(A, 4, "A")
+    br, bc, ldb = _planes(B, 4, "B")
+    m, k = _op_shape(ar, ac, transa)
+    k2, n = _op_shape(br, bc, transb)
+    if (m, n) != (mc, nc) or k != k2:
+        raise MpgemmError(MPG_ERR_ARG, "shape mismatch")
+    pa, ka = _limb_array(A)
+    pb, kb = _limb_array(B)
+    pc, kc = _limb_array(C)
+    t = make_tile(tile)
+    ctx.bind_stream()
+    st = _lib.mpg_zgemm_dd(ctx.handle, OPS[transa], OPS[transb], m, n, k,
+                           ctypes.cast(_scalar(alpha, 4), _pd), pa, lda, pb, ldb,
+                           ctypes.cast(_scalar(beta, 4), _pd), pc, ldc,
+                           ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
+                           ctypes.byref(t) if t is not None else None)
+    ctx.check(st, "mpg_zgemm_dd")
     return C
 
 
