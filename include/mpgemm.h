@@ -55,8 +55,10 @@ typedef enum {
   MPG_SIMPLE = 1,   /* Eq. (1): one thread per c_ij, k in order */
   MPG_BLOCK = 2,    /* Eq. (2): LDS-staged tiles, register-blocked accumulators */
   MPG_STRASSEN = 3, /* Eq. (3), Winograd's form, `depth` levels over MPG_BLOCK */
-  MPG_OZAKI = 4     /* split-precision INT8 product (DD only: mpgemm_dd_ozaki with
+  MPG_OZAKI = 4,    /* split-precision INT8 product (DD only: mpgemm_dd_ozaki with
                        tile->slices, all pairs) */
+  MPG_OZAKI_CRT = 5 /* its residue form (DD only: mpgemm_dd_ozaki with tile->slices,
+                       pairs_mode 2) */
 } mpg_algo;
 
 /* Tile / algorithm parameters.  Zero fields mean "library default" (DD:
@@ -226,9 +228,21 @@ int mpg_batch_plan_destroy(mpg_batch_plan* plan);
  *              With the exact count and pairs_mode 0 the only rounding is
  *              the double-double recombination, so the result meets the
  *              DD bound 8 l 2^-104 (|A||B|)_ij.
- *   pairs_mode 0: all slices^2 digit-plane pairs; 1: only s + t <= slices + 1.
+ *   pairs_mode 0: all slices^2 digit-plane pairs; 1: only s + t <= slices + 1;
+ *              2: the residue (Chinese remainder) form: the integer images
+ *              A'_ik = sum of the row's digits (|A'_ik| < 2^(8 slices - 2)),
+ *              likewise B', are reduced modulo the N leading moduli of
+ *              {256, 255, 253, 251, 247, 241, ...} (pairwise coprime, taken
+ *              greedily from 256 down; residues are signed bytes), N chosen
+ *              so that their product P exceeds 2 l 2^(16 slices - 4); one
+ *              INT8 product per modulus (N products instead of slices^2),
+ *              each reduced modulo its modulus; the exact integer product
+ *              X = (A' B')_ij is rebuilt by the Chinese remainder theorem in
+ *              32-bit words and C_ij = X 2^(e_i + f_j + 4 - 16 slices) is
+ *              rounded to double-double once (no recombination error).
+ *              slices <= 20; any l (sums reduced every 2047 K steps).
  * With fewer slices the truncation error is below
- * l 2^(e_i + f_j) 2^(3 - 8 slices) per entry (pairs_mode 0).
+ * l 2^(e_i + f_j) 2^(3 - 8 slices) per entry (pairs_mode 0 and 2).
  * Up to 24 slices any l (the INT32 sums are flushed every 2048 / slices
  * K steps of 64); above 24 slices l <= 32704.  C_hi/C_lo must not overlap
  * A, B. */
@@ -251,6 +265,13 @@ int mpgemm_dd_ozaki(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
                     const double* A_hi, const double* A_lo, int64_t lda,
                     const double* B_hi, const double* B_lo, int64_t ldb,
                     double* C_hi, double* C_lo, int64_t ldc, int slices, int pairs_mode);
+
+/* Moduli of the last pairs_mode 2 product on this context (0 if none). */
+int mpg_ozaki_last_moduli(const mpg_ctx* ctx);
+/* Moduli a pairs_mode 2 product of `slices` slices and inner dimension l
+ * uses (0 if slices is outside 1..20 or the product is too wide).  Host
+ * only. */
+int mpg_crt_moduli_for(int slices, int64_t l);
 
 /* The slice count that makes the digit planes of A's rows and B's columns
  * exact (the count slices = 0 would use).  Synchronises the stream. */

@@ -443,10 +443,10 @@ int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
       algo = MPG_BLOCK;
     }
   }
-  if (algo == MPG_OZAKI) {
+  if (algo == MPG_OZAKI || algo == MPG_OZAKI_CRT) {
     if (limbs != 2) return mpg_fail(c, MPG_ERR_UNSUPPORTED, "the split-precision product is DD only");
     return mpgemm_dd_ozaki(c, m, n, l, A[0], A[1], lda, B[0], B[1], ldb, C[0], C[1], ldc,
-                           chosen.slices, 0);
+                           chosen.slices, algo == MPG_OZAKI_CRT ? 2 : 0);
   }
   int variant = 0;
   st = mpg_resolve_variant(c, limbs, &chosen, &variant);

@@ -23,8 +23,10 @@ struct mpg_ctx {
   // workspace slots (grow-only, freed with the context): 0 = large operand
   // workspace (Strassen blocks, digit planes), 1 = small (exponents, counters)
   // 2, 3 = batch descriptors (two calls in flight), 4, 5 = packed operands
-  // of the BLAS-style calls, 6 = their product before scaling
-  static constexpr int kSlots = 7;
+  // of the BLAS-style calls, 6 = their product before scaling, 7 = residue
+  // planes of the residue-form split product, 8 = its product residues and
+  // reconstruction table
+  static constexpr int kSlots = 9;
   void* ws[kSlots] = {};
   size_t ws_size[kSlots] = {};
   // batch descriptor uploads: pinned host staging per descriptor slot, and
@@ -55,6 +57,7 @@ struct mpg_ctx {
 
   // slice count used by the last split-precision product
   int last_slices = 0;
+  int last_moduli = 0;  // moduli of the last residue-form product
 
   // learned time model (owned)
   mpg_mlp_state* mlp = nullptr;

@@ -1,0 +1,404 @@
+// Residue (Chinese remainder) form of the split product: the reconstruction
+// table, the residue planes of the integer images and the rebuild of the
+// exact integer product from its residues.
+#include <cmath>
+
+#include "crt_internal.hpp"
+#include "mp_arith.hpp"
+
+namespace mpg {
+namespace {
+
+// ---------------------------------------------------------------------
+// Table: one thread per modulus j forms M_j = prod_{i != j} p_i in 32-bit
+// words, y_j = M_j^-1 mod p_j (extended Euclid on M_j mod p_j) and
+// T_j = M_j y_j (< P, no reduction needed).  Thread 0 also writes P, P / 2
+// and P as a double.
+// ---------------------------------------------------------------------
+__device__ int inverse_mod(int a, int p) {
+  int r0 = p, r1 = a, t0 = 0, t1 = 1;
+  while (r1 != 0) {
+    const int q = r0 / r1;
+    int tmp = r0 - q * r1;
+    r0 = r1;
+    r1 = tmp;
+    tmp = t0 - q * t1;
+    t0 = t1;
+    t1 = tmp;
+  }
+  return t0 < 0 ? t0 + p : t0;  // r0 == 1 for coprime a, p
+}
+
+__device__ void mul_small(uint32_t (&x)[kCrtMaxWords], uint32_t k) {
+  uint64_t carry = 0;
+#pragma unroll
+  for (int w = 0; w < kCrtMaxWords; ++w) {
+    const uint64_t t = (uint64_t)x[w] * k + carry;
+    x[w] = (uint32_t)t;
+    carry = t >> 32;
+  }
+}
+
+__global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t) {
+  const int j = threadIdx.x;
+  if (j < N) {
+    const int pj = kCrtModuli[j];
+    uint32_t M[kCrtMaxWords] = {1};
+    int mmod = 1;
+    for (int i = 0; i < N; ++i)
+      if (i != j) {
+        mul_small(M, (uint32_t)kCrtModuli[i]);
+        mmod = (int)((int64_t)mmod * (kCrtModuli[i] % pj) % pj);
+      }
+    mul_small(M, (uint32_t)inverse_mod(mmod, pj));
+    for (int w = 0; w < kCrtMaxWords; ++w) t->T[j][w] = M[w];
+  }
+  if (j == 0) {
+    uint32_t P[kCrtMaxWords] = {1};
+    for (int i = 0; i < N; ++i) mul_small(P, (uint32_t)kCrtModuli[i]);
+    double pd = 0.0;
+    for (int w = kCrtMaxWords - 1; w >= 0; --w) {
+      t->P[w] = P[w];
+      // P is even: halving shifts each word right, taking the next word's
+      // lowest bit
+      const uint32_t up = w + 1 < kCrtMaxWords ? P[w + 1] : 0u;
+      t->half[w] = (P[w] >> 1) | (up << 31);
+      pd += ldexp((double)P[w], 32 * w);
+    }
+    t->Pd = pd;
+    t->N = N;
+  }
+}
+
+// ---------------------------------------------------------------------
+// Residues of the integer images: a thread takes 8 consecutive bytes of the
+// digit planes (8 elements), folds each element's S digits into 40-bit words
+// (five digits per word, most significant first; every word is an exact
+// double) and, per modulus, sums word * (2^(40 w) mod p) exactly in double
+// (< 2^51), then reduces into [-p/2, p/2).
+// ---------------------------------------------------------------------
+constexpr int kCrtDigitsPerWord = 5;
+constexpr int kCrtImageWords = kCrtMaxSlices / kCrtDigitsPerWord;
+
+struct ResidueConsts {
+  double c[kCrtMaxModuli][kCrtImageWords];  // 2^(40 w) mod p_z, w from the least significant word
+};
+
+__global__ __launch_bounds__(256) void crt_residue_kernel(const int8_t* __restrict__ D, int S,
+                                                          int64_t plane, int N,
+                                                          int8_t* __restrict__ out,
+                                                          const ResidueConsts* __restrict__ rc) {
+  const int64_t chunks = plane / 8;
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < chunks;
+       x += (int64_t)gridDim.x * 256) {
+    // words[w][b]: word w (0 = least significant) of element b
+    double words[kCrtImageWords][8];
+#pragma unroll
+    for (int w = 0; w < kCrtImageWords; ++w)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) words[w][b] = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const uint64_t v = *reinterpret_cast<const uint64_t*>(D + (int64_t)s * plane + 8 * x);
+      const int pos = S - 1 - s;  // power of 256 of digit s
+      const int w = pos / kCrtDigitsPerWord;
+      const double wt = (double)(1ull << (8 * (pos % kCrtDigitsPerWord)));
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const double d = (double)(int8_t)(v >> (8 * b));
+#pragma unroll
+        for (int ww = 0; ww < kCrtImageWords; ++ww)
+          if (ww == w) words[ww][b] = __builtin_fma(d, wt, words[ww][b]);
+      }
+    }
+    for (int z = 0; z < N; ++z) {
+      const int p = kCrtModuli[z];
+      const double pd = (double)p, inv = 1.0 / pd;
+      uint64_t packed = 0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        double acc = 0.0;  // words past the image's length are zero
+#pragma unroll
+        for (int w = 0; w < kCrtImageWords; ++w) acc = __builtin_fma(words[w][b], rc->c[z][w], acc);
+        double r = acc - floor(acc * inv) * pd;  // exact: |acc| < 2^51, r an integer
+        if (r >= pd) r -= pd;
+        if (r < 0.0) r += pd;
+        if (2.0 * r >= pd) r -= pd;              // into [-p/2, p/2)
+        packed |= (uint64_t)(uint8_t)(int8_t)(int)r << (8 * b);
+      }
+      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + 8 * x) = packed;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
+// Reconstruction: a thread takes four consecutive columns of one row.
+//   1. per 32-bit word w, sum_j r_j T_j[w] in a 64-bit accumulator (each
+//      term < 2^40, N <= 49 terms: no carries needed until the end), then
+//      one carry pass gives X' = sum_j r_j T_j < N 255 P < 2^(32 W);
+//   2. q = floor(X' / P) from doubles (X' / P < 2^14, relative error far
+//      below 2^-14), then Y = X' - q P by words; a negative Y or Y >= P is
+//      corrected by one addition or subtraction of P;
+//   3. centre: Y >= P / 2 stands for Y - P (negative, magnitude P - Y);
+//   4. the top five 32-bit words of the magnitude, each scaled exactly by
+//      2^(32 w + e_i + f_j + 4 - 16 S), are summed by TwoSum into a
+//      double-double (the dropped words are below 2^-96 of the top one).
+// ---------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void crt_one(const uint64_t (&acc)[W], const CrtTable& t, int scale,
+                                        double& hi, double& lo) {
+  uint32_t x[W];
+  uint64_t carry = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint64_t s = acc[w] + carry;
+    x[w] = (uint32_t)s;
+    carry = s >> 32;
+  }
+  double xd = 0.0;
+#pragma unroll
+  for (int w = W - 1; w >= 0; --w) xd += ldexp((double)x[w], 32 * w);
+  const uint32_t q = (uint32_t)floor(xd / t.Pd);
+  // Y = X' - q P
+  uint32_t y[W];
+  uint64_t mc = 0;
+  int64_t br = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint64_t qp = (uint64_t)q * t.P[w] + mc;
+    mc = qp >> 32;
+    const int64_t d = (int64_t)x[w] - (int64_t)(uint32_t)qp + br;
+    y[w] = (uint32_t)d;
+    br = d >> 32;  // 0 or -1
+  }
+  if (br < 0) {  // q one too large: add P back
+    uint64_t c = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t s = (uint64_t)y[w] + t.P[w] + c;
+      y[w] = (uint32_t)s;
+      c = s >> 32;
+    }
+  } else {
+    // Y >= P (q one too small): subtract P
+    bool ge = true;
+#pragma unroll
+    for (int w = W - 1; w >= 0; --w) {
+      if (y[w] != t.P[w]) {
+        ge = y[w] > t.P[w];
+        break;
+      }
+    }
+    if (ge) {
+      int64_t b2 = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int64_t d = (int64_t)y[w] - (int64_t)t.P[w] + b2;
+        y[w] = (uint32_t)d;
+        b2 = d >> 32;
+      }
+    }
+  }
+  // centre
+  bool neg = true;  // Y >= P / 2
+#pragma unroll
+  for (int w = W - 1; w >= 0; --w) {
+    if (y[w] != t.half[w]) {
+      neg = y[w] > t.half[w];
+      break;
+    }
+  }
+  if (neg) {  // magnitude P - Y
+    int64_t b2 = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int64_t d = (int64_t)t.P[w] - (int64_t)y[w] + b2;
+      y[w] = (uint32_t)d;
+      b2 = d >> 32;
+    }
+  }
+  int top = -1;
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (y[w] != 0) top = w;
+  hi = 0.0;
+  lo = 0.0;
+  if (top >= 0) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int w = top - k;
+      if (w >= 0) {
+        const double v = ldexp((double)y[w], 32 * w + scale);
+        double s, e;
+        two_sum(hi, v, s, e);
+        hi = s;
+        lo += e;
+      }
+    }
+    dd_renorm(hi, lo);
+    if (neg) {
+      hi = -hi;
+      lo = -lo;
+    }
+  }
+}
+
+struct RecArgs {
+  const uint8_t* R;
+  int64_t ldr, planeR;
+  int N;
+  const CrtTable* t;
+  const int* e;
+  const int* f;
+  int base;  // 4 - 16 S
+  int64_t m, n;
+  double* C_hi;
+  double* C_lo;
+  int64_t ldc;
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void crt_reconstruct_kernel(RecArgs a) {
+  const int64_t j0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
+  if (j0 >= a.n) return;
+  const CrtTable& t = *a.t;
+  int fj[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) fj[b] = j0 + b < a.n ? a.f[j0 + b] : 0;
+  for (int64_t i = blockIdx.y; i < a.m; i += gridDim.y) {
+    uint64_t acc[4][W];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[b][w] = 0;
+    const uint8_t* row = a.R + i * a.ldr + j0;
+    for (int z = 0; z < a.N; ++z) {
+      const uint32_t r4 = *reinterpret_cast<const uint32_t*>(row + (int64_t)z * a.planeR);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint32_t tw = t.T[z][w];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b][w] += (uint64_t)((r4 >> (8 * b)) & 0xffu) * tw;
+      }
+    }
+    const int ei = a.e[i];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (j0 + b < a.n) {
+        double hi, lo;
+        crt_one<W>(acc[b], t, ei + fj[b] + a.base, hi, lo);
+        a.C_hi[i * a.ldc + j0 + b] = hi;
+        a.C_lo[i * a.ldc + j0 + b] = lo;
+      }
+    }
+  }
+}
+
+__global__ void residue_consts_kernel(int N, ResidueConsts* rc) {
+  const int z = threadIdx.x;
+  if (z >= N) return;
+  const int p = kCrtModuli[z];
+  int c = 1;
+  for (int w = 0; w < kCrtImageWords; ++w) {
+    rc->c[z][w] = (double)c;
+    for (int k = 0; k < 40; ++k) c = (2 * c) % p;
+  }
+}
+
+}  // namespace
+
+int crt_product_bits(int S, int64_t l) {
+  int lb = 0;
+  while (lb < 62 && ((int64_t)1 << lb) < l) ++lb;  // bit length of l - 1 for l >= 1
+  return 16 * S - 4 + lb + 1;
+}
+
+int crt_moduli_for_bits(int bits) {
+  // product of the leading moduli in 32-bit words, compared with 2^bits
+  uint32_t P[kCrtMaxWords + 1] = {1};
+  for (int j = 0; j < kCrtMaxModuli; ++j) {
+    uint64_t carry = 0;
+    for (int w = 0; w <= kCrtMaxWords; ++w) {
+      const uint64_t t = (uint64_t)P[w] * (uint32_t)kCrtModuli[j] + carry;
+      P[w] = (uint32_t)t;
+      carry = t >> 32;
+    }
+    int top = 0;
+    for (int w = kCrtMaxWords; w >= 0; --w)
+      if (P[w]) {
+        top = 32 * w + 32 - __builtin_clz(P[w]);
+        break;
+      }
+    // P > 2^bits: a longer bit length, or the same length bits + 1 and P
+    // not a power of two (only the first modulus, 256, is one)
+    if (top > bits + 1 || (top == bits + 1 && j > 0))
+      return j + 1;
+  }
+  return 0;
+}
+
+int crt_words(int N) {
+  if (N < 1 || N > kCrtMaxModuli) return 0;
+  // bit length of N 255 P
+  uint32_t P[kCrtMaxWords + 1] = {1};
+  auto mul = [&](uint32_t k) {
+    uint64_t carry = 0;
+    for (int w = 0; w <= kCrtMaxWords; ++w) {
+      const uint64_t t = (uint64_t)P[w] * k + carry;
+      P[w] = (uint32_t)t;
+      carry = t >> 32;
+    }
+  };
+  for (int j = 0; j < N; ++j) mul((uint32_t)kCrtModuli[j]);
+  mul((uint32_t)(255 * N));
+  int bits = 0;
+  for (int w = kCrtMaxWords; w >= 0; --w)
+    if (P[w]) {
+      bits = 32 * w + 32 - __builtin_clz(P[w]);
+      break;
+    }
+  int W = (bits + 31) / 32;
+  W = W < 4 ? 4 : (W + 1) / 2 * 2;  // built: 4, 6, 8, 10, 12
+  return W <= kCrtMaxWords ? W : 0;
+}
+
+hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s) {
+  if (N < 1 || N > kCrtMaxModuli) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(crt_table_kernel, dim3(1), dim3(64), 0, s, N, t);
+  return hipGetLastError();
+}
+
+size_t crt_residue_consts_bytes() { return sizeof(ResidueConsts); }
+
+hipError_t launch_crt_residues(const int8_t* D, int S, int64_t plane, int N, int8_t* out,
+                               void* consts, hipStream_t s) {
+  if (S < 1 || S > kCrtMaxSlices || N < 1 || N > kCrtMaxModuli || plane % 8) return hipErrorInvalidValue;
+  if (plane <= 0) return hipSuccess;
+  ResidueConsts* rc = reinterpret_cast<ResidueConsts*>(consts);
+  hipLaunchKernelGGL(residue_consts_kernel, dim3(1), dim3(64), 0, s, N, rc);
+  const int64_t chunks = plane / 8;
+  const int64_t blocks = std::min<int64_t>((chunks + 255) / 256, 65536);
+  hipLaunchKernelGGL(crt_residue_kernel, dim3((unsigned)blocks), dim3(256), 0, s, D, S, plane, N, out,
+                     rc);
+  return hipGetLastError();
+}
+
+hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR, int N,
+                                  const CrtTable* t, const int* e, const int* f, int S, int64_t m,
+                                  int64_t n, double* C_hi, double* C_lo, int64_t ldc, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (ldr % 4 || ldr < n) return hipErrorInvalidValue;
+  RecArgs a{R, ldr, planeR, N, t, e, f, 4 - 16 * S, m, n, C_hi, C_lo, ldc};
+  const int64_t gx = ((n + 3) / 4 + 255) / 256;
+  const dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(m, 65535));
+  switch (crt_words(N)) {
+    case 4: hipLaunchKernelGGL(crt_reconstruct_kernel<4>, grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(crt_reconstruct_kernel<6>, grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(crt_reconstruct_kernel<8>, grid, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL(crt_reconstruct_kernel<10>, grid, dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL(crt_reconstruct_kernel<12>, grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mpg

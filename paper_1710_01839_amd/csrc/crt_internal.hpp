@@ -1,0 +1,80 @@
+// Internal interface of the residue (Chinese remainder) form of the split
+// product: the integer images of the operands (the sums of their S radix-256
+// digits) are multiplied modulo N small pairwise coprime moduli on INT8 MFMA,
+// and the exact integer product is rebuilt from the N residues.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpg {
+
+// Pairwise coprime moduli, taken greedily from 256 downwards (largest first,
+// so the first N carry the most bits).  Residues in [-p/2, p/2) fit a signed
+// byte.  Their product is about 2^341.9.
+constexpr int kCrtMaxModuli = 49;
+constexpr int kCrtModuli[kCrtMaxModuli] = {
+    256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199, 197, 193, 191,
+    181, 179, 173, 167, 163, 157, 151, 149, 139, 137, 131, 127, 113, 109, 107, 103, 101,
+    97,  89,  83,  79,  73,  71,  67,  61,  59,  53,  47,  43,  41,  37,  29};
+// 32-bit words of the reconstruction (N 255 P < 2^(32 W) with room for the
+// per-word sums); the largest supported product is 12 words.
+constexpr int kCrtMaxWords = 12;
+// Integer images hold at most this many digits (160 bits: four 40-bit words).
+constexpr int kCrtMaxSlices = 20;
+
+// Reconstruction table, built on the device for N moduli:
+//   T[j] = (P / p_j) * ((P / p_j)^-1 mod p_j) (so X = sum_j r_j T[j] mod P),
+//   P = prod p_j, half = P / 2 (P is even: 256 is the first modulus),
+//   Pd = P rounded to a double.
+struct CrtTable {
+  uint32_t T[kCrtMaxModuli][kCrtMaxWords];
+  uint32_t P[kCrtMaxWords];
+  uint32_t half[kCrtMaxWords];
+  double Pd;
+  int N;
+};
+
+// One INT8 product per modulus: residue planes z of A ([N][m_pad][l_pad],
+// K contiguous) and of B ([N][n_pad][l_pad]), padded as crt_tile_rows(),
+// crt_tile_cols() and crt_k_multiple() ask; output residues in [0, p_z) as
+// bytes, R[z * planeR + r * ldr + c].
+struct CrtGemmArgs {
+  int64_t m, n, l_pad;
+  const int8_t* A;
+  const int8_t* B;
+  int64_t planeA, planeB;
+  uint8_t* R;
+  int64_t ldr, planeR;
+  int N;
+  int mods[kCrtMaxModuli];
+};
+
+// Bits the integer product can need: |(A' B')_ij| < l 2^(16 S - 4), and the
+// symmetric range needs P > 2 max |X|.
+int crt_product_bits(int S, int64_t l);
+// Fewest leading moduli whose product exceeds 2^bits (0 if none).
+int crt_moduli_for_bits(int bits);
+// 32-bit words the reconstruction of N moduli uses (0 if unsupported).
+int crt_words(int N);
+
+hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s);
+// Residue planes of the digit planes D ([S][plane] bytes, plane a multiple
+// of 8): out[z * plane + x] = (sum_s D_s[x] 256^(S-1-s)) mod p_z in
+// [-p_z/2, p_z/2).
+// `consts` is device scratch of crt_residue_consts_bytes() (8-byte aligned)
+// for the per-modulus word weights 2^(40 w) mod p.
+size_t crt_residue_consts_bytes();
+hipError_t launch_crt_residues(const int8_t* D, int S, int64_t plane, int N, int8_t* out,
+                               void* consts, hipStream_t s);
+// Workgroup tile of the residue products: A's planes need rows padded to
+// crt_tile_rows(), B's to crt_tile_cols(), K to crt_k_multiple().
+int crt_tile_rows();
+int crt_tile_cols();
+int crt_k_multiple();
+hipError_t launch_crt_gemm(const CrtGemmArgs& a, hipStream_t s);
+// C_ij = X_ij 2^(e_i + f_j + 4 - 16 S), X the CRT value of the N residues.
+hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR, int N,
+                                  const CrtTable* t, const int* e, const int* f, int S, int64_t m,
+                                  int64_t n, double* C_hi, double* C_lo, int64_t ldc, hipStream_t s);
+
+}  // namespace mpg

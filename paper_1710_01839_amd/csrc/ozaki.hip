@@ -12,6 +12,7 @@
 
 #include "mp_arith.hpp"
 #include "ozaki_internal.hpp"
+#include "crt_internal.hpp"
 
 namespace mpg {
 namespace {
@@ -907,6 +908,139 @@ __global__ __launch_bounds__(256, 1) void ozaki_band_kernel(OzakiGemmArgs a, int
   if (numK == 0) flush(true, true);  // empty K: C := 0
 }
 
+// ---------------------------------------------------------------------
+// Residue form: one INT8 product per modulus.  Workgroup w (after the XCD
+// remap) takes modulus z = w / tiles and tile w % tiles, so the workgroups
+// of one XCD share one modulus' planes.  Every 2047 K steps the INT32 sums
+// are reduced into [0, p_z) (exact integer arithmetic; the quotient comes
+// from a double division that is exact except when the sum is a multiple
+// of p_z, which the range check repairs), and the final residues are
+// stored as bytes.
+// ---------------------------------------------------------------------
+__device__ __forceinline__ int crt_mod(int v, int p, double inv_p) {
+  int r = v - (int)floor((double)v * inv_p) * p;
+  if (r >= p) r -= p;
+  if (r < 0) r += p;
+  return r;
+}
+
+// Residue products on 256 x 128 workgroup tiles: with one digit pair per
+// product, operand reuse has to come from the tile.  Eight wavefronts
+// (4 x 2) each own a 64 x 64 block of outputs (4 x 4 MFMA blocks), so a
+// K step reads 8 fragments from LDS for 16 MFMAs per wavefront (the LDS
+// rate and the INT8 MFMA rate are matched at this size).  Each K step of
+// 64 is one LDS stage moved by the load unit as in the LDS-staged kernel;
+// NBUF stages form a ring, loads run NBUF - 1 stages ahead of the MFMAs
+// (a K step's compute is short next to the latency of an L2 miss).  Rows of
+// A's planes are padded to 256 and of B's to 128.
+constexpr int kCrtBM = 256, kCrtBN = 128;
+constexpr int kCrtNBA = kCrtBM / 16, kCrtNBB = kCrtBN / 16;
+
+template <int NBUF>
+__global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int tiles_m, int tiles_n,
+                                                          int kchunk) {
+  constexpr int STEP_BLOCKS = kCrtNBA + kCrtNBB;  // 24 KiB per K step
+  constexpr int STAGE = STEP_BLOCKS * 1024;
+  constexpr int LOADS = STEP_BLOCKS / 8;          // LDS loads per wavefront per stage
+  static_assert(LOADS * (NBUF - 2) <= 15, "vmcnt immediate");
+  __shared__ __attribute__((aligned(16))) int8_t lds[NBUF * STAGE];
+  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int tiles = tiles_m * tiles_n;
+  int tm, tn, z;
+  {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    z = w / tiles;
+    const int t = w - z * tiles;
+    constexpr int GR = 8;
+    const int per_group = GR * tiles_n;
+    const int group = t / per_group;
+    const int first = group * GR;
+    const int gsize = min(tiles_m - first, GR);
+    const int in = t - group * per_group;
+    tm = first + in % gsize;
+    tn = in / gsize;
+  }
+  const int p = c.mods[z];
+  const double inv_p = 1.0 / (double)p;
+  const int8_t* A = c.A + (int64_t)z * c.planeA;
+  const int8_t* B = c.B + (int64_t)z * c.planeB;
+  const int64_t lp = c.l_pad;
+  const int64_t m0 = (int64_t)tm * kCrtBM, n0 = (int64_t)tn * kCrtBN;
+  const int wr = wave / 2, wc = wave % 2;
+  const uint32_t lane_off = (uint32_t)((lane % 16) * lp + 16 * (lane / 16));
+
+  // K step `st` into its ring slot: blocks round-robin over the waves
+  auto issue = [&](int st) {
+    int8_t* dst = lds + (st % NBUF) * STAGE;
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int b = wave + 8 * i;
+      const int8_t* src = b < kCrtNBA ? A + (m0 + 16 * b) * lp : B + (n0 + 16 * (b - kCrtNBA)) * lp;
+      oz_dma(src, lane_off + (uint32_t)st * 64, dst + b * 1024);
+    }
+  };
+
+  v4i acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v4i{0, 0, 0, 0};
+
+  const int numK = (int)(lp / 64);
+#pragma unroll
+  for (int s = 0; s < NBUF - 1; ++s)
+    if (s < numK) issue(s);
+  for (int st = 0; st < numK; ++st) {
+    // this wave's loads of step st are done once at most the later steps'
+    // (up to NBUF - 2 of them) are outstanding; near the end fewer are
+    const int later = min(NBUF - 2, numK - 1 - st);
+    if (later >= NBUF - 2)
+      __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS * (NBUF - 2)));
+    else
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    // everyone's loads of st have landed; slot (st - 1) is free.  A plain
+    // barrier: __syncthreads() would add a fence that waits for every
+    // outstanding load, including the steps still in flight; the memory
+    // clobber keeps the compiler from moving LDS reads across it.
+    asm volatile("s_barrier" ::: "memory");
+    if (st + NBUF - 1 < numK) issue(st + NBUF - 1);
+    const int8_t* __restrict__ cur = lds + (st % NBUF) * STAGE;
+    v4i fa[4], fb[4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+      fa[bi] = *reinterpret_cast<const v4i*>(cur + (4 * wr + bi) * 1024 + 16 * lane);
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+      fb[bj] = *reinterpret_cast<const v4i*>(cur + (kCrtNBA + 4 * wc + bj) * 1024 + 16 * lane);
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[bi], fb[bj], acc[bi][bj], 0, 0, 0);
+    if ((st + 1) % kchunk == 0) {
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[bi][bj][i] = crt_mod(acc[bi][bj][i], p, inv_p);
+    }
+  }
+  uint8_t* R = c.R + (int64_t)z * c.planeR;
+  const int64_t r0 = m0 + 64 * wr, c0 = n0 + 64 * wc;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      const int64_t col = c0 + 16 * bj + lane % 16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = r0 + 16 * bi + 4 * (lane / 16) + i;
+        if (r < c.m && col < c.n) R[r * c.ldr + col] = (uint8_t)crt_mod(acc[bi][bj][i], p, inv_p);
+      }
+    }
+}
+
 struct OzKernels;
 
 template <int S>
@@ -1031,4 +1165,25 @@ hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+int crt_tile_rows() { return kCrtBM; }
+int crt_tile_cols() { return kCrtBN; }
+int crt_k_multiple() { return 64; }
+
+hipError_t launch_crt_gemm(const CrtGemmArgs& c, hipStream_t s) {
+  const int64_t tiles_m = (c.m + kCrtBM - 1) / kCrtBM, tiles_n = (c.n + kCrtBN - 1) / kCrtBN;
+  const int64_t total = tiles_m * tiles_n * c.N;
+  if (total <= 0) return hipSuccess;
+  if (total > 0x7fffffff || c.N > kCrtMaxModuli || c.l_pad % 64) return hipErrorInvalidValue;
+  constexpr int NBUF = 4;
+  // INT32 sums: |r r'| <= 128^2 per product, 64 per K step, plus the
+  // reduced residue carried over (< 256): reduce every 2047 K steps
+  const int kchunk = (int)((2147483647.0 - 256.0) / (64.0 * 128.0 * 128.0));
+  CrtGemmArgs args = c;
+  int tm = (int)tiles_m, tn = (int)tiles_n, kc = kchunk;
+  void* kargs[] = {(void*)&args, (void*)&tm, (void*)&tn, (void*)&kc};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&crt_tile_kernel<NBUF>), dim3((unsigned)total),
+                         dim3(512), kargs, 0, s);
+}
+
 }  // namespace mpg
+

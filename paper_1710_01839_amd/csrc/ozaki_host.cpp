@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "capi_internal.hpp"
+#include "crt_internal.hpp"
 #include "ozaki_internal.hpp"
 
 using namespace mpg;
@@ -108,6 +109,70 @@ extern "C" int mpg_ozaki_split(mpg_ctx* c, int side, int64_t rows, int64_t cols,
 
 namespace {
 
+// Residue form after the scales: digit planes (as for the digit form), their
+// residues modulo the N leading moduli, one INT8 product per modulus and
+// the reconstruction of the exact integer product.
+int crt_tail(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
+             int64_t lda, const double* B, const double* B_lo, int64_t ldb, double* C_hi,
+             double* C_lo, int64_t ldc, int S, const int* e, const int* f) {
+  const int N = crt_moduli_for_bits(crt_product_bits(S, l));
+  if (N == 0 || crt_words(N) == 0)
+    return mpg_fail(c, MPG_ERR_UNSUPPORTED, "product of %d slices at l = %lld is too wide for the moduli",
+                    S, (long long)l);
+  c->last_slices = S;
+  c->last_moduli = N;
+  // planes padded to the residue products' tile (the split kernels write
+  // zeros into the padding)
+  const int64_t lp = round_up(l, crt_k_multiple()), mp = round_up(m, crt_tile_rows()),
+                np = round_up(n, crt_tile_cols()), n4 = round_up(n, 4);
+  const int64_t planeA = mp * lp, planeB = np * lp;
+  const size_t cb = (crt_residue_consts_bytes() + 255) / 256 * 256;
+  void *big = nullptr, *res = nullptr, *out = nullptr;
+  int st;
+  if ((st = mpg_workspace(c, 0, (size_t)S * (size_t)(planeA + planeB), &big)) != MPG_OK ||
+      (st = mpg_workspace(c, 7, (size_t)N * (size_t)(planeA + planeB) + 2 * cb, &res)) != MPG_OK ||
+      (st = mpg_workspace(c, 8, (size_t)N * (size_t)(m * n4) + 256 + sizeof(CrtTable), &out)) != MPG_OK)
+    return st;
+  int8_t* Asl = (int8_t*)big;
+  int8_t* Bsl = Asl + (size_t)S * planeA;
+  int8_t* Ares = (int8_t*)res;
+  int8_t* Bres = Ares + (size_t)N * planeA;
+  char* consts = (char*)(Bres + (size_t)N * planeB);
+  uint8_t* R = (uint8_t*)out;
+  CrtTable* table = (CrtTable*)((char*)out + ((size_t)N * (size_t)(m * n4) + 255) / 256 * 256);
+  st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipError_t r = launch_ozaki_split_rows(A, A_lo, m, l, lda, e, S, Asl, lp, planeA, mp, lp, c->stream);
+    if (r != hipSuccess) return r;
+    r = launch_ozaki_split_cols(B, B_lo, l, n, ldb, f, S, Bsl, lp, planeB, np, lp, c->stream);
+    if (r != hipSuccess) return r;
+    r = launch_crt_table(N, table, c->stream);
+    if (r != hipSuccess) return r;
+    r = launch_crt_residues(Asl, S, planeA, N, Ares, consts, c->stream);
+    if (r != hipSuccess) return r;
+    return launch_crt_residues(Bsl, S, planeB, N, Bres, consts + cb, c->stream);
+  }, "digit split and residues");
+  if (st != MPG_OK) return st;
+  CrtGemmArgs g{};
+  g.m = m;
+  g.n = n;
+  g.l_pad = lp;
+  g.A = Ares;
+  g.B = Bres;
+  g.planeA = planeA;
+  g.planeB = planeB;
+  g.R = R;
+  g.ldr = n4;
+  g.planeR = m * n4;
+  g.N = N;
+  for (int j = 0; j < N; ++j) g.mods[j] = kCrtModuli[j];
+  st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_crt_gemm(g, c->stream); },
+                  "INT8 MFMA residue products");
+  if (st != MPG_OK) return st;
+  return mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    return launch_crt_reconstruct(R, n4, m * n4, N, table, e, f, S, m, n, C_hi, C_lo, ldc, c->stream);
+  }, "residue reconstruction");
+}
+
 // C := A B through the INT8 path; A_lo / B_lo (both or neither) make the
 // inputs double-double, each element split as one exact value.
 int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
@@ -121,7 +186,7 @@ int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, 
     return mpg_fail(c, MPG_ERR_ARG, "NULL lo limb");
   if (m == 0 || n == 0) return MPG_OK;
   if (!C_hi || !C_lo || ldc < n) return mpg_fail(c, MPG_ERR_ARG, "bad C");
-  if (pairs_mode != 0 && pairs_mode != 1) return mpg_fail(c, MPG_ERR_ARG, "pairs_mode must be 0 or 1");
+  if (pairs_mode < 0 || pairs_mode > 2) return mpg_fail(c, MPG_ERR_ARG, "pairs_mode must be 0, 1 or 2");
   if (slices < 0 || slices > ozaki_max_slices())
     return mpg_fail(c, MPG_ERR_ARG, "slices must be 0 (exact) .. %d", ozaki_max_slices());
   {
@@ -152,6 +217,12 @@ int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, 
     if (S > ozaki_max_slices())
       return mpg_fail(c, MPG_ERR_UNSUPPORTED, "exact slicing needs %d slices (max %d)", S,
                       ozaki_max_slices());
+  }
+  if (pairs_mode == 2) {
+    if (S > kCrtMaxSlices)
+      return mpg_fail(c, MPG_ERR_UNSUPPORTED, "the residue form holds at most %d slices (%d asked)",
+                      kCrtMaxSlices, S);
+    return crt_tail(c, m, n, l, A, A_lo, lda, B, B_lo, ldb, C_hi, C_lo, ldc, S, e, f);
   }
   // INT32 headroom of the general kernel (above ozaki_chunked_max_slices()
   // slices): SB pairs share a diagonal accumulator over the whole of K; the
@@ -210,6 +281,14 @@ extern "C" int mpgemm_dd_ozaki(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
 }
 
 extern "C" int mpg_ozaki_last_slices(const mpg_ctx* c) { return c ? c->last_slices : 0; }
+
+extern "C" int mpg_ozaki_last_moduli(const mpg_ctx* c) { return c ? c->last_moduli : 0; }
+
+extern "C" int mpg_crt_moduli_for(int slices, int64_t l) {
+  if (slices < 1 || slices > kCrtMaxSlices || l < 1) return 0;
+  const int N = crt_moduli_for_bits(crt_product_bits(slices, l));
+  return N > 0 && crt_words(N) > 0 ? N : 0;
+}
 
 // Bound on |x y - (kept digit products)|, in units of 2^(e + f), for
 // |x| < 2^e, |y| < 2^f cut into S radix-256 digits: both remainders are

@@ -24,10 +24,12 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 MPG_OK, MPG_ERR_ARG, MPG_ERR_UNSUPPORTED, MPG_ERR_HIP, MPG_ERR_NOMEM, MPG_ERR_ALIAS, MPG_ERR_STATE = \
     0, -1, -2, -3, -4, -5, -6
-MPG_AUTO, MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN, MPG_OZAKI = 0, 1, 2, 3, 4
+MPG_AUTO, MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN, MPG_OZAKI, MPG_OZAKI_CRT = 0, 1, 2, 3, 4, 5
 MPG_KCLASS_GEMM, MPG_KCLASS_AUX = 0, 1
 ALGOS = {"auto": MPG_AUTO, "simple": MPG_SIMPLE, "block": MPG_BLOCK,
-         "strassen": MPG_STRASSEN, "ozaki": MPG_OZAKI}
+         "strassen": MPG_STRASSEN, "ozaki": MPG_OZAKI, "ozaki_crt": MPG_OZAKI_CRT}
+# pairs_mode of the split product: all digit pairs, the triangle, the residue form
+PAIR_MODES = {"all": 0, "triangle": 1, "crt": 2}
 
 
 class mpg_tile(ctypes.Structure):
@@ -90,6 +92,8 @@ _sig("mpg_ozaki_slices_for_bits", [_ci, _ci])
 _sig("mpg_ozaki_tune", [_vp, _i64, _i64, _i64, _ci, _vp, _i64, _vp, _i64, ctypes.POINTER(ctypes.c_int),
                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)])
 _sig("mpg_ozaki_last_slices", [_vp])
+_sig("mpg_ozaki_last_moduli", [_vp])
+_sig("mpg_crt_moduli_for", [_ci, _i64])
 _sig("mpg_rgemm", [_vp, _ci, _ci, _ci, _i64, _i64, _i64, _pd, _pp, _i64, _pp, _i64, _pd, _pp, _i64,
                    _ci, ctypes.POINTER(mpg_tile)])
 _sig("mpg_zgemm_dd", [_vp, _ci, _ci, _i64, _i64, _i64, _pd, _pp, _i64, _pp, _i64, _pd, _pp, _i64,
@@ -342,7 +346,7 @@ def mpgemm_ozaki_dd(ctx: Context, A, B, C, slices: int = 0, mode: str = "all"):
         raise MpgemmError(MPG_ERR_ARG, "shape mismatch")
     ctx.bind_stream()
     st = _lib.mpgemm_ozaki_dd(ctx.handle, m, n, l, _ptr(A), lda, _ptr(B), ldb, _ptr(C[0]),
-                              _ptr(C[1]), ldc, int(slices), 1 if mode == "triangle" else 0)
+                              _ptr(C[1]), ldc, int(slices), PAIR_MODES.get(mode, mode))
     ctx.check(st, "mpgemm_ozaki_dd")
     return C
 
@@ -360,13 +364,22 @@ def mpgemm_dd_ozaki(ctx: Context, A, B, C, slices: int = 0, mode: str = "all"):
             raise MpgemmError(MPG_ERR_ARG, f"{nm} must share its hi limb's leading dimension")
     ctx.bind_stream()
     st = _lib.mpgemm_dd_ozaki(ctx.handle, m, n, l, _ptr(A[0]), _ptr(A[1]), lda, _ptr(B[0]), _ptr(B[1]),
-                              ldb, _ptr(C[0]), _ptr(C[1]), ldc, int(slices), 1 if mode == "triangle" else 0)
+                              ldb, _ptr(C[0]), _ptr(C[1]), ldc, int(slices), PAIR_MODES.get(mode, mode))
     ctx.check(st, "mpgemm_dd_ozaki")
     return C
 
 
 def ozaki_last_slices(ctx: Context) -> int:
     return int(_lib.mpg_ozaki_last_slices(ctx.handle))
+
+
+def ozaki_last_moduli(ctx: Context) -> int:
+    """Moduli of the last residue-form ('crt') product."""
+    return int(_lib.mpg_ozaki_last_moduli(ctx.handle))
+
+
+def crt_moduli_for(slices: int, l: int) -> int:
+    return int(_lib.mpg_crt_moduli_for(int(slices), int(l)))
 
 
 def method_bound(in_limbs, precision, algo, tile=None, mode="all", m=1, n=1, l=1) -> float:

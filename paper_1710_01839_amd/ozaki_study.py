@@ -32,6 +32,9 @@ def main():
     ap.add_argument("--slices", type=int, nargs="*", default=[8, 12, 15])
     ap.add_argument("--triangle", action="store_true",
                     help="also time each slice count with only the pairs s + t <= S + 1")
+    ap.add_argument("--crt", action="store_true",
+                    help="also time the residue (CRT) form at each slice count up to 20 (one INT8 "
+                         "product per modulus)")
     args = ap.parse_args()
 
     import torch
@@ -77,12 +80,17 @@ def main():
         runs = [(S, "all") for S in [0] + [s for s in args.slices if s < s_exact]]
         if args.triangle:
             runs += [(S, "triangle") for S in [s_exact] + [s for s in args.slices if s < s_exact]]
+        if args.crt:
+            runs += [(S, "crt") for S in [0] + [s for s in args.slices if s < s_exact]
+                     if (S or s_exact) <= 20]
         for S, mode in runs:
             wall, kms, aux = timed(lambda: product(S, mode))
             used = M.ozaki_last_slices(ctx)
-            npairs = used * used if mode == "all" else used * (used + 1) // 2
+            npairs = {"all": used * used, "triangle": used * (used + 1) // 2,
+                      "crt": M.ozaki_last_moduli(ctx)}[mode]
             tops = npairs * 2.0 * n ** 3 / (kms * 1e-3) / 1e12
             print(json.dumps({"kind": "ozaki", "n": n, "dist": args.dist, "slices": used, "pairs": mode,
+                              "int8_products": npairs,
                               "exact": S == 0, "wall_ms": round(wall, 3), "mfma_launch_ms": round(kms, 3),
                               "aux_ms": round(aux, 3), "int8_tops": round(tops, 1),
                               "frac_int8_peak": round(tops / INT8_PEAK_TOPS, 4),

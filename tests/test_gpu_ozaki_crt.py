@@ -1,0 +1,147 @@
+"""GPU parity of the residue (CRT) form of the split product against the
+oracle: the value of every entry within 2^-104 of the oracle's exact integer
+product of the integer images (the only rounding is the final conversion to
+double-double), exact results for integer data, K long enough for several
+reductions of the INT32 sums, the full-size workload on sampled entries, and
+the limits."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import crt, exact, ozaki
+from paper_1710_01839_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = Fraction(1, 2 ** 104)
+
+
+def run_crt(M, ctx, A, B, S):
+    """A, B: FP64 arrays or (hi, lo) tuples."""
+    dd = isinstance(A, tuple)
+    m, n = (A[0] if dd else A).shape[0], (B[0] if dd else B).shape[1]
+    C = M.empty_like_limbs(m, n, 2)
+    if dd:
+        M.mpgemm_dd_ozaki(ctx, M.to_device(A), M.to_device(B), C, S, "crt")
+    else:
+        M.mpgemm_ozaki_dd(ctx, torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda(), C, S, "crt")
+    torch.cuda.synchronize()
+    return M.to_host(C)
+
+
+def worst_relative(C, A, B, S):
+    """max over entries of |C - V| / (2^-104 |V|), V the oracle's exact value
+    X 2^(e_i + f_j + 4 - 16 S) (entries with V == 0 must be 0)."""
+    At = A if isinstance(A, tuple) else (A,)
+    Bt = B if isinstance(B, tuple) else (B,)
+    _, X, (e, f) = crt.crt_product(At, Bt, S)
+    worst = Fraction(0)
+    for idx in np.ndindex(X.shape):
+        i, j = idx
+        V = Fraction(int(X[idx])) * Fraction(2) ** (int(e[i]) + int(f[j]) + 4 - 16 * S)
+        got = Fraction(float(C[0][idx])) + Fraction(float(C[1][idx]))
+        if V == 0:
+            assert got == 0
+            continue
+        worst = max(worst, abs(got - V) / (REL * abs(V)))
+    return float(worst)
+
+
+@pytest.mark.parametrize("kind,S", [("dd", 0), ("dd", 3), ("dd", 9), ("uniform", 0), ("wide", 0),
+                                    ("wide", 5), ("illcond", 0)])
+def test_matches_oracle(gpu, kind, S):
+    """Ragged shapes spanning several 64-wide tiles; a zero row of A and a
+    zero column of B."""
+    M, ctx = gpu
+    m, n, l = 130, 98, 150
+    if kind == "dd":
+        A, B = inputs.dd_uniform(m, l, 80), inputs.dd_uniform(l, n, 81)
+    elif kind == "illcond":
+        A, B = inputs.dd_illcond(m, l, 82, kmax=12), inputs.dd_illcond(l, n, 83, kmax=12)
+    elif kind == "uniform":
+        A, B = inputs.dd_uniform(m, l, 84)[0], inputs.dd_uniform(l, n, 85)[0]
+    else:
+        A, B = inputs.fp64_wide(m, l, 86), inputs.fp64_wide(l, n, 87)
+    if isinstance(A, tuple):
+        A[0][5, :] = 0.0
+        A[1][5, :] = 0.0
+        B[0][:, 7] = 0.0
+        B[1][:, 7] = 0.0
+    else:
+        A[5, :] = 0.0
+        B[:, 7] = 0.0
+    C = run_crt(M, ctx, A, B, S)
+    used = M.ozaki_last_slices(ctx)
+    if S:
+        assert used == S
+    else:
+        assert used == ozaki.slices_exact(A if isinstance(A, tuple) else (A,),
+                                          B if isinstance(B, tuple) else (B,))
+    assert M.ozaki_last_moduli(ctx) == crt.moduli_for_bits(crt.product_bits(used, l))
+    r = worst_relative(C, A, B, used)
+    print(kind, S, "slices", used, "moduli", M.ozaki_last_moduli(ctx), "worst / 2^-104 |V|", r)
+    assert r <= 1.0
+
+
+def test_integer_data_exact_and_long_k(gpu):
+    """Integer entries in [-63, 63] with l = 140000 (several reductions of
+    the INT32 sums): the product is exact."""
+    M, ctx = gpu
+    g = np.random.default_rng(88)
+    m, n, l = 66, 70, 140000
+    A = g.integers(-63, 64, size=(m, l)).astype(np.float64)
+    B = g.integers(-63, 64, size=(l, n)).astype(np.float64)
+    A[:, 0] = 63.0     # row maxima 63 < 2^6: one slice holds every entry
+    B[0, :] = -63.0
+    C = run_crt(M, ctx, A, B, 1)
+    want = A.astype(np.int64) @ B.astype(np.int64)
+    assert np.array_equal(C[0], want.astype(np.float64)) and not C[1].any()
+
+
+def test_algo_enum_is_the_same_call(gpu):
+    M, ctx = gpu
+    A, B = inputs.dd_uniform(64, 96, 89), inputs.dd_uniform(96, 80, 90)
+    C1 = M.empty_like_limbs(64, 80, 2)
+    C2 = M.empty_like_limbs(64, 80, 2)
+    M.mpgemm_dd(ctx, M.to_device(A), M.to_device(B), C1, "ozaki_crt", {"slices": 0})
+    M.mpgemm_dd_ozaki(ctx, M.to_device(A), M.to_device(B), C2, 0, "crt")
+    torch.cuda.synchronize()
+    for p, q in zip(C1, C2):
+        assert torch.equal(p, q)
+
+
+def test_limits(gpu):
+    M, ctx = gpu
+    A = np.full((8, 8), 2.0 ** -200)
+    A[:, 0] = 1.0                    # 26 slices for exactness: beyond the residue form
+    B = np.eye(8)
+    C = M.empty_like_limbs(8, 8, 2)
+    with pytest.raises(M.MpgemmError) as ei:
+        M.mpgemm_ozaki_dd(ctx, torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda(), C, 0, "crt")
+    assert ei.value.status == M.MPG_ERR_UNSUPPORTED
+    with pytest.raises(M.MpgemmError):
+        M.mpgemm_ozaki_dd(ctx, torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda(), C, 21, "crt")
+    # 20 slices are accepted
+    M.mpgemm_ozaki_dd(ctx, torch.as_tensor(A).cuda(), torch.as_tensor(B).cuda(), C, 20, "crt")
+    torch.cuda.synchronize()
+    assert M.ozaki_last_moduli(ctx) == crt.moduli_for_bits(crt.product_bits(20, 8))
+
+
+def test_full_size_dd_sampled(gpu):
+    """m = n = l = 4096 double-double data with the exact slice count:
+    sampled entries against the exact product (2^-104 relative)."""
+    M, ctx = gpu
+    nn = 4096
+    A, B = inputs.dd_uniform(nn, nn, 91), inputs.dd_uniform(nn, nn, 92)
+    C = run_crt(M, ctx, A, B, 0)
+    S, N = M.ozaki_last_slices(ctx), M.ozaki_last_moduli(ctx)
+    print("n=4096 dd: slices", S, "moduli", N)
+    g = np.random.default_rng(93)
+    pairs = sorted({(0, 0), (nn - 1, nn - 1), *[(int(g.integers(nn)), int(g.integers(nn)))
+                                                for _ in range(10)]})
+    vals, _ = exact.entries_exact(A, B, pairs)
+    for (i, j), v in zip(pairs, vals):
+        got = Fraction(float(C[0][i, j])) + Fraction(float(C[1][i, j]))
+        assert abs(got - v) <= REL * abs(v), (i, j)
