@@ -924,22 +924,24 @@ __device__ __forceinline__ int crt_mod(int v, int p, double inv_p) {
   return r;
 }
 
-// Residue products on 256 x 128 workgroup tiles: with one digit pair per
+// Residue products on 256 x 256 workgroup tiles: with one digit pair per
 // product, operand reuse has to come from the tile.  Eight wavefronts
-// (4 x 2) each own a 64 x 64 block of outputs (4 x 4 MFMA blocks), so a
-// K step reads 8 fragments from LDS for 16 MFMAs per wavefront (the LDS
-// rate and the INT8 MFMA rate are matched at this size).  Each K step of
+// (4 x 2) each own a 64 x 128 block of outputs (4 x 8 MFMA blocks), so a
+// K step reads 12 fragments from LDS for 32 MFMAs per wavefront (below the
+// LDS rate the INT8 MFMA rate needs) and a workgroup moves 32 KiB per K
+// step for 256 MFMAs.  Each K step of
 // 64 is one LDS stage moved by the load unit as in the LDS-staged kernel;
 // NBUF stages form a ring, loads run NBUF - 1 stages ahead of the MFMAs
 // (a K step's compute is short next to the latency of an L2 miss).  Rows of
-// A's planes are padded to 256 and of B's to 128.
-constexpr int kCrtBM = 256, kCrtBN = 128;
+// A's and B's planes are padded to 256.
+constexpr int kCrtWN = 8;  // 16-column MFMA blocks per wavefront
+constexpr int kCrtBM = 256, kCrtBN = 32 * kCrtWN;
 constexpr int kCrtNBA = kCrtBM / 16, kCrtNBB = kCrtBN / 16;
 
 template <int NBUF>
 __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int tiles_m, int tiles_n,
                                                           int kchunk) {
-  constexpr int STEP_BLOCKS = kCrtNBA + kCrtNBB;  // 24 KiB per K step
+  constexpr int STEP_BLOCKS = kCrtNBA + kCrtNBB;  // 32 KiB per K step
   constexpr int STAGE = STEP_BLOCKS * 1024;
   constexpr int LOADS = STEP_BLOCKS / 8;          // LDS loads per wavefront per stage
   static_assert(LOADS * (NBUF - 2) <= 15, "vmcnt immediate");
@@ -980,11 +982,11 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
     }
   };
 
-  v4i acc[4][4];
+  v4i acc[4][kCrtWN];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v4i{0, 0, 0, 0};
+    for (int bj = 0; bj < kCrtWN; ++bj) acc[bi][bj] = v4i{0, 0, 0, 0};
 
   const int numK = (int)(lp / 64);
 #pragma unroll
@@ -1005,33 +1007,33 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
     asm volatile("s_barrier" ::: "memory");
     if (st + NBUF - 1 < numK) issue(st + NBUF - 1);
     const int8_t* __restrict__ cur = lds + (st % NBUF) * STAGE;
-    v4i fa[4], fb[4];
+    v4i fa[4], fb[kCrtWN];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
       fa[bi] = *reinterpret_cast<const v4i*>(cur + (4 * wr + bi) * 1024 + 16 * lane);
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
-      fb[bj] = *reinterpret_cast<const v4i*>(cur + (kCrtNBA + 4 * wc + bj) * 1024 + 16 * lane);
+    for (int bj = 0; bj < kCrtWN; ++bj)
+      fb[bj] = *reinterpret_cast<const v4i*>(cur + (kCrtNBA + kCrtWN * wc + bj) * 1024 + 16 * lane);
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj)
+      for (int bj = 0; bj < kCrtWN; ++bj)
         acc[bi][bj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[bi], fb[bj], acc[bi][bj], 0, 0, 0);
     if ((st + 1) % kchunk == 0) {
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+        for (int bj = 0; bj < kCrtWN; ++bj)
 #pragma unroll
           for (int i = 0; i < 4; ++i) acc[bi][bj][i] = crt_mod(acc[bi][bj][i], p, inv_p);
     }
   }
   uint8_t* R = c.R + (int64_t)z * c.planeR;
-  const int64_t r0 = m0 + 64 * wr, c0 = n0 + 64 * wc;
+  const int64_t r0 = m0 + 64 * wr, c0 = n0 + 16 * kCrtWN * wc;
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
+    for (int bj = 0; bj < kCrtWN; ++bj) {
       const int64_t col = c0 + 16 * bj + lane % 16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
