@@ -17,7 +17,9 @@ Also measured on the same GPU and reported in the same line:
                   so DD-class accuracy) against the plain DD kernel on the same
                   FP64 operands (U[-1,1] 2^round(N(0,10)), the split-precision
                   workload, and U[-1,1]; n = 4096) and on the DD workload
-                  above; INT8 MFMA roofline of its product launch;
+                  above; INT8 MFMA roofline of its product launch; and the
+                  same for its residue (Chinese remainder) form, one INT8
+                  product per modulus;
   tuning          wall-clock tuning time at n = 4096 (DD): exhaustive, the
                   paper's prediction procedure and MLP-pruned (top 3; the
                   model trained on exhaustive timings of smaller shapes), with
@@ -110,8 +112,15 @@ def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
             workload = f"double-double hi~U[-1,1], lo in hi's half-ulp, n={n}"
         oz_ms, oz_launch = timed(oz)
         S = M.ozaki_last_slices(ctx)
+        if name.startswith("fp64"):
+            crt = lambda: M.mpgemm_ozaki_dd(ctx, A, B, C, 0, "crt")
+        else:
+            crt = lambda: M.mpgemm_dd_ozaki(ctx, Ad, Bd, C, 0, "crt")
+        crt_ms, crt_launch = timed(crt)
+        N = M.ozaki_last_moduli(ctx)
         dd_ms, _ = timed(lambda: plain_step(Ad, Bd, C))
         tops = S * S * 2.0 * n ** 3 / (oz_launch * 1e-3) / 1e12
+        crt_tops = N * 2.0 * n ** 3 / (crt_launch * 1e-3) / 1e12
         out[name] = {"workload": workload, "slices": S, "pairs": "all", "ozaki_ms": round(oz_ms, 3),
                      "plain_dd_ms": round(dd_ms, 3), "speedup": round(dd_ms / oz_ms, 3),
                      "accuracy": "exact slicing: exact product up to the DD recombination "
@@ -119,7 +128,17 @@ def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
                      "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": INT8_PEAK_TOPS,
                                   "unit": "TOP/s (INT8)", "frac": round(tops / INT8_PEAK_TOPS, 4),
                                   "kernel": "INT8 MFMA digit-plane product",
-                                  "launch_ms": round(oz_launch, 3)}}
+                                  "launch_ms": round(oz_launch, 3)},
+                     "residue_form": {"moduli": N, "ms": round(crt_ms, 3),
+                                      "speedup_vs_plain": round(dd_ms / crt_ms, 3),
+                                      "speedup_vs_digit_form": round(oz_ms / crt_ms, 3),
+                                      "accuracy": "exact slicing: the exact product rounded once to "
+                                                  "double-double",
+                                      "roofline": {"bound": "mfma", "achieved": round(crt_tops, 1),
+                                                   "peak": INT8_PEAK_TOPS, "unit": "TOP/s (INT8)",
+                                                   "frac": round(crt_tops / INT8_PEAK_TOPS, 4),
+                                                   "kernel": "INT8 MFMA residue products",
+                                                   "launch_ms": round(crt_launch, 3)}}}
         del Ad, Bd
     return out
 

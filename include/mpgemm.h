@@ -323,7 +323,8 @@ typedef enum {
   MPG_TUNE_PAPER = 1,      /* the paper's procedure: (1) predict the block time of
                               every tile from a slab product, keep the best tile;
                               (2) time simple, block and Strassen over that tile
-                              (and, for DD, the MPG_OZAKI candidate);
+                              (and, for DD, the MPG_OZAKI and MPG_OZAKI_CRT
+                              candidates);
                               (3) take the fastest */
   MPG_TUNE_MLP = 2         /* the run-time model ranks every candidate; only the
                               best `topk` are timed, the fastest measured wins */
@@ -331,8 +332,9 @@ typedef enum {
 
 /* Candidates for a shape: MPG_SIMPLE, MPG_BLOCK with every built tile,
  * MPG_STRASSEN with every tile and depth 1..3 (DD) / 1..2 (QD) while the
- * leaves keep at least 64 per side, and last, for DD, MPG_OZAKI with
- * slices = 0 (exact slice count, all pairs).  precision: 2 (DD) or 4 (QD).
+ * leaves keep at least 64 per side, and last, for DD, MPG_OZAKI and
+ * MPG_OZAKI_CRT with slices = 0 (exact slice count; all pairs, residue
+ * form).  precision: 2 (DD) or 4 (QD).
  * The tuner times them on its own buffers: limb 0 uniform in (-1, 1), each
  * lower limb a uniform fraction of half an ulp of the limb above (the next
  * 53 bits of a random significand). */
@@ -358,15 +360,15 @@ int mpg_predict_block(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t
 
 /* Tune one shape; the winner also enters the context's table used by
  * MPG_AUTO.  topk: candidates timed in MLP mode (0: one per 12 candidates,
- * at least 2: 3 of the 34 DD candidates, 2 of the 13 QD ones).  Outputs (each
+ * at least 2: 3 of the 35 DD candidates, 2 of the 13 QD ones).  Outputs (each
  * nullable): winner, its median time, wall-clock seconds of the search
  * (trials, warm-ups, predictions and model inference), number of
  * full-size trials. */
 int mpg_tune(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l, int mode, int topk,
              int* best_algo, mpg_tile* best_tile, double* best_ms, double* seconds, int* trials);
 
-/* Put a choice into the table used by MPG_AUTO directly (MPG_OZAKI: DD
- * only, tile->slices as for mpgemm_dd_ozaki). */
+/* Put a choice into the table used by MPG_AUTO directly (MPG_OZAKI,
+ * MPG_OZAKI_CRT: DD only, tile->slices as for mpgemm_dd_ozaki). */
 int mpg_tune_table_set(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
                        int algo, const mpg_tile* tile);
 
@@ -384,7 +386,9 @@ int mpg_tune_table_set(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_
  *     4 x the truncation bound of mpg_ozaki_slices_for_bits (the row and
  *     column scales are below 2 max|a_i.| and 2 max|b_.j|) plus
  *     (4.1 T^2 + 2) 2^-105, T = (2S - 1) x chunks of K, for the
- *     double-double recombination.
+ *     double-double recombination; pairs_mode 2 (or algo MPG_OZAKI_CRT), the
+ *     residue form (slices <= 20): the all-pairs truncation bound x 4 plus
+ *     2^-104 for the single rounding of the exact kept product.
  * Host only. */
 double mpg_method_bound(int in_limbs, int precision, int algo, const mpg_tile* tile,
                         int pairs_mode, int64_t m, int64_t n, int64_t l);
@@ -395,7 +399,8 @@ double mpg_method_bound(int in_limbs, int precision, int algo, const mpg_tile* t
  * in_limbs limbs (1 FP64, 2 DD, 4 QD).  Candidates: DD and QD block (default
  * tile), Winograd-Strassen depth 1..3 (DD) / 1..2 (QD) for square shapes,
  * and the split INT8 product (FP64 or DD inputs) with the fewest slices
- * whose bound meets the target, all pairs and triangle.  Every candidate
+ * whose bound meets the target, all pairs, triangle and the residue form
+ * (*pairs_mode 0, 1, 2).  Every candidate
  * whose mpg_method_bound is within the target is timed at full size on
  * library buffers (median of 3); the fastest is returned: *precision (2:
  * call mpgemm_dd, or mpgemm_ozaki_dd / mpgemm_dd_ozaki for MPG_OZAKI with
@@ -411,8 +416,8 @@ int mpg_select_method(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l, int in_limb
 /* Features of one candidate (MPG_MLP_FEATURES floats): log2 m, n, l / 12;
  * DD and QD indicators; simple / block / Strassen indicators; log2 bm / 8,
  * log2 bn / 8, log2 bk / 5, tm tn / 64, Strassen depth / 3, log2 batch / 10;
- * split-precision indicator.  Target of the model: natural log of
- * milliseconds. */
+ * split product: 1 digit form, 2 residue form, else 0.  Target of the
+ * model: natural log of milliseconds. */
 #define MPG_MLP_FEATURES 15
 int mpg_mlp_features(int precision, int64_t m, int64_t n, int64_t l, int algo,
                      const mpg_tile* tile, int batch, float* out);

@@ -149,7 +149,7 @@ extern "C" int mpg_mlp_features(int precision, int64_t m, int64_t n, int64_t l, 
   f[11] = (float)(t.tm * t.tn) / 64.f;
   f[12] = (float)(algo == MPG_STRASSEN ? t.depth : 0) / 3.f;
   f[13] = (float)(lg((double)batch) / 10.0);
-  f[14] = algo == MPG_OZAKI ? 1.f : 0.f;
+  f[14] = algo == MPG_OZAKI ? 1.f : algo == MPG_OZAKI_CRT ? 2.f : 0.f;  // split product, residue form
   std::memcpy(out, f, sizeof f);
   return MPG_OK;
 }

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "capi_internal.hpp"
+#include "crt_internal.hpp"
 #include "ozaki_internal.hpp"
 
 using namespace mpg;
@@ -60,6 +61,8 @@ std::vector<Cand> candidates(int prec, int64_t m, int64_t n, int64_t l) {
     Cand z{};
     z.algo = MPG_OZAKI;
     z.tile.slices = 0;  // exact digit expansions, every slice pair
+    out.push_back(z);
+    z.algo = MPG_OZAKI_CRT;  // the same exact product through residues
     out.push_back(z);
   }
   return out;
@@ -189,7 +192,7 @@ void db_append(mpg_ctx* c, int prec, int64_t m, int64_t n, int64_t l, const Cand
                "\"kind\":\"%s\"}\n",
                prec, (long long)m, (long long)n, (long long)l, cd.algo, cd.tile.bm, cd.tile.bn,
                cd.tile.bk, cd.tile.tm, cd.tile.tn, cd.algo == MPG_STRASSEN ? cd.tile.depth : 0,
-               cd.algo == MPG_OZAKI ? cd.tile.slices : 0, ms, kind);
+               cd.algo == MPG_OZAKI || cd.algo == MPG_OZAKI_CRT ? cd.tile.slices : 0, ms, kind);
   std::fclose(f);
 }
 
@@ -357,7 +360,7 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
             cd.tile.bk == bt.bk && cd.tile.tm == bt.tm && cd.tile.tn == bt.tn)
           finals.push_back(cd);
       for (const auto& cd : cands)
-        if (cd.algo == MPG_OZAKI) finals.push_back(cd);
+        if (cd.algo == MPG_OZAKI || cd.algo == MPG_OZAKI_CRT) finals.push_back(cd);
       // (3) the fastest of them
       for (const auto& cd : finals)
         if ((st = trial(cd)) != MPG_OK) break;
@@ -396,8 +399,8 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
 
 extern "C" int mpg_tune_table_set(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l,
                                   int algo, const mpg_tile* tile) {
-  if (!c || (precision != 2 && precision != 4) || algo < MPG_SIMPLE || algo > MPG_OZAKI ||
-      (algo == MPG_OZAKI && precision != 2))
+  if (!c || (precision != 2 && precision != 4) || algo < MPG_SIMPLE || algo > MPG_OZAKI_CRT ||
+      ((algo == MPG_OZAKI || algo == MPG_OZAKI_CRT) && precision != 2))
     return MPG_ERR_ARG;
   mpg_tile t{};
   if (tile) t = *tile;
@@ -499,13 +502,19 @@ namespace {
 // at most T^2/2 2^-106 of the largest running sum; the running sums are
 // below the sum of the terms' magnitudes, at most 16.2 l max|A| max|B|
 // (signed-byte digits: sum_s |D_s| 256^-s <= 128/255, scales below
-// 4 max|a|, 4 max|b|); and the final rounding adds 2^-106 |C|.
+// 4 max|a|, 4 max|b|); and the final rounding adds 2^-106 |C|.  The
+// residue form (pairs 2) computes the kept product (the same as with all
+// pairs) exactly and rounds it once: the truncation bound plus 2^-104.
 double method_bound(int in_limbs, int prec, int algo, const mpg_tile& t, int pairs, int64_t m,
                     int64_t l) {
   const double L = (double)l;
   if (algo == MPG_OZAKI) {
     if (in_limbs > 2 || t.slices < 1) return INFINITY;
     const int S = t.slices;
+    if (pairs == 2)
+      return S <= kCrtMaxSlices && mpg_crt_moduli_for(S, l) > 0
+                 ? 4.0 * ozaki_unit_bound(S, 0) + std::ldexp(1.0, -104)
+                 : INFINITY;
     const double T = (double)(2 * S - 1) * ozaki_chunks(S, l);
     const double recomb = (4.1 * T * T + 2.0) * std::ldexp(1.0, -105);
     return 4.0 * ozaki_unit_bound(S, pairs) + recomb;
@@ -530,10 +539,13 @@ extern "C" double mpg_method_bound(int in_limbs, int precision, int algo, const 
   if ((in_limbs != 1 && in_limbs != 2 && in_limbs != 4) || (precision != 2 && precision != 4) ||
       m <= 0 || n <= 0 || l <= 0 || (algo == MPG_STRASSEN && (!tile || tile->depth < 1 || tile->depth > 3 ||
                                                               m != n || n != l)) ||
-      (algo == MPG_OZAKI && (precision != 2 || !tile)) || algo < MPG_SIMPLE || algo > MPG_OZAKI)
+      ((algo == MPG_OZAKI || algo == MPG_OZAKI_CRT) && (precision != 2 || !tile)) ||
+      algo < MPG_SIMPLE || algo > MPG_OZAKI_CRT)
     return INFINITY;
   mpg_tile t{};
   if (tile) t = *tile;
+  if (algo == MPG_OZAKI_CRT) return method_bound(in_limbs, precision, MPG_OZAKI, t, 2, m, l);
+  if (algo == MPG_OZAKI && (pairs_mode < 0 || pairs_mode > 2)) return INFINITY;
   return method_bound(in_limbs, precision, algo, t, pairs_mode, m, l);
 }
 
@@ -562,7 +574,7 @@ extern "C" int mpg_select_method(mpg_ctx* c, int64_t m, int64_t n, int64_t l, in
       consider(prec, MPG_STRASSEN, t, 0);
     }
   }
-  for (int pairs : {0, 1})
+  for (int pairs : {0, 1, 2})
     for (int S = 1; S <= ozaki_max_slices(); ++S) {
       mpg_tile t{};
       t.slices = S;

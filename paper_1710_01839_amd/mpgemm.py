@@ -388,7 +388,7 @@ def method_bound(in_limbs, precision, algo, tile=None, mode="all", m=1, n=1, l=1
     return float(_lib.mpg_method_bound(int(in_limbs), _prec(precision),
                                        ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
                                        ctypes.byref(t) if t is not None else None,
-                                       1 if mode in ("triangle", 1) else 0, m, n, l))
+                                       PAIR_MODES.get(mode, mode), m, n, l))
 
 
 def ozaki_slices_for_bits(bits: int, mode: str = "all") -> int:
@@ -580,7 +580,7 @@ class Tuner:
                                               ctypes.byref(a), ctypes.byref(t), ctypes.byref(pm), ctypes.byref(bb),
                                               ctypes.byref(ms)), "mpg_select_method")
         return {"precision": p.value, "algo": a.value, "tile": t.as_dict(),
-                "pairs": "triangle" if pm.value else "all", "bound_bits": bb.value, "ms": ms.value}
+                "pairs": ("all", "triangle", "crt")[pm.value], "bound_bits": bb.value, "ms": ms.value}
 
     def table_set(self, precision, m, n, l, algo, tile=None):
         """Put a choice into the table MPG_AUTO follows."""

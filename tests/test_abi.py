@@ -58,12 +58,12 @@ def test_tuner_host_logic(lib):
     nv_dd, nv_qd = lib.mpg_num_variants(2), lib.mpg_num_variants(4)
     # simple + every tile + every tile under each admissible Strassen depth,
     # and for DD the split-precision product with the exact slice count
-    assert len(M.candidates("dd", 4096, 4096, 4096)) == 1 + nv_dd * 4 + 1
+    assert len(M.candidates("dd", 4096, 4096, 4096)) == 1 + nv_dd * 4 + 2
     assert len(M.candidates("qd", 2048, 2048, 2048)) == 1 + nv_qd * 3
-    assert len(M.candidates("dd", 200, 200, 200)) == 1 + nv_dd * 2 + 1  # leaves >= 64: depth 1 only
-    assert len(M.candidates("dd", 100, 5000, 5000)) == 1 + nv_dd + 1
-    algo, tile = M.candidates("dd", 512, 512, 512)[-1]
-    assert algo == M.MPG_OZAKI and tile["slices"] == 0
+    assert len(M.candidates("dd", 200, 200, 200)) == 1 + nv_dd * 2 + 2  # leaves >= 64: depth 1 only
+    assert len(M.candidates("dd", 100, 5000, 5000)) == 1 + nv_dd + 2
+    (a1, t1), (a2, t2) = M.candidates("dd", 512, 512, 512)[-2:]
+    assert (a1, a2) == (M.MPG_OZAKI, M.MPG_OZAKI_CRT) and t1["slices"] == t2["slices"] == 0
     assert all(a != M.MPG_OZAKI for a, _ in M.candidates("qd", 512, 512, 512))
     f = M.mlp_features("qd", 256, 512, 1024, "block", M.variants(4)[0], batch=8)
     assert f.dtype == np.float32 and f.shape == (M.MLP_FEATURES,)
@@ -71,6 +71,8 @@ def test_tuner_host_logic(lib):
     assert np.isclose(f[13], 0.3) and f[14] == 0
     g = M.mlp_features("dd", 256, 512, 1024, "ozaki", {"slices": 0})
     assert g[14] == 1 and g[3] == 1 and not g[5:8].any()
+    h = M.mlp_features("dd", 256, 512, 1024, "ozaki_crt", {"slices": 0})
+    assert h[14] == 2 and h[3] == 1 and not h[5:8].any()
 
 
 def test_slices_for_bits_matches_oracle(lib):
@@ -99,7 +101,24 @@ def test_method_bounds_host_only(lib):
     oz = 4 * 2.0 ** (3 - 8 * 14) + (4.1 * 27 * 27 + 2) * 2.0 ** -105
     assert math.isclose(M.method_bound(2, "dd", "ozaki", {"slices": 14}, "all", 4096, 4096, 4096), oz, rel_tol=1e-15)
     assert M.method_bound(4, "dd", "ozaki", {"slices": 14}, "all", 64, 64, 64) == inf        # no QD split
+    # residue form: the all-pairs truncation bound plus one rounding, up to 20 slices
+    crt14 = 4 * 2.0 ** (3 - 8 * 14) + 2.0 ** -104
+    assert M.method_bound(2, "dd", "ozaki", {"slices": 14}, "crt", 4096, 4096, 4096) == crt14
+    assert M.method_bound(2, "dd", "ozaki_crt", {"slices": 14}, "all", 4096, 4096, 4096) == crt14
+    assert M.method_bound(2, "dd", "ozaki", {"slices": 21}, "crt", 64, 64, 64) == inf
     # truncation falls by 2^-8 per slice until the recombination term (which
     # grows with the square of the 2S - 1 diagonals) takes over near 2^-94
     b = [M.method_bound(1, "dd", "ozaki", {"slices": S}, "all", 512, 512, 512) for S in range(1, 16)]
     assert all(x > y for x, y in zip(b[:11], b[1:11])) and 2.0 ** -96 < min(b) < 2.0 ** -92
+
+
+def test_crt_moduli_match_oracle(lib):
+    """Moduli count of the residue form (host only) equals the oracle's:
+    the fewest leading moduli whose product exceeds 2 l 2^(16 S - 4)."""
+    from oracle import crt
+    from paper_1710_01839_amd import mpgemm as M
+    for S in range(1, 21):
+        for l in (1, 2, 3, 64, 100, 4096, 4097, 1 << 20):
+            want = crt.moduli_for_bits(crt.product_bits(S, l)) or 0
+            assert M.crt_moduli_for(S, l) == want, (S, l)
+    assert M.crt_moduli_for(21, 64) == 0 and M.crt_moduli_for(0, 64) == 0

@@ -138,8 +138,9 @@ def test_tuner_modes(gpu, tmp_path):
         pa = T.tune(prec, n, n, n, "paper")
         ml = T.tune(prec, n, n, n, "mlp", 3)
         assert ml["trials"] == 3 and ex["trials"] == len(M.candidates(prec, n, n, n))
-        # simple, block, up to three Strassen depths, and the split product for DD
-        assert pa["trials"] <= 1 + 1 + 3 + (prec == "dd")
+        # simple, block, up to three Strassen depths, and the split product
+        # (digit and residue forms) for DD
+        assert pa["trials"] <= 1 + 1 + 3 + 2 * (prec == "dd")
         best = T.time(prec, n, n, n, ex["algo"], ex["tile"], reps=5)
         got = T.time(prec, n, n, n, ml["algo"], ml["tile"], reps=5)
         print(prec, n, "exhaustive", ex, "paper", pa, "mlp", ml)
@@ -157,7 +158,7 @@ def test_auto_uses_tuning_table(gpu):
     A, B = M.to_device(inputs.dd_uniform(n, n, 1)), M.to_device(inputs.dd_uniform(n, n, 2))
     C1, C2 = M.empty_like_limbs(n, n, 2), M.empty_like_limbs(n, n, 2)
     M.mpgemm_dd(ctx, A, B, C1, algo="auto")
-    algo = {1: "simple", 2: "block", 3: "strassen", 4: "ozaki"}[r["algo"]]
+    algo = {1: "simple", 2: "block", 3: "strassen", 4: "ozaki", 5: "ozaki_crt"}[r["algo"]]
     M.mpgemm_dd(ctx, A, B, C2, algo=algo, tile=r["tile"])
     torch.cuda.synchronize()
     assert torch.equal(C1[0], C2[0]) and torch.equal(C1[1], C2[1])
@@ -181,13 +182,16 @@ def test_auto_follows_split_product_entry(gpu):
 
 
 def test_split_product_candidate_timed(gpu):
-    """The DD candidate list ends with the split-precision product; the tuner
-    times it on its own DD buffers (full lower limbs)."""
+    """The DD candidate list ends with the split-precision product (digit
+    form, then residue form); the tuner times both on its own DD buffers (full
+    lower limbs)."""
     M, ctx = gpu
     T = M.Tuner(ctx)
     n = 512
-    algo, tile = M.candidates("dd", n, n, n)[-1]
-    assert algo == M.MPG_OZAKI
-    ms = T.time("dd", n, n, n, algo, tile, reps=3)
-    # lower limbs ~2^-54 below the upper ones, 53 bits each: > 100 bits per entry
-    assert ms > 0 and M.ozaki_last_slices(ctx) >= 15
+    (a1, t1), (a2, t2) = M.candidates("dd", n, n, n)[-2:]
+    assert (a1, a2) == (M.MPG_OZAKI, M.MPG_OZAKI_CRT)
+    for algo, tile in ((a1, t1), (a2, t2)):
+        ms = T.time("dd", n, n, n, algo, tile, reps=3)
+        # lower limbs ~2^-54 below the upper ones, 53 bits each: > 100 bits per entry
+        assert ms > 0 and M.ozaki_last_slices(ctx) >= 15
+    assert M.ozaki_last_moduli(ctx) == M.crt_moduli_for(M.ozaki_last_slices(ctx), n)
