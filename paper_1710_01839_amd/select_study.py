@@ -5,7 +5,8 @@
 For FP64 and double-double inputs and each target of `bits` (normwise:
 max |C - AB| <= 2^-bits l max|A| max|B|), the library times every method
 whose a-priori bound meets the target (DD / QD block, Winograd-Strassen
-depths, the split INT8 product with its slice count) and keeps the fastest.
+depths, the split INT8 product with its slice count: all digit pairs, the
+triangle, the residue form) and keeps the fastest.
 Printed per target (one JSON line): the choice, the bits its bound
 guarantees, its time, the wall time of the choice itself, and the time of
 the plain choice (the DD block kernel when its bound meets the target, else
@@ -43,8 +44,10 @@ def main():
             secs = time.perf_counter() - t0
             dd_ok = M.method_bound(kind, 2, "block", None, "all", n, n, n) <= 2.0 ** -bits
             base = plain[2] if dd_ok else plain[4]
-            what = ALGO[r["algo"]] + (f" depth {r['tile']['depth']}" if r["algo"] == 3 else "") + \
-                (f", {r['tile']['slices']} slices, {r['pairs']} pairs" if r["algo"] == 4 else "")
+            what = ALGO[r["algo"]] + (f" depth {r['tile']['depth']}" if r["algo"] == 3 else "")
+            if r["algo"] == 4:
+                what += f", {r['tile']['slices']} slices, " + \
+                    ("residue form" if r["pairs"] == "crt" else f"{r['pairs']} pairs")
             print(json.dumps({"n": n, "in_limbs": kind, "bits": bits,
                               "choice": f"{'DD' if r['precision'] == 2 else 'QD'} {what}",
                               "bound_bits": round(r["bound_bits"], 1), "ms": round(r["ms"], 3),
