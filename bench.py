@@ -21,7 +21,7 @@ Also measured on the same GPU and reported in the same line:
                   same for its residue (Chinese remainder) form, one INT8
                   product per modulus;
   tuning          wall-clock tuning time at n = 4096 (DD): exhaustive, the
-                  paper's prediction procedure and MLP-pruned (top 3; the
+                  paper's prediction procedure and MLP-pruned (default top-k; the
                   model trained on exhaustive timings of smaller shapes), with
                   each pick's regret against the exhaustive pick.
 """
@@ -145,7 +145,7 @@ def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
 
 def tuning_time(M, ctx, n):
     """Tuning of one n x n x n DD product: exhaustive, the paper's procedure
-    and MLP-pruned (top 3), each pick re-timed; the model is trained on the
+    and MLP-pruned (default top-k: 4 of the 35 DD candidates), each pick re-timed; the model is trained on the
     exhaustive timings of TUNING_TRAIN first (not counted in its time)."""
     import tempfile
     T = M.Tuner(ctx)
@@ -158,7 +158,7 @@ def tuning_time(M, ctx, n):
     T.set_db(None)
     mlp = M.MLP(ctx)
     loss, rows = mlp.train_db(db, 3000, 3e-3)
-    res = {mode: T.tune("dd", n, n, n, mode, 3) for mode in ("exhaustive", "paper", "mlp")}
+    res = {mode: T.tune("dd", n, n, n, mode, 0) for mode in ("exhaustive", "paper", "mlp")}
     best = T.time("dd", n, n, n, res["exhaustive"]["algo"], res["exhaustive"]["tile"], reps=5)
     out = {"shape": [n, n, n], "precision": "dd", "model_training": {"shapes": len(TUNING_TRAIN),
                                                                     "rows": rows, "sweep_s": round(train_s, 2),

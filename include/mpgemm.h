@@ -359,8 +359,8 @@ int mpg_predict_block(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t
                       const mpg_tile* tile, int rule, double* predicted_ms, double* slab_ms);
 
 /* Tune one shape; the winner also enters the context's table used by
- * MPG_AUTO.  topk: candidates timed in MLP mode (0: one per 12 candidates,
- * at least 2: 3 of the 35 DD candidates, 2 of the 13 QD ones).  Outputs (each
+ * MPG_AUTO.  topk: candidates timed in MLP mode (0: one per 9 candidates,
+ * at least 2: 4 of the 35 DD candidates, 2 of the 13 QD ones).  Outputs (each
  * nullable): winner, its median time, wall-clock seconds of the search
  * (trials, warm-ups, predictions and model inference), number of
  * full-size trials. */

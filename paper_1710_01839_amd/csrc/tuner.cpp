@@ -377,7 +377,7 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
       for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
       std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return y[a] < y[b]; });
       // default: one timed candidate per 12 ranked, at least 2
-      const int dflt = std::max(2, (int)((idx.size() + 11) / 12));
+      const int dflt = std::max(2, (int)((idx.size() + 8) / 9));  // 4 of 35 DD, 2 of 13 QD
       const int k = std::max(1, std::min<int>(topk > 0 ? topk : dflt, (int)idx.size()));
       for (int i = 0; i < k; ++i)
         if ((st = trial(cands[idx[i]])) != MPG_OK) break;
