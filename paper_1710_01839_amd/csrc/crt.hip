@@ -1,5 +1,5 @@
 // Residue (Chinese remainder) form of the split product: the reconstruction
-// table, the residue planes of the integer images and the rebuild of the
+// table, the residue weights of the image words and the rebuild of the
 // exact integer product from its residues.
 #include <cmath>
 
@@ -67,66 +67,6 @@ __global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t) {
     }
     t->Pd = pd;
     t->N = N;
-  }
-}
-
-// ---------------------------------------------------------------------
-// Residues of the integer images: a thread takes 8 consecutive bytes of the
-// digit planes (8 elements), folds each element's S digits into 40-bit words
-// (five digits per word, most significant first; every word is an exact
-// double) and, per modulus, sums word * (2^(40 w) mod p) exactly in double
-// (< 2^51), then reduces into [-p/2, p/2).
-// ---------------------------------------------------------------------
-constexpr int kCrtDigitsPerWord = 5;
-constexpr int kCrtImageWords = kCrtMaxSlices / kCrtDigitsPerWord;
-
-struct ResidueConsts {
-  double c[kCrtMaxModuli][kCrtImageWords];  // 2^(40 w) mod p_z, w from the least significant word
-};
-
-__global__ __launch_bounds__(256) void crt_residue_kernel(const int8_t* __restrict__ D, int S,
-                                                          int64_t plane, int N,
-                                                          int8_t* __restrict__ out,
-                                                          const ResidueConsts* __restrict__ rc) {
-  const int64_t chunks = plane / 8;
-  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < chunks;
-       x += (int64_t)gridDim.x * 256) {
-    // words[w][b]: word w (0 = least significant) of element b
-    double words[kCrtImageWords][8];
-#pragma unroll
-    for (int w = 0; w < kCrtImageWords; ++w)
-#pragma unroll
-      for (int b = 0; b < 8; ++b) words[w][b] = 0.0;
-    for (int s = 0; s < S; ++s) {
-      const uint64_t v = *reinterpret_cast<const uint64_t*>(D + (int64_t)s * plane + 8 * x);
-      const int pos = S - 1 - s;  // power of 256 of digit s
-      const int w = pos / kCrtDigitsPerWord;
-      const double wt = (double)(1ull << (8 * (pos % kCrtDigitsPerWord)));
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const double d = (double)(int8_t)(v >> (8 * b));
-#pragma unroll
-        for (int ww = 0; ww < kCrtImageWords; ++ww)
-          if (ww == w) words[ww][b] = __builtin_fma(d, wt, words[ww][b]);
-      }
-    }
-    for (int z = 0; z < N; ++z) {
-      const int p = kCrtModuli[z];
-      const double pd = (double)p, inv = 1.0 / pd;
-      uint64_t packed = 0;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        double acc = 0.0;  // words past the image's length are zero
-#pragma unroll
-        for (int w = 0; w < kCrtImageWords; ++w) acc = __builtin_fma(words[w][b], rc->c[z][w], acc);
-        double r = acc - floor(acc * inv) * pd;  // exact: |acc| < 2^51, r an integer
-        if (r >= pd) r -= pd;
-        if (r < 0.0) r += pd;
-        if (2.0 * r >= pd) r -= pd;              // into [-p/2, p/2)
-        packed |= (uint64_t)(uint8_t)(int8_t)(int)r << (8 * b);
-      }
-      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + 8 * x) = packed;
-    }
   }
 }
 
@@ -293,14 +233,14 @@ __global__ __launch_bounds__(256) void crt_reconstruct_kernel(RecArgs a) {
   }
 }
 
-__global__ void residue_consts_kernel(int N, ResidueConsts* rc) {
+__global__ void residue_consts_kernel(int N, CrtResidueConsts* rc) {
   const int z = threadIdx.x;
   if (z >= N) return;
   const int p = kCrtModuli[z];
   int c = 1;
   for (int w = 0; w < kCrtImageWords; ++w) {
     rc->c[z][w] = (double)c;
-    for (int k = 0; k < 40; ++k) c = (2 * c) % p;
+    for (int k = 0; k < 8 * kCrtDigitsPerWord; ++k) c = (2 * c) % p;
   }
 }
 
@@ -367,18 +307,9 @@ hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t crt_residue_consts_bytes() { return sizeof(ResidueConsts); }
-
-hipError_t launch_crt_residues(const int8_t* D, int S, int64_t plane, int N, int8_t* out,
-                               void* consts, hipStream_t s) {
-  if (S < 1 || S > kCrtMaxSlices || N < 1 || N > kCrtMaxModuli || plane % 8) return hipErrorInvalidValue;
-  if (plane <= 0) return hipSuccess;
-  ResidueConsts* rc = reinterpret_cast<ResidueConsts*>(consts);
+hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s) {
+  if (N < 1 || N > kCrtMaxModuli) return hipErrorInvalidValue;
   hipLaunchKernelGGL(residue_consts_kernel, dim3(1), dim3(64), 0, s, N, rc);
-  const int64_t chunks = plane / 8;
-  const int64_t blocks = std::min<int64_t>((chunks + 255) / 256, 65536);
-  hipLaunchKernelGGL(crt_residue_kernel, dim3((unsigned)blocks), dim3(256), 0, s, D, S, plane, N, out,
-                     rc);
   return hipGetLastError();
 }
 

@@ -58,14 +58,48 @@ int crt_moduli_for_bits(int bits);
 int crt_words(int N);
 
 hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s);
-// Residue planes of the digit planes D ([S][plane] bytes, plane a multiple
-// of 8): out[z * plane + x] = (sum_s D_s[x] 256^(S-1-s)) mod p_z in
-// [-p_z/2, p_z/2).
-// `consts` is device scratch of crt_residue_consts_bytes() (8-byte aligned)
-// for the per-modulus word weights 2^(40 w) mod p.
-size_t crt_residue_consts_bytes();
-hipError_t launch_crt_residues(const int8_t* D, int S, int64_t plane, int N, int8_t* out,
-                               void* consts, hipStream_t s);
+
+// Integer images are folded into words of five digits (40 bits, exact
+// doubles), least significant word first; kCrtImageWords of them hold 20
+// digits.  Residue weights 2^(40 w) mod p_z per modulus.
+constexpr int kCrtDigitsPerWord = 5;
+constexpr int kCrtImageWords = kCrtMaxSlices / kCrtDigitsPerWord;
+struct CrtResidueConsts {
+  double c[kCrtMaxModuli][kCrtImageWords];
+};
+hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s);
+
+// Residues of 8 elements' images (words[w][q], |sum_w word c| < 2^51, so
+// every step is exact in FP64) modulo p, each in [-p/2, p/2), packed as
+// signed bytes (element q in byte q).
+__device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImageWords][8],
+                                                  const double* c, int p) {
+  const double pd = (double)p, inv = 1.0 / pd;
+  uint64_t packed = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCrtImageWords; ++w) acc = __builtin_fma(words[w][q], c[w], acc);
+    double r = acc - floor(acc * inv) * pd;  // an integer; the quotient may be off by one
+    if (r >= pd) r -= pd;
+    if (r < 0.0) r += pd;
+    if (2.0 * r >= pd) r -= pd;  // into [-p/2, p/2)
+    packed |= (uint64_t)(uint8_t)(int8_t)(int)r << (8 * q);
+  }
+  return packed;
+}
+
+// Residue planes straight from the operand rows: for each row r of X (R x K,
+// X + Xlo as one exact value when Xlo is given) and its scale e[r], the S
+// truncated radix-256 digits of x 2^-(e + 2) are folded into the image
+// A' = trunc(x 2^(8S - 2 - e)) and reduced modulo the N leading moduli:
+// out[z * plane + r * Kp + k] (r < Rp, k < Kp, zeros in the padding; plane
+// = Rp Kp).  Columns of B go through a transposed copy.
+hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                           const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
+                           const CrtResidueConsts* rc, hipStream_t s);
+
 // Workgroup tile of the residue products: A's planes need rows padded to
 // crt_tile_rows(), B's to crt_tile_cols(), K to crt_k_multiple().
 int crt_tile_rows();

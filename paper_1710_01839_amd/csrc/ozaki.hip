@@ -271,6 +271,53 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const double* X, const 
   for (int s = S - 1; s >= 0; --s) w[s * plane / 8] = carry_word(w[s * plane / 8], neg, c, s == 0);
 }
 
+// Residue planes of the residue form straight from the operand: one thread
+// per 8 consecutive k of a row, as in split_rows_kernel, but the truncated
+// digits (before any carry: the carry does not change their weighted sum)
+// are folded into the image's 40-bit words in registers and only the
+// residues are written, one byte per element and modulus.
+template <bool DD>
+__global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const double* Xlo, int64_t R,
+                                                       int64_t K, int64_t ld, const int* e, int S, int N,
+                                                       int8_t* __restrict__ out, int64_t Rp, int64_t Kp,
+                                                       const CrtResidueConsts* __restrict__ rc) {
+  const int64_t per_row = Kp / 8;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= Rp * per_row) return;
+  const int64_t r = idx / per_row, k0 = (idx % per_row) * 8;
+  double y[8], yl[8];
+  const int er = r < R ? e[r] : 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t k = k0 + q;
+    const bool ok = r < R && k < K;
+    y[q] = ldexp(ok ? X[r * ld + k] : 0.0, -(er + 2));
+    yl[q] = 0.0;
+    if (DD) two_sum(y[q], ldexp(ok ? Xlo[r * ld + k] : 0.0, -(er + 2)), y[q], yl[q]);
+  }
+  double words[kCrtImageWords][8];
+#pragma unroll
+  for (int w = 0; w < kCrtImageWords; ++w)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) words[w][q] = 0.0;
+  for (int s = 0; s < S; ++s) {
+    const int pos = S - 1 - s;  // digit s + 1 weighs 256^pos in the image
+    const int w = pos / kCrtDigitsPerWord;
+    const double wt = (double)(1ull << (8 * (pos % kCrtDigitsPerWord)));
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double d = (double)digit_step<DD>(y[q], yl[q]);
+#pragma unroll
+      for (int ww = 0; ww < kCrtImageWords; ++ww)
+        if (ww == w) words[ww][q] = __builtin_fma(d, wt, words[ww][q]);
+    }
+  }
+  const int64_t plane = Rp * Kp;
+  for (int z = 0; z < N; ++z)
+    *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + r * Kp + k0) =
+        crt_residues8(words, rc->c[z], kCrtModuli[z]);
+}
+
 // Columns of X (K x C, row-major) -> planes out[s][c][k] (transposed, c < Cp,
 // k < Kp, zero padded).  A 32 (k) x 64 (c) tile is read coalesced along c
 // (each thread keeps 8 remainders in registers); for each digit plane the
@@ -1164,6 +1211,22 @@ hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
   const int64_t tiles = ((a.m + kOzTile - 1) / kOzTile) * ((a.n + kOzTile - 1) / kOzTile);
   if (tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(ozaki_mfma_kernel<4>, dim3((unsigned)tiles), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                           const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
+                           const CrtResidueConsts* rc, hipStream_t s) {
+  if (S < 1 || S > kCrtMaxSlices || N < 1 || N > kCrtMaxModuli || Kp % 8) return hipErrorInvalidValue;
+  const int64_t work = Rp * (Kp / 8);
+  if (work <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((work + 255) / 256));
+  if (Xlo)
+    hipLaunchKernelGGL(crt_rows_kernel<true>, grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out, Rp,
+                       Kp, rc);
+  else
+    hipLaunchKernelGGL(crt_rows_kernel<false>, grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out, Rp,
+                       Kp, rc);
   return hipGetLastError();
 }
 

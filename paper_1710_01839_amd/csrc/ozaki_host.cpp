@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "capi_internal.hpp"
+#include "blas_internal.hpp"
 #include "crt_internal.hpp"
 #include "ozaki_internal.hpp"
 
@@ -109,9 +110,10 @@ extern "C" int mpg_ozaki_split(mpg_ctx* c, int side, int64_t rows, int64_t cols,
 
 namespace {
 
-// Residue form after the scales: digit planes (as for the digit form), their
-// residues modulo the N leading moduli, one INT8 product per modulus and
-// the reconstruction of the exact integer product.
+// Residue form after the scales: residue planes of A's rows and of the
+// rows of a transposed copy of B (the integer images never exist as digit
+// planes), one INT8 product per modulus and the reconstruction of the
+// exact integer product.
 int crt_tail(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
              int64_t lda, const double* B, const double* B_lo, int64_t ldb, double* C_hi,
              double* C_lo, int64_t ldc, int S, const int* e, const int* f) {
@@ -121,36 +123,41 @@ int crt_tail(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const
                     S, (long long)l);
   c->last_slices = S;
   c->last_moduli = N;
-  // planes padded to the residue products' tile (the split kernels write
+  // planes padded to the residue products' tile (the rows kernel writes
   // zeros into the padding)
   const int64_t lp = round_up(l, crt_k_multiple()), mp = round_up(m, crt_tile_rows()),
                 np = round_up(n, crt_tile_cols()), n4 = round_up(n, 4);
   const int64_t planeA = mp * lp, planeB = np * lp;
-  const size_t cb = (crt_residue_consts_bytes() + 255) / 256 * 256;
-  void *big = nullptr, *res = nullptr, *out = nullptr;
+  const bool dd = B_lo != nullptr;
+  const size_t cb = (sizeof(CrtResidueConsts) + 255) / 256 * 256;
+  void *bt = nullptr, *res = nullptr, *out = nullptr;
   int st;
-  if ((st = mpg_workspace(c, 0, (size_t)S * (size_t)(planeA + planeB), &big)) != MPG_OK ||
-      (st = mpg_workspace(c, 7, (size_t)N * (size_t)(planeA + planeB) + 2 * cb, &res)) != MPG_OK ||
+  if ((st = mpg_workspace(c, 0, (size_t)(dd ? 2 : 1) * (size_t)(n * l) * sizeof(double), &bt)) != MPG_OK ||
+      (st = mpg_workspace(c, 7, (size_t)N * (size_t)(planeA + planeB) + cb, &res)) != MPG_OK ||
       (st = mpg_workspace(c, 8, (size_t)N * (size_t)(m * n4) + 256 + sizeof(CrtTable), &out)) != MPG_OK)
     return st;
-  int8_t* Asl = (int8_t*)big;
-  int8_t* Bsl = Asl + (size_t)S * planeA;
+  double* BT = (double*)bt;
+  double* BTlo = dd ? BT + (size_t)(n * l) : nullptr;
   int8_t* Ares = (int8_t*)res;
   int8_t* Bres = Ares + (size_t)N * planeA;
-  char* consts = (char*)(Bres + (size_t)N * planeB);
+  CrtResidueConsts* consts = (CrtResidueConsts*)(Bres + (size_t)N * planeB);
   uint8_t* R = (uint8_t*)out;
   CrtTable* table = (CrtTable*)((char*)out + ((size_t)N * (size_t)(m * n4) + 255) / 256 * 256);
   st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    hipError_t r = launch_ozaki_split_rows(A, A_lo, m, l, lda, e, S, Asl, lp, planeA, mp, lp, c->stream);
-    if (r != hipSuccess) return r;
-    r = launch_ozaki_split_cols(B, B_lo, l, n, ldb, f, S, Bsl, lp, planeB, np, lp, c->stream);
+    PackArgs pk{};
+    pk.job[0] = PackJob{B, BT, n, l, ldb, l, 1, 1.0};
+    if (dd) pk.job[1] = PackJob{B_lo, BTlo, n, l, ldb, l, 1, 1.0};
+    pk.count = dd ? 2 : 1;
+    hipError_t r = launch_pack(pk, c->stream);
     if (r != hipSuccess) return r;
     r = launch_crt_table(N, table, c->stream);
     if (r != hipSuccess) return r;
-    r = launch_crt_residues(Asl, S, planeA, N, Ares, consts, c->stream);
+    r = launch_crt_residue_consts(N, consts, c->stream);
     if (r != hipSuccess) return r;
-    return launch_crt_residues(Bsl, S, planeB, N, Bres, consts + cb, c->stream);
-  }, "digit split and residues");
+    r = launch_crt_rows(A, A_lo, m, l, lda, e, S, N, Ares, mp, lp, consts, c->stream);
+    if (r != hipSuccess) return r;
+    return launch_crt_rows(BT, BTlo, n, l, l, f, S, N, Bres, np, lp, consts, c->stream);
+  }, "residue planes");
   if (st != MPG_OK) return st;
   CrtGemmArgs g{};
   g.m = m;
