@@ -57,8 +57,9 @@ typedef enum {
   MPG_STRASSEN = 3, /* Eq. (3), Winograd's form, `depth` levels over MPG_BLOCK */
   MPG_OZAKI = 4,    /* split-precision INT8 product (DD only: mpgemm_dd_ozaki with
                        tile->slices, all pairs) */
-  MPG_OZAKI_CRT = 5 /* its residue form (DD only: mpgemm_dd_ozaki with tile->slices,
-                       pairs_mode 2) */
+  MPG_OZAKI_CRT = 5 /* its residue form: DD through mpgemm_dd_ozaki with tile->slices,
+                       pairs_mode 2; QD as three residue-form products of the
+                       operands' double-double parts (mpgemm_qd) */
 } mpg_algo;
 
 /* Tile / algorithm parameters.  Zero fields mean "library default" (DD:
@@ -118,7 +119,13 @@ int mpgemm_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
  * pointers (leading limb first), each plane row-major with the given
  * leading dimension.  algo MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN or MPG_AUTO
  * as for mpgemm_dd.  Error: componentwise |C - AB|_ij <= 8 l 2^-208
- * (|A||B|)_ij for SIMPLE and BLOCK (bitwise identical to each other). */
+ * (|A||B|)_ij for SIMPLE and BLOCK (bitwise identical to each other).
+ * MPG_OZAKI_CRT: each operand is split exactly into its double-double parts
+ * (limbs 0 + 1, limbs 2 + 3); A_H B_H, A_H B_L and A_L B_H are formed
+ * exactly by the residue form (exact slice count of each part, at most 20,
+ * else MPG_ERR_UNSUPPORTED; synchronises the stream once for the counts)
+ * and added in quad-double; A_L B_L is left out (below 2^-210 (|A||B|) for
+ * canonical operands). */
 int mpgemm_qd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
               const double* const A[4], int64_t lda,
               const double* const B[4], int64_t ldb,
@@ -334,7 +341,7 @@ typedef enum {
  * MPG_STRASSEN with every tile and depth 1..3 (DD) / 1..2 (QD) while the
  * leaves keep at least 64 per side, and last, for DD, MPG_OZAKI and
  * MPG_OZAKI_CRT with slices = 0 (exact slice count; all pairs, residue
- * form).  precision: 2 (DD) or 4 (QD).
+ * form), for QD MPG_OZAKI_CRT.  precision: 2 (DD) or 4 (QD).
  * The tuner times them on its own buffers: limb 0 uniform in (-1, 1), each
  * lower limb a uniform fraction of half an ulp of the limb above (the next
  * 53 bits of a random significand). */
@@ -360,15 +367,15 @@ int mpg_predict_block(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t
 
 /* Tune one shape; the winner also enters the context's table used by
  * MPG_AUTO.  topk: candidates timed in MLP mode (0: one per 9 candidates,
- * at least 2: 4 of the 35 DD candidates, 2 of the 13 QD ones).  Outputs (each
+ * at least 2: 4 of the 35 DD candidates, 2 of the 14 QD ones).  Outputs (each
  * nullable): winner, its median time, wall-clock seconds of the search
  * (trials, warm-ups, predictions and model inference), number of
  * full-size trials. */
 int mpg_tune(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l, int mode, int topk,
              int* best_algo, mpg_tile* best_tile, double* best_ms, double* seconds, int* trials);
 
-/* Put a choice into the table used by MPG_AUTO directly (MPG_OZAKI,
- * MPG_OZAKI_CRT: DD only, tile->slices as for mpgemm_dd_ozaki). */
+/* Put a choice into the table used by MPG_AUTO directly (MPG_OZAKI: DD
+ * only, tile->slices as for mpgemm_dd_ozaki). */
 int mpg_tune_table_set(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
                        int algo, const mpg_tile* tile);
 
@@ -388,7 +395,12 @@ int mpg_tune_table_set(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_
  *     (4.1 T^2 + 2) 2^-105, T = (2S - 1) x chunks of K, for the
  *     double-double recombination; pairs_mode 2 (or algo MPG_OZAKI_CRT), the
  *     residue form (slices <= 20): the all-pairs truncation bound x 4 plus
- *     2^-104 for the single rounding of the exact kept product.
+ *     2^-104 for the single rounding of the exact kept product;
+ *   MPG_OZAKI_CRT with precision 4 (quad-double through the residue form):
+ *     2^-204 (exact part products, quad-double roundings and additions, the
+ *     dropped product of the trailing parts).  Feasible only when each
+ *     part's exact slice count is at most 20 (the call then fails with
+ *     MPG_ERR_UNSUPPORTED otherwise).
  * Host only. */
 double mpg_method_bound(int in_limbs, int precision, int algo, const mpg_tile* tile,
                         int pairs_mode, int64_t m, int64_t n, int64_t l);
@@ -400,7 +412,7 @@ double mpg_method_bound(int in_limbs, int precision, int algo, const mpg_tile* t
  * tile), Winograd-Strassen depth 1..3 (DD) / 1..2 (QD) for square shapes,
  * and the split INT8 product (FP64 or DD inputs) with the fewest slices
  * whose bound meets the target, all pairs, triangle and the residue form
- * (*pairs_mode 0, 1, 2).  Every candidate
+ * (*pairs_mode 0, 1, 2), and quad-double through the residue form.  Every candidate
  * whose mpg_method_bound is within the target is timed at full size on
  * library buffers (median of 3); the fastest is returned: *precision (2:
  * call mpgemm_dd, or mpgemm_ozaki_dd / mpgemm_dd_ozaki for MPG_OZAKI with

@@ -443,8 +443,9 @@ int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
       algo = MPG_BLOCK;
     }
   }
+  if (algo == MPG_OZAKI_CRT && limbs == 4) return mpg_qd_crt(c, m, n, l, A, lda, B, ldb, C, ldc);
   if (algo == MPG_OZAKI || algo == MPG_OZAKI_CRT) {
-    if (limbs != 2) return mpg_fail(c, MPG_ERR_UNSUPPORTED, "the split-precision product is DD only");
+    if (limbs != 2) return mpg_fail(c, MPG_ERR_UNSUPPORTED, "the digit form of the split product is DD only");
     return mpgemm_dd_ozaki(c, m, n, l, A[0], A[1], lda, B[0], B[1], ldb, C[0], C[1], ldc,
                            chosen.slices, algo == MPG_OZAKI_CRT ? 2 : 0);
   }

@@ -77,6 +77,9 @@ int mpg_resolve_variant(mpg_ctx* c, int precision, const mpg_tile* t, int* varia
 int mpg_strassen(mpg_ctx* c, int limbs, int depth, int variant, int64_t m, int64_t n, int64_t l,
                  const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
                  double* const* C, int64_t ldc);
+// Quad-double product through the residue form (C := A B, four limbs).
+int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const* A, int64_t lda,
+               const double* const* B, int64_t ldb, double* const* C, int64_t ldc);
 int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
                     const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
                     double* const* C, int64_t ldc, mpg_algo algo, const mpg_tile* tile);

@@ -79,13 +79,14 @@ __global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t) {
 //      below 2^-14), then Y = X' - q P by words; a negative Y or Y >= P is
 //      corrected by one addition or subtraction of P;
 //   3. centre: Y >= P / 2 stands for Y - P (negative, magnitude P - Y);
-//   4. the top five 32-bit words of the magnitude, each scaled exactly by
-//      2^(32 w + e_i + f_j + 4 - 16 S), are summed by TwoSum into a
-//      double-double (the dropped words are below 2^-96 of the top one).
+//   4. the top words of the magnitude, each scaled exactly by
+//      2^(32 w + e_i + f_j + 4 - 16 S), are summed into a double-double
+//      (five words; the dropped ones are below 2^-96 of the top one) or
+//      added to a quad-double result (eight words, below 2^-192).
 // ---------------------------------------------------------------------
 template <int W>
-__device__ __forceinline__ void crt_one(const uint64_t (&acc)[W], const CrtTable& t, int scale,
-                                        double& hi, double& lo) {
+__device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const CrtTable& t,
+                                              uint32_t (&y)[W]) {
   uint32_t x[W];
   uint64_t carry = 0;
 #pragma unroll
@@ -99,7 +100,6 @@ __device__ __forceinline__ void crt_one(const uint64_t (&acc)[W], const CrtTable
   for (int w = W - 1; w >= 0; --w) xd += ldexp((double)x[w], 32 * w);
   const uint32_t q = (uint32_t)floor(xd / t.Pd);
   // Y = X' - q P
-  uint32_t y[W];
   uint64_t mc = 0;
   int64_t br = 0;
 #pragma unroll
@@ -156,30 +156,64 @@ __device__ __forceinline__ void crt_one(const uint64_t (&acc)[W], const CrtTable
       b2 = d >> 32;
     }
   }
+  return neg;
+}
+
+// The signed value (magnitude words y, sign neg) times 2^scale as a
+// double-double: the top five words, each scaled exactly, summed by TwoSum.
+template <int W>
+__device__ __forceinline__ void crt_to_dd(const uint32_t (&y)[W], bool neg, int scale, double& hi,
+                                          double& lo) {
   int top = -1;
 #pragma unroll
   for (int w = 0; w < W; ++w)
     if (y[w] != 0) top = w;
   hi = 0.0;
   lo = 0.0;
-  if (top >= 0) {
+  if (top < 0) return;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int w = top - k;
-      if (w >= 0) {
-        const double v = ldexp((double)y[w], 32 * w + scale);
-        double s, e;
-        two_sum(hi, v, s, e);
-        hi = s;
-        lo += e;
-      }
-    }
-    dd_renorm(hi, lo);
-    if (neg) {
-      hi = -hi;
-      lo = -lo;
+  for (int k = 0; k < 5; ++k) {
+    const int w = top - k;
+    if (w >= 0) {
+      const double v = ldexp((double)y[w], 32 * w + scale);
+      double s, e;
+      two_sum(hi, v, s, e);
+      hi = s;
+      lo += e;
     }
   }
+  dd_renorm(hi, lo);
+  if (neg) {
+    hi = -hi;
+    lo = -lo;
+  }
+}
+
+// The same as a quad-double: the top eight words (256 bits), each added
+// from the top into a four-term expansion by a TwoSum chain, renormalised.
+template <int W>
+__device__ __forceinline__ void crt_to_qd(const uint32_t (&y)[W], bool neg, int scale, double (&s)[4]) {
+  int top = -1;
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (y[w] != 0) top = w;
+  s[0] = s[1] = s[2] = s[3] = 0.0;
+  if (top < 0) return;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int w = top - k;
+    if (w >= 0) {
+      double e = ldexp((double)y[w], 32 * w + scale);
+      two_sum(s[0], e, s[0], e);
+      two_sum(s[1], e, s[1], e);
+      two_sum(s[2], e, s[2], e);
+      s[3] += e;
+    }
+  }
+  qd_finish(s);
+  if (neg)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = -s[q];
 }
 
 struct RecArgs {
@@ -191,12 +225,12 @@ struct RecArgs {
   const int* f;
   int base;  // 4 - 16 S
   int64_t m, n;
-  double* C_hi;
-  double* C_lo;
+  double* C[4];
   int64_t ldc;
 };
 
-template <int W>
+// QD = false: C (hi, lo) := the value; QD = true: C (four limbs) += it.
+template <int W, bool QD>
 __global__ __launch_bounds__(256) void crt_reconstruct_kernel(RecArgs a) {
   const int64_t j0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
   if (j0 >= a.n) return;
@@ -224,10 +258,21 @@ __global__ __launch_bounds__(256) void crt_reconstruct_kernel(RecArgs a) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       if (j0 + b < a.n) {
-        double hi, lo;
-        crt_one<W>(acc[b], t, ei + fj[b] + a.base, hi, lo);
-        a.C_hi[i * a.ldc + j0 + b] = hi;
-        a.C_lo[i * a.ldc + j0 + b] = lo;
+        uint32_t y[W];
+        const bool neg = crt_magnitude<W>(acc[b], t, y);
+        const int64_t o = i * a.ldc + j0 + b;
+        if constexpr (!QD) {
+          double hi, lo;
+          crt_to_dd<W>(y, neg, ei + fj[b] + a.base, hi, lo);
+          a.C[0][o] = hi;
+          a.C[1][o] = lo;
+        } else {
+          double v[4], c[4] = {a.C[0][o], a.C[1][o], a.C[2][o], a.C[3][o]}, r[4];
+          crt_to_qd<W>(y, neg, ei + fj[b] + a.base, v);
+          qd_add(c, v, r);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a.C[q][o] = r[q];
+        }
       }
     }
   }
@@ -315,20 +360,33 @@ hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s)
 
 hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR, int N,
                                   const CrtTable* t, const int* e, const int* f, int S, int64_t m,
-                                  int64_t n, double* C_hi, double* C_lo, int64_t ldc, hipStream_t s) {
+                                  int64_t n, double* const* C, int limbs, int64_t ldc, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (ldr % 4 || ldr < n) return hipErrorInvalidValue;
-  RecArgs a{R, ldr, planeR, N, t, e, f, 4 - 16 * S, m, n, C_hi, C_lo, ldc};
+  if (ldr % 4 || ldr < n || (limbs != 2 && limbs != 4)) return hipErrorInvalidValue;
+  RecArgs a{R, ldr, planeR, N, t, e, f, 4 - 16 * S, m, n, {C[0], C[1], nullptr, nullptr}, ldc};
+  if (limbs == 4) {
+    a.C[2] = C[2];
+    a.C[3] = C[3];
+  }
   const int64_t gx = ((n + 3) / 4 + 255) / 256;
   const dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(m, 65535));
+#define MPG_CRT_REC(WW)                                                                        \
+  case WW:                                                                                     \
+    if (limbs == 2)                                                                            \
+      hipLaunchKernelGGL((crt_reconstruct_kernel<WW, false>), grid, dim3(256), 0, s, a);       \
+    else                                                                                       \
+      hipLaunchKernelGGL((crt_reconstruct_kernel<WW, true>), grid, dim3(256), 0, s, a);        \
+    break;
   switch (crt_words(N)) {
-    case 4: hipLaunchKernelGGL(crt_reconstruct_kernel<4>, grid, dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL(crt_reconstruct_kernel<6>, grid, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(crt_reconstruct_kernel<8>, grid, dim3(256), 0, s, a); break;
-    case 10: hipLaunchKernelGGL(crt_reconstruct_kernel<10>, grid, dim3(256), 0, s, a); break;
-    case 12: hipLaunchKernelGGL(crt_reconstruct_kernel<12>, grid, dim3(256), 0, s, a); break;
-    default: return hipErrorInvalidValue;
+    MPG_CRT_REC(4)
+    MPG_CRT_REC(6)
+    MPG_CRT_REC(8)
+    MPG_CRT_REC(10)
+    MPG_CRT_REC(12)
+    default:
+      return hipErrorInvalidValue;
   }
+#undef MPG_CRT_REC
   return hipGetLastError();
 }
 

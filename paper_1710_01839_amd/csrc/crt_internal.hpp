@@ -106,9 +106,11 @@ int crt_tile_rows();
 int crt_tile_cols();
 int crt_k_multiple();
 hipError_t launch_crt_gemm(const CrtGemmArgs& a, hipStream_t s);
-// C_ij = X_ij 2^(e_i + f_j + 4 - 16 S), X the CRT value of the N residues.
+// V_ij = X_ij 2^(e_i + f_j + 4 - 16 S), X the CRT value of the N residues:
+// limbs 2: C (hi, lo) := V rounded to double-double; limbs 4: C (four
+// limbs) := C + V in quad-double.
 hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR, int N,
                                   const CrtTable* t, const int* e, const int* f, int S, int64_t m,
-                                  int64_t n, double* C_hi, double* C_lo, int64_t ldc, hipStream_t s);
+                                  int64_t n, double* const* C, int limbs, int64_t ldc, hipStream_t s);
 
 }  // namespace mpg

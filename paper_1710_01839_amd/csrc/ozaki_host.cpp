@@ -110,13 +110,14 @@ extern "C" int mpg_ozaki_split(mpg_ctx* c, int side, int64_t rows, int64_t cols,
 
 namespace {
 
-// Residue form after the scales: residue planes of A's rows and of the
-// rows of a transposed copy of B (the integer images never exist as digit
-// planes), one INT8 product per modulus and the reconstruction of the
-// exact integer product.
-int crt_tail(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
-             int64_t lda, const double* B, const double* B_lo, int64_t ldb, double* C_hi,
-             double* C_lo, int64_t ldc, int S, const int* e, const int* f) {
+// One residue-form product after the scales: residue planes of the rows of
+// A (+ A_lo) and of BT (+ BT_lo, B transposed: n x l, leading dimension l),
+// one INT8 product per modulus and the reconstruction of the exact integer
+// product, written to C as a double-double (limbs 2) or added to C as a
+// quad-double (limbs 4).
+int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
+                int64_t lda, const int* e, const double* BT, const double* BT_lo, const int* f, int S,
+                double* const* C, int limbs, int64_t ldc) {
   const int N = crt_moduli_for_bits(crt_product_bits(S, l));
   if (N == 0 || crt_words(N) == 0)
     return mpg_fail(c, MPG_ERR_UNSUPPORTED, "product of %d slices at l = %lld is too wide for the moduli",
@@ -128,35 +129,25 @@ int crt_tail(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const
   const int64_t lp = round_up(l, crt_k_multiple()), mp = round_up(m, crt_tile_rows()),
                 np = round_up(n, crt_tile_cols()), n4 = round_up(n, 4);
   const int64_t planeA = mp * lp, planeB = np * lp;
-  const bool dd = B_lo != nullptr;
   const size_t cb = (sizeof(CrtResidueConsts) + 255) / 256 * 256;
-  void *bt = nullptr, *res = nullptr, *out = nullptr;
+  void *res = nullptr, *out = nullptr;
   int st;
-  if ((st = mpg_workspace(c, 0, (size_t)(dd ? 2 : 1) * (size_t)(n * l) * sizeof(double), &bt)) != MPG_OK ||
-      (st = mpg_workspace(c, 7, (size_t)N * (size_t)(planeA + planeB) + cb, &res)) != MPG_OK ||
+  if ((st = mpg_workspace(c, 7, (size_t)N * (size_t)(planeA + planeB) + cb, &res)) != MPG_OK ||
       (st = mpg_workspace(c, 8, (size_t)N * (size_t)(m * n4) + 256 + sizeof(CrtTable), &out)) != MPG_OK)
     return st;
-  double* BT = (double*)bt;
-  double* BTlo = dd ? BT + (size_t)(n * l) : nullptr;
   int8_t* Ares = (int8_t*)res;
   int8_t* Bres = Ares + (size_t)N * planeA;
   CrtResidueConsts* consts = (CrtResidueConsts*)(Bres + (size_t)N * planeB);
   uint8_t* R = (uint8_t*)out;
   CrtTable* table = (CrtTable*)((char*)out + ((size_t)N * (size_t)(m * n4) + 255) / 256 * 256);
   st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    PackArgs pk{};
-    pk.job[0] = PackJob{B, BT, n, l, ldb, l, 1, 1.0};
-    if (dd) pk.job[1] = PackJob{B_lo, BTlo, n, l, ldb, l, 1, 1.0};
-    pk.count = dd ? 2 : 1;
-    hipError_t r = launch_pack(pk, c->stream);
-    if (r != hipSuccess) return r;
-    r = launch_crt_table(N, table, c->stream);
+    hipError_t r = launch_crt_table(N, table, c->stream);
     if (r != hipSuccess) return r;
     r = launch_crt_residue_consts(N, consts, c->stream);
     if (r != hipSuccess) return r;
     r = launch_crt_rows(A, A_lo, m, l, lda, e, S, N, Ares, mp, lp, consts, c->stream);
     if (r != hipSuccess) return r;
-    return launch_crt_rows(BT, BTlo, n, l, l, f, S, N, Bres, np, lp, consts, c->stream);
+    return launch_crt_rows(BT, BT_lo, n, l, l, f, S, N, Bres, np, lp, consts, c->stream);
   }, "residue planes");
   if (st != MPG_OK) return st;
   CrtGemmArgs g{};
@@ -176,8 +167,41 @@ int crt_tail(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const
                   "INT8 MFMA residue products");
   if (st != MPG_OK) return st;
   return mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    return launch_crt_reconstruct(R, n4, m * n4, N, table, e, f, S, m, n, C_hi, C_lo, ldc, c->stream);
+    return launch_crt_reconstruct(R, n4, m * n4, N, table, e, f, S, m, n, C, limbs, ldc, c->stream);
   }, "residue reconstruction");
+}
+
+// Copies `count` limb planes of B (l x n) transposed into workspace slot 0
+// (n x l each, leading dimension l).
+int transpose_b(mpg_ctx* c, int64_t l, int64_t n, const double* const* B, int64_t ldb, int count,
+                double** BT) {
+  void* w = nullptr;
+  int st = mpg_workspace(c, 0, (size_t)count * (size_t)(n * l) * sizeof(double), &w);
+  if (st != MPG_OK) return st;
+  PackArgs pk{};
+  for (int q = 0; q < count; ++q) {
+    BT[q] = (double*)w + (size_t)q * (size_t)(n * l);
+    pk.job[q] = PackJob{B[q], BT[q], n, l, ldb, l, 1, 1.0};
+  }
+  pk.count = count;
+  return mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_pack(pk, c->stream); }, "transposed copy of B");
+}
+
+// The double-double residue form after the scales.
+int crt_tail(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
+             int64_t lda, const double* B, const double* B_lo, int64_t ldb, double* C_hi,
+             double* C_lo, int64_t ldc, int S, const int* e, const int* f) {
+  const bool dd = B_lo != nullptr;
+  const double* Bp[2] = {B, B_lo};
+  double* BT[2] = {nullptr, nullptr};
+  int st = transpose_b(c, l, n, Bp, ldb, dd ? 2 : 1, BT);
+  if (st != MPG_OK) return st;
+  double* Cp[4] = {C_hi, C_lo, nullptr, nullptr};
+  return crt_product(c, m, n, l, A, A_lo, lda, e, BT[0], BT[1], f, S, Cp, 2, ldc);
+}
+
+__global__ void zero_ints_kernel(int* p, int count) {
+  if ((int)threadIdx.x < count) p[threadIdx.x] = 0;
 }
 
 // C := A B through the INT8 path; A_lo / B_lo (both or neither) make the
@@ -285,6 +309,74 @@ extern "C" int mpgemm_dd_ozaki(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
   if (c && l > 0 && m > 0 && n > 0 && (!A_lo || !B_lo)) return mpg_fail(c, MPG_ERR_ARG, "NULL lo limb");
   return ozaki_product(c, m, n, l, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc, slices,
                        pairs_mode);
+}
+
+// Quad-double C := A B through the residue form: each operand is split
+// exactly into its leading and trailing double-double parts (limbs 0 + 1 and
+// 2 + 3), A = A_H + A_L, B = B_H + B_L; C = A_H B_H + A_H B_L + A_L B_H, each
+// product exact with its own exact slice count (at most 20) and added into C
+// in quad-double; A_L B_L (below 2^-210 of |A||B| for canonical operands) is
+// left out.
+int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const* A, int64_t lda,
+               const double* const* B, int64_t ldb, double* const* C, int64_t ldc) {
+  const int64_t mp = round_up(std::max<int64_t>(m, 1), 64), np = round_up(std::max<int64_t>(n, 1), 64);
+  void* small = nullptr;
+  int st = mpg_workspace(c, 1, (size_t)(2 * mp + 3 * np + 64) * sizeof(int), &small);
+  if (st != MPG_OK) return st;
+  int* eH = (int*)small;
+  int* eL = eH + mp;
+  int* fH = eL + mp;
+  int* fL = fH + np;
+  int* low = fL + np;
+  int* cnt = low + np;  // digits needed by A_H, A_L, B_H, B_L
+  st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, c->stream, cnt, 4);
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    if ((r = launch_ozaki_scan(A[0], A[1], m, l, lda, 0, eH, nullptr, cnt + 0, c->stream)) != hipSuccess) return r;
+    if ((r = launch_ozaki_scan(A[2], A[3], m, l, lda, 0, eL, nullptr, cnt + 1, c->stream)) != hipSuccess) return r;
+    if ((r = launch_ozaki_scan(B[0], B[1], l, n, ldb, 1, fH, low, cnt + 2, c->stream)) != hipSuccess) return r;
+    return launch_ozaki_scan(B[2], B[3], l, n, ldb, 1, fL, low, cnt + 3, c->stream);
+  }, "exponent scans");
+  if (st != MPG_OK) return st;
+  int need[4] = {0, 0, 0, 0};
+  {
+    hipError_t r = hipMemcpyAsync(need, cnt, sizeof(need), hipMemcpyDeviceToHost, c->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+    if (r != hipSuccess) return mpg_hip_fail(c, r, "slice-count read-back");
+  }
+  struct Part {
+    int a, b;  // 0: leading part, 1: trailing part
+  };
+  const Part parts[3] = {{0, 0}, {0, 1}, {1, 0}};
+  int S[3];
+  for (int k = 0; k < 3; ++k) {
+    S[k] = std::max(need[parts[k].a], need[2 + parts[k].b]);
+    const bool zero = need[parts[k].a] == 0 || need[2 + parts[k].b] == 0;  // an all-zero part
+    if (zero) S[k] = 0;
+    if (S[k] > kCrtMaxSlices)
+      return mpg_fail(c, MPG_ERR_UNSUPPORTED,
+                      "an exact split of the quad-double operands needs %d slices per part (max %d)", S[k],
+                      kCrtMaxSlices);
+  }
+  double* BT[4] = {nullptr, nullptr, nullptr, nullptr};
+  if ((st = transpose_b(c, l, n, B, ldb, 4, BT)) != MPG_OK) return st;
+  if ((st = mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_zero(C, 4, m, n, ldc, c->stream); },
+                       "zero C")) != MPG_OK)
+    return st;
+  int slices = 0, moduli = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (S[k] == 0) continue;
+    const int pa = parts[k].a, pb = parts[k].b;
+    st = crt_product(c, m, n, l, A[2 * pa], A[2 * pa + 1], lda, pa ? eL : eH, BT[2 * pb], BT[2 * pb + 1],
+                     pb ? fL : fH, S[k], C, 4, ldc);
+    if (st != MPG_OK) return st;
+    slices = std::max(slices, S[k]);
+    moduli += c->last_moduli;
+  }
+  c->last_slices = slices;
+  c->last_moduli = moduli;
+  return MPG_OK;
 }
 
 extern "C" int mpg_ozaki_last_slices(const mpg_ctx* c) { return c ? c->last_slices : 0; }

@@ -64,6 +64,10 @@ std::vector<Cand> candidates(int prec, int64_t m, int64_t n, int64_t l) {
     out.push_back(z);
     z.algo = MPG_OZAKI_CRT;  // the same exact product through residues
     out.push_back(z);
+  } else {
+    Cand z{};
+    z.algo = MPG_OZAKI_CRT;  // three residue-form products of the double-double parts
+    out.push_back(z);
   }
   return out;
 }
@@ -400,7 +404,7 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
 extern "C" int mpg_tune_table_set(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l,
                                   int algo, const mpg_tile* tile) {
   if (!c || (precision != 2 && precision != 4) || algo < MPG_SIMPLE || algo > MPG_OZAKI_CRT ||
-      ((algo == MPG_OZAKI || algo == MPG_OZAKI_CRT) && precision != 2))
+      (algo == MPG_OZAKI && precision != 2))
     return MPG_ERR_ARG;
   mpg_tile t{};
   if (tile) t = *tile;
@@ -508,6 +512,11 @@ namespace {
 double method_bound(int in_limbs, int prec, int algo, const mpg_tile& t, int pairs, int64_t m,
                     int64_t l) {
   const double L = (double)l;
+  // quad-double through the residue form: the three kept part products are
+  // exact, each is rounded to quad-double and added (a few 2^-211 of the
+  // magnitudes), and the dropped product of the trailing parts is below
+  // 2^-210 l max|A| max|B| for canonical operands
+  if (algo == MPG_OZAKI_CRT && prec == 4) return std::ldexp(1.0, -204);
   if (algo == MPG_OZAKI) {
     if (in_limbs > 2 || t.slices < 1) return INFINITY;
     const int S = t.slices;
@@ -539,11 +548,12 @@ extern "C" double mpg_method_bound(int in_limbs, int precision, int algo, const 
   if ((in_limbs != 1 && in_limbs != 2 && in_limbs != 4) || (precision != 2 && precision != 4) ||
       m <= 0 || n <= 0 || l <= 0 || (algo == MPG_STRASSEN && (!tile || tile->depth < 1 || tile->depth > 3 ||
                                                               m != n || n != l)) ||
-      ((algo == MPG_OZAKI || algo == MPG_OZAKI_CRT) && (precision != 2 || !tile)) ||
+      (algo == MPG_OZAKI && (precision != 2 || !tile)) || (algo == MPG_OZAKI_CRT && precision == 2 && !tile) ||
       algo < MPG_SIMPLE || algo > MPG_OZAKI_CRT)
     return INFINITY;
   mpg_tile t{};
   if (tile) t = *tile;
+  if (algo == MPG_OZAKI_CRT && precision == 4) return method_bound(in_limbs, 4, MPG_OZAKI_CRT, t, 0, m, l);
   if (algo == MPG_OZAKI_CRT) return method_bound(in_limbs, precision, MPG_OZAKI, t, 2, m, l);
   if (algo == MPG_OZAKI && (pairs_mode < 0 || pairs_mode > 2)) return INFINITY;
   return method_bound(in_limbs, precision, algo, t, pairs_mode, m, l);
@@ -566,6 +576,7 @@ extern "C" int mpg_select_method(mpg_ctx* c, int64_t m, int64_t n, int64_t l, in
     if (method_bound(in_limbs, prec, a, t, pairs, m, l) <= target) feasible.push_back({prec, a, pairs, t});
   };
   const bool square = m == n && n == l;
+  consider(4, MPG_OZAKI_CRT, mpg_tile{}, 0);
   for (int prec : {2, 4}) {
     consider(prec, MPG_BLOCK, mpg_tile{}, 0);
     for (int d = 1; d <= (prec == 2 ? 3 : 2) && square && m >= (int64_t)64 << d; ++d) {

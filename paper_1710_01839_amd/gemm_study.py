@@ -3,7 +3,9 @@
     python -m paper_1710_01839_amd.gemm_study [--qd 512 1024 2048] [--batch 512]
 
 QD: every built QD tile alone, then Winograd-Strassen depth 1 and 2 over
-the default tile, on square n x n products of QD operands (limb 0 ~
+the default tile, and the residue form of the split INT8 product (three
+products of the operands' double-double parts), on square n x n products
+of QD operands (limb 0 ~
 U[-1, 1], each next limb inside the previous limb's half-ulp).  Per run:
 wall time, the multiply-add launch time, QD Gflop/s (2 n^3 / wall) and the
 fraction of the FP64 issue peak the multiply-add launch reaches (124 FP64
@@ -57,13 +59,20 @@ def main():
         C = M.empty_like_limbs(n, n, 4)
         runs = [("block", v) for v in M.variants(4)]
         runs += [("strassen", {"depth": d}) for d in (1, 2) if n >= 64 << d]
+        runs += [("ozaki_crt", None)]
         for algo, tile in runs:
             wall, kms = timed(lambda: M.mpgemm_qd(ctx, A, B, C, algo=algo, tile=tile), args.reps)
-            d = tile.get("depth", 0) if algo == "strassen" else 0
-            frac = (7 / 8) ** d * n ** 3 * QD_OPS_PER_MADD / (kms * 1e-3) / (FP64_ISSUE_PEAK_TOPS * 1e12)
-            print(json.dumps({"kind": "qd", "n": n, "algo": algo, "tile": tile, "wall_ms": round(wall, 3),
-                              "launch_ms": round(kms, 3), "qd_gflops": round(2.0 * n ** 3 / wall / 1e6, 1),
-                              "frac_fp64_issue_peak": round(frac, 4)}), flush=True)
+            rec = {"kind": "qd", "n": n, "algo": algo, "tile": tile, "wall_ms": round(wall, 3),
+                   "launch_ms": round(kms, 3), "qd_gflops": round(2.0 * n ** 3 / wall / 1e6, 1)}
+            if algo == "ozaki_crt":
+                # three residue-form products of the double-double parts; launch_ms is the
+                # mean INT8 product launch (one per part product)
+                rec.update({"slices": M.ozaki_last_slices(ctx), "moduli_all_products": M.ozaki_last_moduli(ctx)})
+            else:
+                d = tile.get("depth", 0) if algo == "strassen" else 0
+                rec["frac_fp64_issue_peak"] = round(
+                    (7 / 8) ** d * n ** 3 * QD_OPS_PER_MADD / (kms * 1e-3) / (FP64_ISSUE_PEAK_TOPS * 1e12), 4)
+            print(json.dumps(rec), flush=True)
         del A, B, C
         torch.cuda.empty_cache()
 

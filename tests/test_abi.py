@@ -59,12 +59,13 @@ def test_tuner_host_logic(lib):
     # simple + every tile + every tile under each admissible Strassen depth,
     # and for DD the split-precision product with the exact slice count
     assert len(M.candidates("dd", 4096, 4096, 4096)) == 1 + nv_dd * 4 + 2
-    assert len(M.candidates("qd", 2048, 2048, 2048)) == 1 + nv_qd * 3
+    assert len(M.candidates("qd", 2048, 2048, 2048)) == 1 + nv_qd * 3 + 1
     assert len(M.candidates("dd", 200, 200, 200)) == 1 + nv_dd * 2 + 2  # leaves >= 64: depth 1 only
     assert len(M.candidates("dd", 100, 5000, 5000)) == 1 + nv_dd + 2
     (a1, t1), (a2, t2) = M.candidates("dd", 512, 512, 512)[-2:]
     assert (a1, a2) == (M.MPG_OZAKI, M.MPG_OZAKI_CRT) and t1["slices"] == t2["slices"] == 0
     assert all(a != M.MPG_OZAKI for a, _ in M.candidates("qd", 512, 512, 512))
+    assert M.candidates("qd", 512, 512, 512)[-1][0] == M.MPG_OZAKI_CRT
     f = M.mlp_features("qd", 256, 512, 1024, "block", M.variants(4)[0], batch=8)
     assert f.dtype == np.float32 and f.shape == (M.MLP_FEATURES,)
     assert np.allclose(f[:3], [8 / 12, 9 / 12, 10 / 12]) and f[4] == 1 and f[6] == 1
@@ -106,6 +107,7 @@ def test_method_bounds_host_only(lib):
     assert M.method_bound(2, "dd", "ozaki", {"slices": 14}, "crt", 4096, 4096, 4096) == crt14
     assert M.method_bound(2, "dd", "ozaki_crt", {"slices": 14}, "all", 4096, 4096, 4096) == crt14
     assert M.method_bound(2, "dd", "ozaki", {"slices": 21}, "crt", 64, 64, 64) == inf
+    assert M.method_bound(4, "qd", "ozaki_crt", None, "all", 64, 64, 64) == 2.0 ** -204
     # truncation falls by 2^-8 per slice until the recombination term (which
     # grows with the square of the 2S - 1 diagonals) takes over near 2^-94
     b = [M.method_bound(1, "dd", "ozaki", {"slices": S}, "all", 512, 512, 512) for S in range(1, 16)]

@@ -145,3 +145,72 @@ def test_full_size_dd_sampled(gpu):
     for (i, j), v in zip(pairs, vals):
         got = Fraction(float(C[0][i, j])) + Fraction(float(C[1][i, j]))
         assert abs(got - v) <= REL * abs(v), (i, j)
+
+
+# ---------------------------------------------------------------------------
+# quad-double through the residue form (three products of the DD parts)
+# ---------------------------------------------------------------------------
+
+QD_BOUND = 8.0   # |C - AB| <= 8 l 2^-208 (|A||B|), the QD kernels' bound
+
+
+def run_qd(M, ctx, A, B, algo="ozaki_crt"):
+    m, n = A[0].shape[0], B[0].shape[1]
+    C = M.empty_like_limbs(m, n, 4)
+    M.mpgemm_qd(ctx, M.to_device(A), M.to_device(B), C, algo=algo)
+    torch.cuda.synchronize()
+    return M.to_host(C)
+
+
+@pytest.mark.parametrize("kind", ["qd", "dd_only", "integers", "mixed"])
+def test_qd_within_qd_bound(gpu, kind):
+    """Ragged shapes; every entry against the exact product (oracle
+    super-accumulator) within the QD kernels' componentwise bound."""
+    from tests.helpers import error_ratio_full
+    M, ctx = gpu
+    m, n, l = 130, 98, 150
+    if kind == "qd":
+        A, B = inputs.qd_uniform(m, l, 94), inputs.qd_uniform(l, n, 95)
+    elif kind == "dd_only":      # trailing parts zero: one product
+        A = inputs.with_limbs(inputs.dd_uniform(m, l, 96), 4)
+        B = inputs.with_limbs(inputs.dd_uniform(l, n, 97), 4)
+    elif kind == "integers":
+        A, B = inputs.integers(m, l, 4, 98, bits=20), inputs.integers(l, n, 4, 99, bits=20)
+    else:                        # QD rows, a zero row, DD columns
+        A = inputs.qd_uniform(m, l, 100)
+        A = tuple(p.copy() for p in A)
+        for p in A:
+            p[3, :] = 0.0
+        B = inputs.with_limbs(inputs.dd_uniform(l, n, 101), 4)
+    C = run_qd(M, ctx, A, B)
+    r, _ = error_ratio_full(C, A, B, -208)
+    print(kind, "slices", M.ozaki_last_slices(ctx), "moduli (all products)", M.ozaki_last_moduli(ctx),
+          "ratio", r)
+    assert r <= QD_BOUND
+    if kind == "integers":
+        want = A[0].astype(np.int64) @ B[0].astype(np.int64)
+        assert np.array_equal(C[0], want.astype(np.float64)) and not C[1].any()
+
+
+def test_qd_wide_parts_refused(gpu):
+    """Parts whose exact split needs more than 20 slices are refused."""
+    M, ctx = gpu
+    A, B = inputs.qd_uniform(64, 64, 102, illcond=True), inputs.qd_uniform(64, 64, 103, illcond=True)
+    with pytest.raises(M.MpgemmError) as ei:
+        run_qd(M, ctx, A, B)
+    assert ei.value.status == M.MPG_ERR_UNSUPPORTED
+
+
+def test_qd_full_size_sampled(gpu):
+    """m = n = l = 2048 quad-double operands: sampled entries against the
+    exact product, QD bound."""
+    M, ctx = gpu
+    nn = 2048
+    A, B = inputs.qd_uniform(nn, nn, 104), inputs.qd_uniform(nn, nn, 105)
+    C = run_qd(M, ctx, A, B)
+    g = np.random.default_rng(106)
+    pairs = sorted({(0, 0), (nn - 1, nn - 1), *[(int(g.integers(nn)), int(g.integers(nn))) for _ in range(10)]})
+    vals, mags = exact.entries_exact(A, B, pairs)
+    for (i, j), v, mg in zip(pairs, vals, mags):
+        got = sum((Fraction(float(p[i, j])) for p in C), Fraction(0))
+        assert abs(got - v) <= QD_BOUND * nn * Fraction(2) ** -208 * mg, (i, j)
