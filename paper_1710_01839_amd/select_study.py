@@ -19,7 +19,7 @@ import json
 import sys
 import time
 
-ALGO = {1: "simple", 2: "block", 3: "strassen", 4: "split INT8"}
+ALGO = {1: "simple", 2: "block", 3: "strassen", 4: "split INT8", 5: "split INT8, residue form of the DD parts"}
 
 
 def main():
