@@ -65,8 +65,11 @@ def test_real_dd_form(gpu, ta, tb, sc):
     assert r <= 1.0
 
 
-@pytest.mark.parametrize("ta,tb", [("T", "N"), ("N", "T"), ("T", "T")])
-def test_real_qd_form(gpu, ta, tb):
+@pytest.mark.parametrize("ta,tb,algo", [("T", "N", "block"), ("N", "T", "block"), ("T", "T", "block"),
+                                        ("T", "T", "ozaki_crt")])
+def test_real_qd_form(gpu, ta, tb, algo):
+    """QD form; the residue-form product (three exact part products) meets
+    the same bound."""
     M, ctx = gpu
     m, n, k = 37, 29, 41
     alpha = (-0.75, 2.0 ** -58, -2.0 ** -112, 2.0 ** -166)
@@ -75,7 +78,7 @@ def test_real_qd_form(gpu, ta, tb):
     _, B = stored(k, n, tb, 5, limbs=4)
     Cin = inputs.qd_uniform(m, n, seed_offset=6)
     Cd = M.to_device(Cin)
-    M.rgemm(ctx, M.to_device(A), M.to_device(B), Cd, alpha, beta, ta, tb)
+    M.rgemm(ctx, M.to_device(A), M.to_device(B), Cd, alpha, beta, ta, tb, algo)
     torch.cuda.synchronize()
     r = real_ratio(M.to_host(Cd), ta, tb, alpha, A, B, beta, Cin, k, -208)
     print(ta, tb, "qd ratio", r)
@@ -83,7 +86,8 @@ def test_real_qd_form(gpu, ta, tb):
 
 
 @pytest.mark.parametrize("algo,tile", [("block", None), ("simple", None),
-                                       ("strassen", {"depth": 1}), ("ozaki", {"slices": 0})])
+                                       ("strassen", {"depth": 1}), ("ozaki", {"slices": 0}),
+                                       ("ozaki_crt", {"slices": 0})])
 def test_transposes_are_bitwise_the_plain_product(gpu, algo, tile):
     """op(A) op(B) with alpha = 1, beta = 0 is the plain product of the
     transposed copies, bit for bit, for every algorithm; with alpha and beta
@@ -145,7 +149,8 @@ def test_complex_dd_form(gpu, ta, tb):
     assert rr <= 1.0 and ri <= 1.0
 
 
-@pytest.mark.parametrize("algo,tile", [("strassen", {"depth": 1}), ("ozaki", {"slices": 0})])
+@pytest.mark.parametrize("algo,tile", [("strassen", {"depth": 1}), ("ozaki", {"slices": 0}),
+                                       ("ozaki_crt", {"slices": 0})])
 def test_complex_other_products(gpu, algo, tile):
     """The embedding's product by Strassen or by the split product: a
     double-double-level normwise check, 2^-96 max|.| (|A||B|) per term."""
