@@ -122,8 +122,9 @@ int mpgemm_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
  * (|A||B|)_ij for SIMPLE and BLOCK (bitwise identical to each other).
  * MPG_OZAKI_CRT: each operand is split exactly into its double-double parts
  * (limbs 0 + 1, limbs 2 + 3); A_H B_H, A_H B_L and A_L B_H are formed
- * exactly by the residue form (exact slice count of each part, at most 20,
- * else MPG_ERR_UNSUPPORTED; synchronises the stream once for the counts)
+ * exactly by the residue form (one slice count, the largest exact count of
+ * the parts taking part, at most 20, else MPG_ERR_UNSUPPORTED; synchronises
+ * the stream once for the counts)
  * and added in quad-double; A_L B_L is left out (below 2^-210 (|A||B|) for
  * canonical operands). */
 int mpgemm_qd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,

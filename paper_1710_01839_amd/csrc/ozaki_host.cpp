@@ -314,9 +314,10 @@ extern "C" int mpgemm_dd_ozaki(mpg_ctx* c, int64_t m, int64_t n, int64_t l, cons
 // Quad-double C := A B through the residue form: each operand is split
 // exactly into its leading and trailing double-double parts (limbs 0 + 1 and
 // 2 + 3), A = A_H + A_L, B = B_H + B_L; C = A_H B_H + A_H B_L + A_L B_H, each
-// product exact with its own exact slice count (at most 20) and added into C
-// in quad-double; A_L B_L (below 2^-210 of |A||B| for canonical operands) is
-// left out.
+// product exact (one slice count for all three: the largest exact count of
+// the parts taking part, at most 20, so each part's residue planes serve
+// both of its products) and added into C in quad-double; A_L B_L (below
+// 2^-210 of |A||B| for canonical operands) is left out.
 int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const* A, int64_t lda,
                const double* const* B, int64_t ldb, double* const* C, int64_t ldc) {
   const int64_t mp = round_up(std::max<int64_t>(m, 1), 64), np = round_up(std::max<int64_t>(n, 1), 64);
@@ -364,16 +365,82 @@ int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const*
   if ((st = mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_zero(C, 4, m, n, ldc, c->stream); },
                        "zero C")) != MPG_OK)
     return st;
-  int slices = 0, moduli = 0;
+  // one slice count for the three products, so each part's residue planes
+  // are formed once and serve both products it takes part in
+  int Sc = 0;
+  for (int k = 0; k < 3; ++k) Sc = std::max(Sc, S[k]);
+  if (Sc == 0) {
+    c->last_slices = 0;
+    c->last_moduli = 0;
+    return MPG_OK;
+  }
+  const int N = crt_moduli_for_bits(crt_product_bits(Sc, l));
+  if (N == 0 || crt_words(N) == 0)
+    return mpg_fail(c, MPG_ERR_UNSUPPORTED, "product of %d slices at l = %lld is too wide for the moduli",
+                    Sc, (long long)l);
+  const int64_t lp = round_up(l, crt_k_multiple()), mpad = round_up(m, crt_tile_rows()),
+                npad = round_up(n, crt_tile_cols()), n4 = round_up(n, 4);
+  const int64_t planeA = mpad * lp, planeB = npad * lp;
+  const size_t cb = (sizeof(CrtResidueConsts) + 255) / 256 * 256;
+  void *res = nullptr, *out = nullptr;
+  if ((st = mpg_workspace(c, 7, (size_t)N * (size_t)(2 * planeA + 2 * planeB) + cb, &res)) != MPG_OK ||
+      (st = mpg_workspace(c, 8, (size_t)N * (size_t)(m * n4) + 256 + sizeof(CrtTable), &out)) != MPG_OK)
+    return st;
+  int8_t* Ares[2] = {(int8_t*)res, (int8_t*)res + (size_t)N * planeA};
+  int8_t* Bres[2] = {Ares[1] + (size_t)N * planeA, Ares[1] + (size_t)N * (planeA + planeB)};
+  CrtResidueConsts* consts = (CrtResidueConsts*)(Bres[1] + (size_t)N * planeB);
+  uint8_t* R = (uint8_t*)out;
+  CrtTable* table = (CrtTable*)((char*)out + ((size_t)N * (size_t)(m * n4) + 255) / 256 * 256);
+  // parts that take part in a product (a zero part takes part in none)
+  bool useA[2] = {false, false}, useB[2] = {false, false};
+  for (int k = 0; k < 3; ++k)
+    if (S[k] > 0) {
+      useA[parts[k].a] = true;
+      useB[parts[k].b] = true;
+    }
+  st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipError_t r = launch_crt_table(N, table, c->stream);
+    if (r != hipSuccess) return r;
+    if ((r = launch_crt_residue_consts(N, consts, c->stream)) != hipSuccess) return r;
+    for (int pa = 0; pa < 2; ++pa)
+      if (useA[pa] && (r = launch_crt_rows(A[2 * pa], A[2 * pa + 1], m, l, lda, pa ? eL : eH, Sc, N, Ares[pa],
+                                           mpad, lp, consts, c->stream)) != hipSuccess)
+        return r;
+    for (int pb = 0; pb < 2; ++pb)
+      if (useB[pb] && (r = launch_crt_rows(BT[2 * pb], BT[2 * pb + 1], n, l, l, pb ? fL : fH, Sc, N, Bres[pb],
+                                           npad, lp, consts, c->stream)) != hipSuccess)
+        return r;
+    return hipSuccess;
+  }, "residue planes");
+  if (st != MPG_OK) return st;
   for (int k = 0; k < 3; ++k) {
     if (S[k] == 0) continue;
     const int pa = parts[k].a, pb = parts[k].b;
-    st = crt_product(c, m, n, l, A[2 * pa], A[2 * pa + 1], lda, pa ? eL : eH, BT[2 * pb], BT[2 * pb + 1],
-                     pb ? fL : fH, S[k], C, 4, ldc);
-    if (st != MPG_OK) return st;
-    slices = std::max(slices, S[k]);
-    moduli += c->last_moduli;
+    CrtGemmArgs g{};
+    g.m = m;
+    g.n = n;
+    g.l_pad = lp;
+    g.A = Ares[pa];
+    g.B = Bres[pb];
+    g.planeA = planeA;
+    g.planeB = planeB;
+    g.R = R;
+    g.ldr = n4;
+    g.planeR = m * n4;
+    g.N = N;
+    for (int j = 0; j < N; ++j) g.mods[j] = kCrtModuli[j];
+    if ((st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_crt_gemm(g, c->stream); },
+                         "INT8 MFMA residue products")) != MPG_OK)
+      return st;
+    if ((st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+           return launch_crt_reconstruct(R, n4, m * n4, N, table, pa ? eL : eH, pb ? fL : fH, Sc, m, n, C, 4,
+                                         ldc, c->stream);
+         }, "residue reconstruction")) != MPG_OK)
+      return st;
   }
+  const int slices = Sc;
+  int moduli = 0;
+  for (int k = 0; k < 3; ++k) moduli += S[k] > 0 ? N : 0;
   c->last_slices = slices;
   c->last_moduli = moduli;
   return MPG_OK;
