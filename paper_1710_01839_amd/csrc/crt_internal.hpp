@@ -69,9 +69,12 @@ struct CrtResidueConsts {
 };
 hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s);
 
-// Residues of 8 elements' images (words[w][q], |sum_w word c| < 2^51, so
-// every step is exact in FP64) modulo p, each in [-p/2, p/2), packed as
-// signed bytes (element q in byte q).
+// Residues of 8 elements' images (words[w][q], the first NW words nonzero;
+// |sum_w word c| < 2^51, so the sum, the rounded quotient's product and the
+// remainder are exact in FP64) modulo p, each in [-p/2, p/2), packed as
+// signed bytes (element q in byte q).  The quotient rounded to nearest is
+// off by at most one, which one correction each way repairs.
+template <int NW>
 __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImageWords][8],
                                                   const double* c, int p) {
   const double pd = (double)p, inv = 1.0 / pd;
@@ -80,11 +83,10 @@ __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImag
   for (int q = 0; q < 8; ++q) {
     double acc = 0.0;
 #pragma unroll
-    for (int w = 0; w < kCrtImageWords; ++w) acc = __builtin_fma(words[w][q], c[w], acc);
-    double r = acc - floor(acc * inv) * pd;  // an integer; the quotient may be off by one
-    if (r >= pd) r -= pd;
-    if (r < 0.0) r += pd;
-    if (2.0 * r >= pd) r -= pd;  // into [-p/2, p/2)
+    for (int w = 0; w < NW; ++w) acc = __builtin_fma(words[w][q], c[w], acc);
+    double r = __builtin_fma(-rint(acc * inv), pd, acc);
+    if (2.0 * r >= pd) r -= pd;
+    if (2.0 * r < -pd) r += pd;
     packed |= (uint64_t)(uint8_t)(int8_t)(int)r << (8 * q);
   }
   return packed;

@@ -313,9 +313,16 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
     }
   }
   const int64_t plane = Rp * Kp;
-  for (int z = 0; z < N; ++z)
-    *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + r * Kp + k0) =
-        crt_residues8(words, rc->c[z], kCrtModuli[z]);
+  // images of up to 10 digits fill two words (uniform branch)
+  if (S <= 2 * kCrtDigitsPerWord) {
+    for (int z = 0; z < N; ++z)
+      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + r * Kp + k0) =
+          crt_residues8<2>(words, rc->c[z], kCrtModuli[z]);
+  } else {
+    for (int z = 0; z < N; ++z)
+      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + r * Kp + k0) =
+          crt_residues8<kCrtImageWords>(words, rc->c[z], kCrtModuli[z]);
+  }
 }
 
 // Columns of X (K x C, row-major) -> planes out[s][c][k] (transposed, c < Cp,
