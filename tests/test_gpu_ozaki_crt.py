@@ -214,3 +214,19 @@ def test_qd_full_size_sampled(gpu):
     for (i, j), v, mg in zip(pairs, vals, mags):
         got = sum((Fraction(float(p[i, j])) for p in C), Fraction(0))
         assert abs(got - v) <= QD_BOUND * nn * Fraction(2) ** -208 * mg, (i, j)
+
+
+@pytest.mark.parametrize("m,n,l", [(1, 1, 1), (1, 300, 7), (257, 1, 5), (3, 5, 1)])
+def test_small_and_thin_shapes(gpu, m, n, l):
+    """Degenerate shapes: one row, one column, one inner term; double-double
+    and quad-double residue forms against the exact product."""
+    from tests.helpers import error_ratio_full
+    M, ctx = gpu
+    A, B = inputs.dd_uniform(m, l, 110), inputs.dd_uniform(l, n, 111)
+    C = run_crt(M, ctx, A, B, 0)
+    r = worst_relative(C, A, B, M.ozaki_last_slices(ctx))
+    assert r <= 1.0
+    Aq, Bq = inputs.qd_uniform(m, l, 112), inputs.qd_uniform(l, n, 113)
+    Cq = run_qd(M, ctx, Aq, Bq)
+    rq, _ = error_ratio_full(Cq, Aq, Bq, -208)
+    assert rq <= QD_BOUND
