@@ -183,6 +183,31 @@ int mpg_zgemm_dd(mpg_ctx* ctx, mpg_op transa, mpg_op transb,
                  const double* const B[4], int64_t ldb, const double beta[4],
                  double* const C[4], int64_t ldc, mpg_algo algo, const mpg_tile* tile);
 
+/* ---- exact long-integer (fixed-point) products -------------------------- */
+
+/* C := A B exactly for matrices of long integers: the fixed-point analog of
+ * the paper's 128- to 2048-bit runs (a fixed-point number x 2^-f is its
+ * integer x; the product carries 2^-(fa + fb)).  Entries are two's
+ * complement integers of words_a / words_b 32-bit words (1..64: up to 2048
+ * bits), stored as word planes: word w of entry (i, k) of A is
+ * A[w * plane_a + i * lda + k] (DEVICE memory); likewise B (l x n) and C
+ * (m x n, words_c planes).  words_c must be at least
+ * mpg_int_words_needed(words_a, words_b, l), so every product fits and the
+ * result is exact.  Through INT8 matrix cores: entries are cut into 128-bit
+ * chunks; for each modulus of the residue form the chunk pairs of one
+ * diagonal (chunk indices summing to g) are multiplied in one INT8 product
+ * over a K made of the pairs; each diagonal's exact integer sum is rebuilt
+ * by the Chinese remainder theorem and added at 2^(128 g) into C.  C must
+ * not overlap A or B. */
+int mpg_int_gemm(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
+                 const uint32_t* A, int words_a, int64_t lda, int64_t plane_a,
+                 const uint32_t* B, int words_b, int64_t ldb, int64_t plane_b,
+                 uint32_t* C, int words_c, int64_t ldc, int64_t plane_c);
+/* Words that hold every entry of a product of words_a- and words_b-word
+ * operands with inner dimension l: ceil((32 (words_a + words_b) - 1 +
+ * bit length of l) / 32) (0 for bad arguments).  Host only. */
+int mpg_int_words_needed(int words_a, int words_b, int64_t l);
+
 /* ---- batches of uneven DD products ------------------------------------ */
 
 /* One problem C := A B of a batch (same conventions as mpgemm_dd). */

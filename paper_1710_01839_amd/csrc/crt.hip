@@ -84,81 +84,6 @@ __global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t) {
 //      (five words; the dropped ones are below 2^-96 of the top one) or
 //      added to a quad-double result (eight words, below 2^-192).
 // ---------------------------------------------------------------------
-template <int W>
-__device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const CrtTable& t,
-                                              uint32_t (&y)[W]) {
-  uint32_t x[W];
-  uint64_t carry = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    const uint64_t s = acc[w] + carry;
-    x[w] = (uint32_t)s;
-    carry = s >> 32;
-  }
-  double xd = 0.0;
-#pragma unroll
-  for (int w = W - 1; w >= 0; --w) xd += ldexp((double)x[w], 32 * w);
-  const uint32_t q = (uint32_t)floor(xd / t.Pd);
-  // Y = X' - q P
-  uint64_t mc = 0;
-  int64_t br = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    const uint64_t qp = (uint64_t)q * t.P[w] + mc;
-    mc = qp >> 32;
-    const int64_t d = (int64_t)x[w] - (int64_t)(uint32_t)qp + br;
-    y[w] = (uint32_t)d;
-    br = d >> 32;  // 0 or -1
-  }
-  if (br < 0) {  // q one too large: add P back
-    uint64_t c = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const uint64_t s = (uint64_t)y[w] + t.P[w] + c;
-      y[w] = (uint32_t)s;
-      c = s >> 32;
-    }
-  } else {
-    // Y >= P (q one too small): subtract P
-    bool ge = true;
-#pragma unroll
-    for (int w = W - 1; w >= 0; --w) {
-      if (y[w] != t.P[w]) {
-        ge = y[w] > t.P[w];
-        break;
-      }
-    }
-    if (ge) {
-      int64_t b2 = 0;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int64_t d = (int64_t)y[w] - (int64_t)t.P[w] + b2;
-        y[w] = (uint32_t)d;
-        b2 = d >> 32;
-      }
-    }
-  }
-  // centre
-  bool neg = true;  // Y >= P / 2
-#pragma unroll
-  for (int w = W - 1; w >= 0; --w) {
-    if (y[w] != t.half[w]) {
-      neg = y[w] > t.half[w];
-      break;
-    }
-  }
-  if (neg) {  // magnitude P - Y
-    int64_t b2 = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int64_t d = (int64_t)t.P[w] - (int64_t)y[w] + b2;
-      y[w] = (uint32_t)d;
-      b2 = d >> 32;
-    }
-  }
-  return neg;
-}
-
 // The signed value (magnitude words y, sign neg) times 2^scale as a
 // double-double: the top five words, each scaled exactly, summed by TwoSum.
 template <int W>

@@ -38,6 +38,10 @@ struct CrtTable {
 // K contiguous) and of B ([N][n_pad][l_pad]), padded as crt_tile_rows(),
 // crt_tile_cols() and crt_k_multiple() ask; output residues in [0, p_z) as
 // bytes, R[z * planeR + r * ldr + c].
+// K may run over several segments (a sum of products A_s B_s of equal
+// shape, one INT32 accumulation): segment s reads the planes at A + segA[s],
+// B + segB[s] (byte offsets; nseg 0 or 1 with zero offsets is one product).
+constexpr int kCrtMaxSegments = 16;
 struct CrtGemmArgs {
   int64_t m, n, l_pad;
   const int8_t* A;
@@ -47,6 +51,8 @@ struct CrtGemmArgs {
   int64_t ldr, planeR;
   int N;
   int mods[kCrtMaxModuli];
+  int nseg;
+  int64_t segA[kCrtMaxSegments], segB[kCrtMaxSegments];
 };
 
 // Bits the integer product can need: |(A' B')_ij| < l 2^(16 S - 4), and the
@@ -56,6 +62,86 @@ int crt_product_bits(int S, int64_t l);
 int crt_moduli_for_bits(int bits);
 // 32-bit words the reconstruction of N moduli uses (0 if unsupported).
 int crt_words(int N);
+
+// Reduces X' = sum_j r_j T_j (per 32-bit word in 64-bit accumulators, W
+// words) to the centred CRT value: returns its sign and writes its magnitude
+// words to y.  The quotient by P comes from doubles (off by at most one,
+// corrected by one addition or subtraction of P); Y >= P / 2 stands for
+// Y - P.
+template <int W>
+__device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const CrtTable& t,
+                                              uint32_t (&y)[W]) {
+  uint32_t x[W];
+  uint64_t carry = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint64_t s = acc[w] + carry;
+    x[w] = (uint32_t)s;
+    carry = s >> 32;
+  }
+  double xd = 0.0;
+#pragma unroll
+  for (int w = W - 1; w >= 0; --w) xd += ldexp((double)x[w], 32 * w);
+  const uint32_t q = (uint32_t)floor(xd / t.Pd);
+  // Y = X' - q P
+  uint64_t mc = 0;
+  int64_t br = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint64_t qp = (uint64_t)q * t.P[w] + mc;
+    mc = qp >> 32;
+    const int64_t d = (int64_t)x[w] - (int64_t)(uint32_t)qp + br;
+    y[w] = (uint32_t)d;
+    br = d >> 32;  // 0 or -1
+  }
+  if (br < 0) {  // q one too large: add P back
+    uint64_t c = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t s = (uint64_t)y[w] + t.P[w] + c;
+      y[w] = (uint32_t)s;
+      c = s >> 32;
+    }
+  } else {
+    // Y >= P (q one too small): subtract P
+    bool ge = true;
+#pragma unroll
+    for (int w = W - 1; w >= 0; --w) {
+      if (y[w] != t.P[w]) {
+        ge = y[w] > t.P[w];
+        break;
+      }
+    }
+    if (ge) {
+      int64_t b2 = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int64_t d = (int64_t)y[w] - (int64_t)t.P[w] + b2;
+        y[w] = (uint32_t)d;
+        b2 = d >> 32;
+      }
+    }
+  }
+  // centre
+  bool neg = true;  // Y >= P / 2
+#pragma unroll
+  for (int w = W - 1; w >= 0; --w) {
+    if (y[w] != t.half[w]) {
+      neg = y[w] > t.half[w];
+      break;
+    }
+  }
+  if (neg) {  // magnitude P - Y
+    int64_t b2 = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int64_t d = (int64_t)t.P[w] - (int64_t)y[w] + b2;
+      y[w] = (uint32_t)d;
+      b2 = d >> 32;
+    }
+  }
+  return neg;
+}
 
 hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s);
 

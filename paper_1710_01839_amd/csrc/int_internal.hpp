@@ -1,0 +1,43 @@
+// Internal interface of the long-integer product (intgemm.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "crt_internal.hpp"
+
+namespace mpg {
+
+// Largest operand size: 64 words (2048 bits, 16 chunks of 128 bits).
+constexpr int kIntMaxWords = 4 * kCrtMaxSegments;
+
+// Residue planes of every 128-bit chunk of X's entries (R x K logical, word
+// planes `pstride` elements apart, leading dimension ld; with cols the
+// logical (r, k) entry is X[k][r]): out[(c N + z) Rp Kp + r Kp + k], zeros in
+// the padding (Rp a multiple of 32, Kp of 64).
+struct IntResidueArgs {
+  const uint32_t* X;
+  int words;
+  int64_t pstride, ld;
+  int64_t R, K, Rp, Kp;
+  int chunks, N;
+  int8_t* out;
+};
+
+// C (words_c word planes, pstride apart, leading dimension ldc) += the CRT
+// values of the residue planes R (N planes, ldr, planeR) times 2^(32 word_off).
+struct IntAccumArgs {
+  const uint8_t* R;
+  int64_t ldr, planeR;
+  int N;
+  const CrtTable* t;
+  uint32_t* C;
+  int words_c, word_off;
+  int64_t pstride, ldc, m, n;
+};
+
+hipError_t launch_int_residues(const IntResidueArgs& a, bool cols, hipStream_t s);
+hipError_t launch_int_accumulate(const IntAccumArgs& a, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* C, int words, int64_t pstride, int64_t m, int64_t n, int64_t ldc,
+                           hipStream_t s);
+
+}  // namespace mpg

@@ -1,0 +1,196 @@
+// Exact product of long-integer matrices through the residue form: the
+// fixed-point analog of the paper's arbitrary-precision runs.
+//
+// Entries are two's complement integers of `words` 32-bit words, stored as
+// word planes (plane w: word w of every entry).  An entry is cut into 128-bit
+// chunks, x = sum_c U_c 2^(128 c) with U_c in [0, 2^128) below the top chunk
+// and the top chunk signed.  For each chunk the residues modulo the N leading
+// moduli are formed directly from its four words; the products of chunk
+// pairs on one diagonal g = c + d run as one INT8 product over a K made of
+// the pairs (segments), and each diagonal's exact integer Y_g is rebuilt and
+// added at 2^(128 g) into the multiword result.
+#include "crt_internal.hpp"
+#include "int_internal.hpp"
+
+namespace mpg {
+namespace {
+
+// 2^(32 j) mod p_z for the N moduli, built by the first threads of a block.
+struct WordWeights {
+  double c[kCrtMaxModuli][4];
+};
+
+__device__ void word_weights(WordWeights& w, int N) {
+  for (int z = threadIdx.x; z < N; z += blockDim.x) {
+    const uint64_t p = (uint64_t)kCrtModuli[z];
+    uint64_t v = 1;
+    for (int j = 0; j < 4; ++j) {
+      w.c[z][j] = (double)v;
+      v = (v << 32) % p;
+    }
+  }
+}
+
+// Chunk c of an entry (four words from word 4c; words past the entry's own
+// are its sign extension; the top chunk's last word is signed).
+__device__ __forceinline__ void chunk_words(const uint32_t* X, int64_t pstride, int64_t off, int words,
+                                            int c, int chunks, bool ok, double (&v)[4]) {
+  const int64_t top_word = (int64_t)words - 1;
+  uint32_t sign = 0;
+  if (ok) sign = (int32_t)X[top_word * pstride + off] < 0 ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int w = 4 * c + j;
+    uint32_t u = 0;
+    if (ok) u = w < words ? X[(int64_t)w * pstride + off] : sign;
+    v[j] = (c == chunks - 1 && j == 3) ? (double)(int32_t)u : (double)u;
+  }
+}
+
+// Residue planes of all chunks: out[(c N + z) plane + r Kp + k].  COLS:
+// element (r, k) is X[w][k][r] (the columns of B); else X[w][r][k].
+// Rows: a thread takes 8 consecutive k of one row.  Columns: a block takes
+// 32 columns x 64 k, a thread 8 consecutive k of one column (reads of one k
+// across the 32 columns are contiguous).
+template <bool COLS>
+__global__ __launch_bounds__(256) void int_residue_kernel(IntResidueArgs a) {
+  __shared__ WordWeights ww;
+  word_weights(ww, a.N);
+  __syncthreads();
+  int64_t r, k0;
+  if (!COLS) {
+    const int64_t per_row = a.Kp / 8;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.Rp * per_row) return;
+    r = idx / per_row;
+    k0 = (idx % per_row) * 8;
+  } else {
+    r = (int64_t)blockIdx.x * 32 + threadIdx.x % 32;
+    k0 = (int64_t)blockIdx.y * 64 + 8 * (threadIdx.x / 32);
+    if (r >= a.Rp || k0 >= a.Kp) return;
+  }
+  const int64_t plane = a.Rp * a.Kp;
+  for (int c = 0; c < a.chunks; ++c) {
+    // the chunk's four words of 8 elements
+    double v[4][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t k = k0 + q;
+      const bool ok = r < a.R && k < a.K;
+      const int64_t off = ok ? (COLS ? k * a.ld + r : r * a.ld + k) : 0;
+      double t[4];
+      chunk_words(a.X, a.pstride, off, a.words, c, a.chunks, ok, t);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j][q] = t[j];
+    }
+    for (int z = 0; z < a.N; ++z) {
+      const double pd = (double)kCrtModuli[z], inv = 1.0 / pd;
+      uint64_t packed = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        double acc = 0.0;  // |acc| < 4 2^32 256: exact
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = __builtin_fma(v[j][q], ww.c[z][j], acc);
+        double res = __builtin_fma(-rint(acc * inv), pd, acc);
+        if (2.0 * res >= pd) res -= pd;
+        if (2.0 * res < -pd) res += pd;
+        packed |= (uint64_t)(uint8_t)(int8_t)(int)res << (8 * q);
+      }
+      *reinterpret_cast<uint64_t*>(a.out + ((int64_t)c * a.N + z) * plane + r * a.Kp + k0) = packed;
+    }
+  }
+}
+
+// Rebuilds each entry's diagonal sum Y (W words) and adds it, signed, into
+// C's words from `word_off` up (carries and borrows run to the top word).
+template <int W>
+__global__ __launch_bounds__(256) void int_accumulate_kernel(IntAccumArgs a) {
+  const int64_t j0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
+  if (j0 >= a.n) return;
+  const CrtTable& t = *a.t;
+  for (int64_t i = blockIdx.y; i < a.m; i += gridDim.y) {
+    uint64_t acc[4][W];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[b][w] = 0;
+    const uint8_t* row = a.R + i * a.ldr + j0;
+    for (int z = 0; z < a.N; ++z) {
+      const uint32_t r4 = *reinterpret_cast<const uint32_t*>(row + (int64_t)z * a.planeR);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint32_t tw = t.T[z][w];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b][w] += (uint64_t)((r4 >> (8 * b)) & 0xffu) * tw;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (j0 + b >= a.n) continue;
+      uint32_t y[W];
+      const bool neg = crt_magnitude<W>(acc[b], t, y);
+      uint32_t* cw = a.C + i * a.ldc + j0 + b;
+      // C += (neg ? -Y : Y) at word_off, in two's complement over words_c words
+      int64_t carry = 0;
+      for (int w = a.word_off; w < a.words_c; ++w) {
+        const int64_t yw = w - a.word_off < W ? (int64_t)y[w - a.word_off] : 0;
+        if (yw == 0 && carry == 0 && w - a.word_off >= W) break;
+        const int64_t cur = (int64_t)cw[(int64_t)w * a.pstride];
+        const int64_t s = neg ? cur - yw + carry : cur + yw + carry;
+        cw[(int64_t)w * a.pstride] = (uint32_t)s;
+        carry = s >> 32;  // -1, 0 or 1
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t* C, int words, int64_t pstride, int64_t m,
+                                                       int64_t n, int64_t ldc) {
+  const int64_t total = m * n;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+    const int64_t off = (idx / n) * ldc + idx % n;
+    for (int w = 0; w < words; ++w) C[(int64_t)w * pstride + off] = 0u;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_int_residues(const IntResidueArgs& a, bool cols, hipStream_t s) {
+  if (a.chunks < 1 || a.N < 1 || a.N > kCrtMaxModuli || a.Kp % 64 || a.Rp % 32) return hipErrorInvalidValue;
+  if (a.Rp <= 0 || a.Kp <= 0) return hipSuccess;
+  if (!cols) {
+    const int64_t work = a.Rp * (a.Kp / 8);
+    hipLaunchKernelGGL(int_residue_kernel<false>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, a);
+  } else {
+    if (a.Kp / 64 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(int_residue_kernel<true>, dim3((unsigned)(a.Rp / 32), (unsigned)(a.Kp / 64)), dim3(256),
+                       0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_int_accumulate(const IntAccumArgs& a, hipStream_t s) {
+  if (a.m <= 0 || a.n <= 0) return hipSuccess;
+  if (a.ldr % 4 || a.ldr < a.n) return hipErrorInvalidValue;
+  const int64_t gx = ((a.n + 3) / 4 + 255) / 256;
+  const dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(a.m, 65535));
+  switch (crt_words(a.N)) {
+    case 4: hipLaunchKernelGGL(int_accumulate_kernel<4>, grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(int_accumulate_kernel<6>, grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(int_accumulate_kernel<8>, grid, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL(int_accumulate_kernel<10>, grid, dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL(int_accumulate_kernel<12>, grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* C, int words, int64_t pstride, int64_t m, int64_t n, int64_t ldc,
+                           hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((m * n + 255) / 256, 65536);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, C, words, pstride, m, n, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace mpg

@@ -1025,14 +1025,19 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
   const int wr = wave / 2, wc = wave % 2;
   const uint32_t lane_off = (uint32_t)((lane % 16) * lp + 16 * (lane / 16));
 
+  // K steps per segment; the segments' products add up in one accumulation
+  const int kps = (int)(lp / 64);
   // K step `st` into its ring slot: blocks round-robin over the waves
   auto issue = [&](int st) {
     int8_t* dst = lds + (st % NBUF) * STAGE;
+    const int seg = st / kps, kk = st - seg * kps;
+    const int8_t* As = A + c.segA[seg];
+    const int8_t* Bs = B + c.segB[seg];
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       const int b = wave + 8 * i;
-      const int8_t* src = b < kCrtNBA ? A + (m0 + 16 * b) * lp : B + (n0 + 16 * (b - kCrtNBA)) * lp;
-      oz_dma(src, lane_off + (uint32_t)st * 64, dst + b * 1024);
+      const int8_t* src = b < kCrtNBA ? As + (m0 + 16 * b) * lp : Bs + (n0 + 16 * (b - kCrtNBA)) * lp;
+      oz_dma(src, lane_off + (uint32_t)kk * 64, dst + b * 1024);
     }
   };
 
@@ -1042,7 +1047,7 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
 #pragma unroll
     for (int bj = 0; bj < kCrtWN; ++bj) acc[bi][bj] = v4i{0, 0, 0, 0};
 
-  const int numK = (int)(lp / 64);
+  const int numK = kps * c.nseg;
 #pragma unroll
   for (int s = 0; s < NBUF - 1; ++s)
     if (s < numK) issue(s);
@@ -1245,12 +1250,14 @@ hipError_t launch_crt_gemm(const CrtGemmArgs& c, hipStream_t s) {
   const int64_t tiles_m = (c.m + kCrtBM - 1) / kCrtBM, tiles_n = (c.n + kCrtBN - 1) / kCrtBN;
   const int64_t total = tiles_m * tiles_n * c.N;
   if (total <= 0) return hipSuccess;
-  if (total > 0x7fffffff || c.N > kCrtMaxModuli || c.l_pad % 64) return hipErrorInvalidValue;
+  if (total > 0x7fffffff || c.N > kCrtMaxModuli || c.l_pad % 64 || c.nseg > kCrtMaxSegments)
+    return hipErrorInvalidValue;
   constexpr int NBUF = 4;
   // INT32 sums: |r r'| <= 128^2 per product, 64 per K step, plus the
   // reduced residue carried over (< 256): reduce every 2047 K steps
   const int kchunk = (int)((2147483647.0 - 256.0) / (64.0 * 128.0 * 128.0));
   CrtGemmArgs args = c;
+  if (args.nseg < 1) args.nseg = 1;
   int tm = (int)tiles_m, tn = (int)tiles_n, kc = kchunk;
   void* kargs[] = {(void*)&args, (void*)&tm, (void*)&tn, (void*)&kc};
   return hipLaunchKernel(reinterpret_cast<const void*>(&crt_tile_kernel<NBUF>), dim3((unsigned)total),

@@ -98,6 +98,8 @@ _sig("mpg_rgemm", [_vp, _ci, _ci, _ci, _i64, _i64, _i64, _pd, _pp, _i64, _pp, _i
                    _ci, ctypes.POINTER(mpg_tile)])
 _sig("mpg_zgemm_dd", [_vp, _ci, _ci, _i64, _i64, _i64, _pd, _pp, _i64, _pp, _i64, _pd, _pp, _i64,
                       _ci, ctypes.POINTER(mpg_tile)])
+_sig("mpg_int_gemm", [_vp, _i64, _i64, _i64, _vp, _ci, _i64, _i64, _vp, _ci, _i64, _i64, _vp, _ci, _i64, _i64])
+_sig("mpg_int_words_needed", [_ci, _ci, _i64])
 _sig("mpgemm_dd_batched", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile)])
 _sig("mpg_batch_plan_create", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile),
                                ctypes.POINTER(_vp)])
@@ -332,6 +334,32 @@ def zgemm_dd(ctx: Context, A, B, C, alpha=(1.0, 0.0, 0.0, 0.0), beta=(0.0, 0.0, 
                            ALGOS.get(algo, algo) if isinstance(algo, str) else algo,
                            ctypes.byref(t) if t is not None else None)
     ctx.check(st, "mpg_zgemm_dd")
+    return C
+
+
+def int_words_needed(words_a: int, words_b: int, l: int) -> int:
+    return int(_lib.mpg_int_words_needed(int(words_a), int(words_b), int(l)))
+
+
+def _words(t: torch.Tensor, name: str):
+    if t.dtype != torch.int32 or not t.is_cuda or t.dim() != 3 or not t.is_contiguous():
+        raise MpgemmError(MPG_ERR_ARG, f"{name} must be a contiguous int32 device tensor (words, rows, cols)")
+    return t.shape[0], t.shape[1], t.shape[2]
+
+
+def int_gemm(ctx: Context, A, B, C):
+    """C := A B exactly for long integers stored as word planes: int32 device
+    tensors of shape (words, rows, cols), word 0 least significant, two's
+    complement over all words (the bits are read as unsigned words)."""
+    wa, m, l = _words(A, "A")
+    wb, l2, n = _words(B, "B")
+    wc, m2, n2 = _words(C, "C")
+    if l2 != l or (m2, n2) != (m, n):
+        raise MpgemmError(MPG_ERR_ARG, "shape mismatch")
+    ctx.bind_stream()
+    st = _lib.mpg_int_gemm(ctx.handle, m, n, l, _ptr(A), wa, l, m * l, _ptr(B), wb, n, l * n,
+                           _ptr(C), wc, n, m * n)
+    ctx.check(st, "mpg_int_gemm")
     return C
 
 

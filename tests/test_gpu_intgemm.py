@@ -1,0 +1,109 @@
+"""GPU parity of the exact long-integer (fixed-point) product against the
+exact oracle: every word of every entry equal (bit-exact), for operand sizes
+from 32 to 2048 bits, signs and extreme values, ragged shapes, long K, and
+the argument checks."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bigint
+
+pytestmark = pytest.mark.gpu
+
+
+def rand_planes(g, rows, cols, words, extreme=False):
+    """Uniform two's complement integers of 32 words bits (every bit random);
+    with extreme, the most negative and most positive values mixed in."""
+    P = g.integers(0, 1 << 32, size=(words, rows, cols), dtype=np.uint64).astype(np.uint32)
+    if extreme:
+        P[:, 0, :] = 0
+        P[-1, 0, :] = 0x80000000          # most negative
+        P[:, -1, :] = 0xFFFFFFFF
+        P[-1, -1, :] = 0x7FFFFFFF         # most positive
+    return P
+
+
+def run(M, ctx, A, B, words_c=None):
+    l = A.shape[2]
+    wc = words_c or M.int_words_needed(A.shape[0], B.shape[0], l)
+    Ad = torch.as_tensor(A.view(np.int32)).cuda()
+    Bd = torch.as_tensor(B.view(np.int32)).cuda()
+    Cd = torch.empty((wc, A.shape[1], B.shape[2]), dtype=torch.int32, device="cuda")
+    M.int_gemm(ctx, Ad, Bd, Cd)
+    torch.cuda.synchronize()
+    return Cd.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("wa,wb", [(1, 1), (2, 3), (4, 4), (5, 9), (8, 8), (16, 16), (32, 7)])
+def test_bit_exact(gpu, wa, wb):
+    M, ctx = gpu
+    g = np.random.default_rng(wa * 100 + wb)
+    m, n, l = 67, 45, 83
+    A = rand_planes(g, m, l, wa, extreme=True)
+    B = rand_planes(g, l, n, wb, extreme=True)
+    C = run(M, ctx, A, B)
+    want = bigint.gemm(A, B)
+    print(wa, wb, "words_c", C.shape[0], "moduli", M._lib.mpg_ozaki_last_moduli(ctx.handle))
+    assert np.array_equal(C, want)
+
+
+def test_2048_bits_and_small_values(gpu):
+    """64-word operands (2048 bits, 16 chunks: 31 diagonals, up to 16 chunk
+    pairs per product); then small values in wide words (upper chunks zero or
+    sign extension)."""
+    M, ctx = gpu
+    g = np.random.default_rng(7)
+    A = rand_planes(g, 9, 20, 64)
+    B = rand_planes(g, 20, 11, 64)
+    assert np.array_equal(run(M, ctx, A, B), bigint.gemm(A, B))
+    small_a = np.zeros((12, 30, 40), dtype=np.uint32)
+    small_b = np.zeros((12, 40, 20), dtype=np.uint32)
+    va = g.integers(-1000, 1000, size=(30, 40))
+    vb = g.integers(-1000, 1000, size=(40, 20))
+    small_a[:] = np.where(va < 0, 0xFFFFFFFF, 0).astype(np.uint32)
+    small_b[:] = np.where(vb < 0, 0xFFFFFFFF, 0).astype(np.uint32)
+    small_a[0] = va.astype(np.int64).astype(np.uint32)
+    small_b[0] = vb.astype(np.int64).astype(np.uint32)
+    C = run(M, ctx, small_a, small_b)
+    assert np.array_equal(C, bigint.gemm(small_a, small_b))
+
+
+def test_long_k(gpu):
+    """l = 9000: several reductions of the INT32 sums inside each product."""
+    M, ctx = gpu
+    g = np.random.default_rng(8)
+    A = rand_planes(g, 5, 9000, 4)
+    B = rand_planes(g, 9000, 6, 2)
+    assert np.array_equal(run(M, ctx, A, B), bigint.gemm(A, B))
+
+
+def test_full_size_sampled(gpu):
+    """m = n = l = 1024 with 1024-bit operands: sampled entries exact."""
+    M, ctx = gpu
+    g = np.random.default_rng(9)
+    nn, w = 1024, 32
+    A = rand_planes(g, nn, nn, w)
+    B = rand_planes(g, nn, nn, w)
+    C = run(M, ctx, A, B)
+    rows = [0, 5, 511, nn - 1]
+    cols = [0, 17, 700, nn - 1]
+    want = bigint.gemm(np.ascontiguousarray(A[:, rows, :]), np.ascontiguousarray(B[:, :, cols]), C.shape[0])
+    assert np.array_equal(C[:, rows][:, :, cols], want)
+
+
+def test_argument_checks(gpu):
+    M, ctx = gpu
+    A = torch.zeros((2, 4, 4), dtype=torch.int32, device="cuda")
+    B = torch.zeros((2, 4, 4), dtype=torch.int32, device="cuda")
+    small = torch.zeros((4, 4, 4), dtype=torch.int32, device="cuda")   # needs 5 words
+    assert M.int_words_needed(2, 2, 4) == 5
+    with pytest.raises(M.MpgemmError) as ei:
+        M.int_gemm(ctx, A, B, small)
+    assert ei.value.status == M.MPG_ERR_ARG
+    with pytest.raises(M.MpgemmError):
+        M.int_gemm(ctx, torch.zeros((65, 4, 4), dtype=torch.int32, device="cuda"), B,
+                   torch.zeros((70, 4, 4), dtype=torch.int32, device="cuda"))
+    C = torch.full((5, 4, 4), 7, dtype=torch.int32, device="cuda")
+    M.int_gemm(ctx, A, B, C)       # zero operands: C := 0 in every word
+    torch.cuda.synchronize()
+    assert not C.any()
