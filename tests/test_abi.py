@@ -124,3 +124,15 @@ def test_crt_moduli_match_oracle(lib):
             want = crt.moduli_for_bits(crt.product_bits(S, l)) or 0
             assert M.crt_moduli_for(S, l) == want, (S, l)
     assert M.crt_moduli_for(21, 64) == 0 and M.crt_moduli_for(0, 64) == 0
+
+
+def test_int_words_needed_matches_oracle(lib):
+    """Output word count of the exact long-integer product (host only) equals
+    the oracle's bound for every operand size pair and a range of l."""
+    from oracle import bigint
+    from paper_1710_01839_amd import mpgemm as M
+    for wa in (1, 2, 3, 4, 7, 16, 64):
+        for wb in (1, 5, 32, 64):
+            for l in (1, 2, 3, 4, 5, 1000, 1024, 1025, 1 << 20):
+                assert M.int_words_needed(wa, wb, l) == bigint.words_needed(wa, wb, l), (wa, wb, l)
+    assert M.int_words_needed(0, 1, 5) == 0
