@@ -51,7 +51,9 @@ typedef enum {
 } mpg_status;
 
 typedef enum {
-  MPG_AUTO = 0,     /* use the context's tuning table, else a default */
+  MPG_AUTO = 0,     /* use the context's tuning table, else a default; a tabled split
+                       product the data's exact slice count rules out falls back to
+                       MPG_BLOCK of the same precision */
   MPG_SIMPLE = 1,   /* Eq. (1): one thread per c_ij, k in order */
   MPG_BLOCK = 2,    /* Eq. (2): LDS-staged tiles, register-blocked accumulators */
   MPG_STRASSEN = 3, /* Eq. (3), Winograd's form, `depth` levels over MPG_BLOCK */

@@ -433,21 +433,32 @@ int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
                       "zero C");
   mpg_tile chosen{};
   if (tile) chosen = *tile;
+  bool from_table = false;
   if (algo == MPG_AUTO) {
     int a = MPG_BLOCK;
     mpg_tile t{};
     if (mpg_table_lookup(c, limbs, m, n, l, &a, &t)) {
       algo = (mpg_algo)a;
       chosen = t;
+      from_table = true;
     } else {
       algo = MPG_BLOCK;
     }
   }
-  if (algo == MPG_OZAKI_CRT && limbs == 4) return mpg_qd_crt(c, m, n, l, A, lda, B, ldb, C, ldc);
   if (algo == MPG_OZAKI || algo == MPG_OZAKI_CRT) {
-    if (limbs != 2) return mpg_fail(c, MPG_ERR_UNSUPPORTED, "the digit form of the split product is DD only");
-    return mpgemm_dd_ozaki(c, m, n, l, A[0], A[1], lda, B[0], B[1], ldb, C[0], C[1], ldc,
-                           chosen.slices, algo == MPG_OZAKI_CRT ? 2 : 0);
+    if (algo == MPG_OZAKI && limbs != 2)
+      return mpg_fail(c, MPG_ERR_UNSUPPORTED, "the digit form of the split product is DD only");
+    st = algo == MPG_OZAKI_CRT && limbs == 4
+             ? mpg_qd_crt(c, m, n, l, A, lda, B, ldb, C, ldc)
+             : mpgemm_dd_ozaki(c, m, n, l, A[0], A[1], lda, B[0], B[1], ldb, C[0], C[1], ldc, chosen.slices,
+                               algo == MPG_OZAKI_CRT ? 2 : 0);
+    // a tuned split product that the data's exact slice count rules out
+    // (nothing is written to C then) falls back to the block kernel of the
+    // same precision, so MPG_AUTO runs on any canonical input
+    if (st != MPG_ERR_UNSUPPORTED || !from_table) return st;
+    c->last_error.clear();
+    algo = MPG_BLOCK;
+    chosen = mpg_tile{};
   }
   int variant = 0;
   st = mpg_resolve_variant(c, limbs, &chosen, &variant);

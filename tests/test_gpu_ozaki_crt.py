@@ -230,3 +230,32 @@ def test_small_and_thin_shapes(gpu, m, n, l):
     Cq = run_qd(M, ctx, Aq, Bq)
     rq, _ = error_ratio_full(Cq, Aq, Bq, -208)
     assert rq <= QD_BOUND
+
+
+def test_auto_falls_back_when_the_split_is_ruled_out(gpu):
+    """A tuning-table entry naming the residue form, on data whose exact
+    split needs more than 20 slices: MPG_AUTO runs the block kernel instead,
+    bit for bit (DD and QD); the explicit call is still refused."""
+    M, ctx = gpu
+    T = M.Tuner(ctx)
+    m, n, l = 40, 24, 32
+    A = inputs.dd_uniform(m, l, 120)
+    A = (A[0].copy(), A[1].copy())
+    A[0][:, 3] = 2.0 ** -220           # far below the row scale: > 20 slices
+    B = inputs.dd_uniform(l, n, 121)
+    T.table_set("dd", m, n, l, "ozaki_crt", {"slices": 0})
+    C1, C2 = M.empty_like_limbs(m, n, 2), M.empty_like_limbs(m, n, 2)
+    M.mpgemm_dd(ctx, M.to_device(A), M.to_device(B), C1, algo="auto")
+    M.mpgemm_dd(ctx, M.to_device(A), M.to_device(B), C2, algo="block")
+    torch.cuda.synchronize()
+    assert torch.equal(C1[0], C2[0]) and torch.equal(C1[1], C2[1])
+    with pytest.raises(M.MpgemmError):
+        M.mpgemm_dd(ctx, M.to_device(A), M.to_device(B), C2, algo="ozaki_crt", tile={"slices": 0})
+    Aq, Bq = inputs.qd_uniform(m, l, 122, illcond=True), inputs.qd_uniform(l, n, 123, illcond=True)
+    T.table_set("qd", m, n, l, "ozaki_crt", None)
+    Q1, Q2 = M.empty_like_limbs(m, n, 4), M.empty_like_limbs(m, n, 4)
+    M.mpgemm_qd(ctx, M.to_device(Aq), M.to_device(Bq), Q1, algo="auto")
+    M.mpgemm_qd(ctx, M.to_device(Aq), M.to_device(Bq), Q2, algo="block")
+    torch.cuda.synchronize()
+    for p, q in zip(Q1, Q2):
+        assert torch.equal(p, q)
