@@ -34,8 +34,9 @@ struct CrtTable {
   int N;
 };
 
-// One INT8 product per modulus: residue planes z of A ([N][m_pad][l_pad],
-// K contiguous) and of B ([N][n_pad][l_pad]), padded as crt_tile_rows(),
+// One INT8 product per modulus: residue planes z of A ([N] planes of
+// m_pad x l_pad) and of B ([N] planes of n_pad x l_pad, the columns of B as
+// rows), in the tiled layout of crt_plane_offset, padded as crt_tile_rows(),
 // crt_tile_cols() and crt_k_multiple() ask; output residues in [0, p_z) as
 // bytes, R[z * planeR + r * ldr + c].
 // K may run over several segments (a sum of products A_s B_s of equal
@@ -62,6 +63,14 @@ int crt_product_bits(int S, int64_t l);
 int crt_moduli_for_bits(int bits);
 // 32-bit words the reconstruction of N moduli uses (0 if unsupported).
 int crt_words(int N);
+
+// Byte offset of element (r, k) in a residue plane of Kp columns: planes are
+// stored in 1 KiB blocks of 16 rows x 64 k (block (r / 16, k / 64), row-major
+// inside), so the 16 x 64 operand block of one K step is one contiguous
+// kibibyte (whole cache lines) for the product kernel's LDS loads.
+__host__ __device__ __forceinline__ int64_t crt_plane_offset(int64_t r, int64_t k, int64_t Kp) {
+  return ((r >> 4) * (Kp >> 6) + (k >> 6)) * 1024 + (r & 15) * 64 + (k & 63);
+}
 
 // Reduces X' = sum_j r_j T_j (per 32-bit word in 64-bit accumulators, W
 // words) to the centred CRT value: returns its sign and writes its magnitude
@@ -182,8 +191,8 @@ __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImag
 // X + Xlo as one exact value when Xlo is given) and its scale e[r], the S
 // truncated radix-256 digits of x 2^-(e + 2) are folded into the image
 // A' = trunc(x 2^(8S - 2 - e)) and reduced modulo the N leading moduli:
-// out[z * plane + r * Kp + k] (r < Rp, k < Kp, zeros in the padding; plane
-// = Rp Kp).  Columns of B go through a transposed copy.
+// plane z of out (Rp Kp bytes), element (r, k) at crt_plane_offset(r, k, Kp)
+// (r < Rp, k < Kp, zeros in the padding).  Columns of B go through a transposed copy.
 hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
                            const CrtResidueConsts* rc, hipStream_t s);

@@ -12,8 +12,9 @@ constexpr int kIntMaxWords = 4 * kCrtMaxSegments;
 
 // Residue planes of every 128-bit chunk of X's entries (R x K logical, word
 // planes `pstride` elements apart, leading dimension ld; with cols the
-// logical (r, k) entry is X[k][r]): out[(c N + z) Rp Kp + r Kp + k], zeros in
-// the padding (Rp a multiple of 32, Kp of 64).
+// logical (r, k) entry is X[k][r]): plane c N + z (Rp Kp bytes each) of out,
+// element (r, k) at crt_plane_offset(r, k, Kp), zeros in the padding (Rp a
+// multiple of 32, Kp of 64).
 struct IntResidueArgs {
   const uint32_t* X;
   int words;

@@ -47,7 +47,8 @@ __device__ __forceinline__ void chunk_words(const uint32_t* X, int64_t pstride, 
   }
 }
 
-// Residue planes of all chunks: out[(c N + z) plane + r Kp + k].  COLS:
+// Residue planes of all chunks: plane c N + z of out, element (r, k) at
+// crt_plane_offset(r, k, Kp).  COLS:
 // element (r, k) is X[w][k][r] (the columns of B); else X[w][r][k].
 // Rows: a thread takes 8 consecutive k of one row.  Columns: a block takes
 // 32 columns x 64 k, a thread 8 consecutive k of one column (reads of one k
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(256) void int_residue_kernel(IntResidueArgs a) {
         if (2.0 * res < -pd) res += pd;
         packed |= (uint64_t)(uint8_t)(int8_t)(int)res << (8 * q);
       }
-      *reinterpret_cast<uint64_t*>(a.out + ((int64_t)c * a.N + z) * plane + r * a.Kp + k0) = packed;
+      *reinterpret_cast<uint64_t*>(a.out + ((int64_t)c * a.N + z) * plane + crt_plane_offset(r, k0, a.Kp)) =
+          packed;
     }
   }
 }

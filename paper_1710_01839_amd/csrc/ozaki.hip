@@ -316,11 +316,11 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
   // images of up to 10 digits fill two words (uniform branch)
   if (S <= 2 * kCrtDigitsPerWord) {
     for (int z = 0; z < N; ++z)
-      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + r * Kp + k0) =
+      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + crt_plane_offset(r, k0, Kp)) =
           crt_residues8<2>(words, rc->c[z], kCrtModuli[z]);
   } else {
     for (int z = 0; z < N; ++z)
-      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + r * Kp + k0) =
+      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + crt_plane_offset(r, k0, Kp)) =
           crt_residues8<kCrtImageWords>(words, rc->c[z], kCrtModuli[z]);
   }
 }
@@ -1023,7 +1023,8 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
   const int64_t lp = c.l_pad;
   const int64_t m0 = (int64_t)tm * kCrtBM, n0 = (int64_t)tn * kCrtBN;
   const int wr = wave / 2, wc = wave % 2;
-  const uint32_t lane_off = (uint32_t)((lane % 16) * lp + 16 * (lane / 16));
+  // within a 1 KiB block of the tiled plane layout: row lane % 16, k chunk lane / 16
+  const uint32_t lane_off = (uint32_t)((lane % 16) * 64 + 16 * (lane / 16));
 
   // K steps per segment; the segments' products add up in one accumulation
   const int kps = (int)(lp / 64);
@@ -1036,8 +1037,9 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       const int b = wave + 8 * i;
-      const int8_t* src = b < kCrtNBA ? As + (m0 + 16 * b) * lp : Bs + (n0 + 16 * (b - kCrtNBA)) * lp;
-      oz_dma(src, lane_off + (uint32_t)kk * 64, dst + b * 1024);
+      const int64_t rb = b < kCrtNBA ? m0 / 16 + b : n0 / 16 + (b - kCrtNBA);  // row block
+      const int8_t* src = (b < kCrtNBA ? As : Bs) + (rb * kps + kk) * 1024;
+      oz_dma(src, lane_off, dst + b * 1024);
     }
   };
 
