@@ -107,3 +107,27 @@ def test_argument_checks(gpu):
     M.int_gemm(ctx, A, B, C)       # zero operands: C := 0 in every word
     torch.cuda.synchronize()
     assert not C.any()
+
+
+def test_empty_inner_dimension_and_alias(gpu):
+    """l = 0: every word of C := 0 (the empty sum).  C overlapping an input:
+    MPG_ERR_ALIAS, refused before any launch, C unchanged."""
+    M, ctx = gpu
+    A = torch.zeros((3, 5, 0), dtype=torch.int32, device="cuda")
+    B = torch.zeros((2, 0, 6), dtype=torch.int32, device="cuda")
+    wc = M.int_words_needed(3, 2, 0)
+    assert wc == bigint.words_needed(3, 2, 0)
+    C = torch.full((wc, 5, 6), -1, dtype=torch.int32, device="cuda")
+    M.int_gemm(ctx, A, B, C)
+    torch.cuda.synchronize()
+    assert not C.any()
+
+    buf = torch.arange(200, dtype=torch.int32, device="cuda")
+    A2 = buf[0:32].view(2, 4, 4)
+    C2 = buf[16:96].view(5, 4, 4)            # shares buf[16:32] with A2
+    B2 = torch.ones((2, 4, 4), dtype=torch.int32, device="cuda")
+    with pytest.raises(M.MpgemmError) as ei:
+        M.int_gemm(ctx, A2, B2, C2)
+    assert ei.value.status == M.MPG_ERR_ALIAS
+    torch.cuda.synchronize()
+    assert torch.equal(buf, torch.arange(200, dtype=torch.int32, device="cuda"))
