@@ -166,10 +166,15 @@ hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s)
 
 // Residues of 8 elements' images (words[w][q], the first NW words nonzero;
 // |sum_w word c| < 2^51, so the sum, the rounded quotient's product and the
-// remainder are exact in FP64) modulo p, each in [-p/2, p/2), packed as
-// signed bytes (element q in byte q).  The quotient rounded to nearest is
-// off by at most one, which one correction each way repairs.
-template <int NW>
+// remainder are exact in FP64) modulo p, packed as signed bytes (element q
+// in byte q).  The computed quotient acc (1/p) is within 1/(2p) of the
+// exact one (two roundings of relative 2^-53 on a value below 2^51 / p), so
+// the remainder of its nearest integer lies in [-(p+1)/2, (p+1)/2]: for the
+// odd moduli up to 253 that is inside [-127, 127] and already a signed
+// byte.  With CENTRE (p = 256, 255) one correction each way brings it into
+// [-p/2, p/2).  Any representative serves the products, which reduce modulo
+// p at the end.
+template <int NW, bool CENTRE>
 __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImageWords][8],
                                                   const double* c, int p) {
   const double pd = (double)p, inv = 1.0 / pd;
@@ -180,8 +185,10 @@ __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImag
 #pragma unroll
     for (int w = 0; w < NW; ++w) acc = __builtin_fma(words[w][q], c[w], acc);
     double r = __builtin_fma(-rint(acc * inv), pd, acc);
-    if (2.0 * r >= pd) r -= pd;
-    if (2.0 * r < -pd) r += pd;
+    if (CENTRE) {
+      if (2.0 * r >= pd) r -= pd;
+      if (2.0 * r < -pd) r += pd;
+    }
     packed |= (uint64_t)(uint8_t)(int8_t)(int)r << (8 * q);
   }
   return packed;

@@ -314,14 +314,18 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
   }
   const int64_t plane = Rp * Kp;
   // images of up to 10 digits fill two words (uniform branch)
+  // the first two moduli (256, 255) need their residues centred to fit a
+  // signed byte; the odd ones below do not
   if (S <= 2 * kCrtDigitsPerWord) {
     for (int z = 0; z < N; ++z)
       *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + crt_plane_offset(r, k0, Kp)) =
-          crt_residues8<2>(words, rc->c[z], kCrtModuli[z]);
+          z < 2 ? crt_residues8<2, true>(words, rc->c[z], kCrtModuli[z])
+                : crt_residues8<2, false>(words, rc->c[z], kCrtModuli[z]);
   } else {
     for (int z = 0; z < N; ++z)
       *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + crt_plane_offset(r, k0, Kp)) =
-          crt_residues8<kCrtImageWords>(words, rc->c[z], kCrtModuli[z]);
+          z < 2 ? crt_residues8<kCrtImageWords, true>(words, rc->c[z], kCrtModuli[z])
+                : crt_residues8<kCrtImageWords, false>(words, rc->c[z], kCrtModuli[z]);
   }
 }
 
