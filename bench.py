@@ -171,15 +171,22 @@ def tuning_time(M, ctx, n):
     return out
 
 
-def cpu_baseline(n: int, target_s: float):
-    """The oracle's step-by-step DD simple algorithm (Eq. 1) on a slab of r
-    rows of A against the full B, all host threads; rate scaled to the
-    metric's unit (DD Gflop/s, 2 r n n / t)."""
-    from oracle import cref
-    from paper_1710_01839_amd import inputs
-    A = inputs.dd_uniform(n, n, 20)
-    B = inputs.dd_uniform(n, n, 21)
-    threads = cref.max_threads()
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_rate(cref, A, B, n, threads, target_s):
+    """Oracle DD simple algorithm on a growing slab of A's rows until one run
+    takes about 0.6 target_s or more: (rows, seconds)."""
     rows = max(1, threads // 2)
     while True:
         As = tuple(a[:rows].copy() for a in A)
@@ -187,12 +194,29 @@ def cpu_baseline(n: int, target_s: float):
         cref.gemm_simple(As, B, threads=threads)
         dt = time.perf_counter() - t0
         if dt >= 0.6 * target_s or rows >= n:
-            break
+            return rows, dt
         rows = min(n, int(rows * max(2.0, target_s / max(dt, 1e-3))))
+
+
+def cpu_baseline(n: int, target_s: float):
+    """The oracle's step-by-step DD simple algorithm (Eq. 1) on a slab of r
+    rows of A against the full B, on all host threads and on one thread;
+    rates scaled to the metric's unit (DD Gflop/s, 2 r n n / t)."""
+    from oracle import cref
+    from paper_1710_01839_amd import inputs
+    A = inputs.dd_uniform(n, n, 20)
+    B = inputs.dd_uniform(n, n, 21)
+    threads = cref.max_threads()
+    rows, dt = _oracle_rate(cref, A, B, n, threads, target_s)
+    rows1, dt1 = _oracle_rate(cref, A, B, n, 1, target_s / 2)
+    model = cpu_model()
     return {"value": 2.0 * rows * n * n / dt / 1e9, "unit": "DD Gflop/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"rows 0..{rows - 1} of A ({rows}x{n}) times the full {n}x{n} B, DD simple "
-                      f"algorithm (Eq. 1) step by step, {dt:.1f} s on {threads} threads"}
+                      f"algorithm (Eq. 1) step by step, {dt:.1f} s on {threads} threads of {model}",
+            "single_thread": {"value": 2.0 * rows1 * n * n / dt1 / 1e9, "unit": "DD Gflop/s", "cores": 1,
+                              "sample": f"rows 0..{rows1 - 1} of A ({rows1}x{n}) times the full B, "
+                                        f"{dt1:.1f} s on 1 thread"}}
 
 
 def main():

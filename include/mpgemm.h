@@ -358,8 +358,8 @@ typedef enum {
   MPG_TUNE_PAPER = 1,      /* the paper's procedure: (1) predict the block time of
                               every tile from a slab product, keep the best tile;
                               (2) time simple, block and Strassen over that tile
-                              (and, for DD, the MPG_OZAKI and MPG_OZAKI_CRT
-                              candidates);
+                              and the split-product candidates (DD: MPG_OZAKI and
+                              MPG_OZAKI_CRT; QD: MPG_OZAKI_CRT);
                               (3) take the fastest */
   MPG_TUNE_MLP = 2         /* the run-time model ranks every candidate; only the
                               best `topk` are timed, the fastest measured wins */
@@ -392,6 +392,14 @@ int mpg_time_candidate(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_
  * workgroup waves of the full and the partial product. */
 int mpg_predict_block(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
                       const mpg_tile* tile, int rule, double* predicted_ms, double* slab_ms);
+/* The slab mpg_predict_block times and its scale, host only: *rows of A
+ * (against the full B) and the factor applied to the slab's time.  rule 1:
+ * rows = min(m, 2 bm), scale m / rows.  rule 0: the rows of enough tile rows
+ * for num_cu x resident workgroups, scale = waves of the full product /
+ * waves of the slab.  tile as for mpgemm_dd (NULL: the default); an
+ * unbuilt tile gives MPG_ERR_UNSUPPORTED. */
+int mpg_predict_slab(int precision, int64_t m, int64_t n, int64_t l, const mpg_tile* tile, int rule,
+                     int num_cu, int resident, int64_t* rows, double* scale);
 
 /* Tune one shape; the winner also enters the context's table used by
  * MPG_AUTO.  topk: candidates timed in MLP mode (0: one per 9 candidates,
@@ -501,6 +509,15 @@ int mpg_prof_enable(mpg_ctx* ctx, int on);
 /* Synchronise the recorded events and return total milliseconds and number
  * of launches of kernel class `kclass` since profiling was enabled. */
 int mpg_prof_read(mpg_ctx* ctx, int kclass, double* total_ms, int64_t* launches);
+
+/* ---- failure injection (tests of the error paths) ---------------------- */
+
+/* kind 1: the next `count` workspace allocations of this context fail
+ * (MPG_ERR_NOMEM, no hipMalloc is made); kind 2: the next `count` kernel
+ * launches of this context fail with hipErrorLaunchFailure (MPG_ERR_HIP,
+ * nothing is launched; the call returns at that launch).  count 0 clears.
+ * The tuner's own timing buffers are not workspace and are not affected. */
+int mpg_test_inject(mpg_ctx* ctx, int kind, int count);
 
 #ifdef __cplusplus
 }

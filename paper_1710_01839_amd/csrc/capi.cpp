@@ -59,7 +59,9 @@ int mpg_workspace(mpg_ctx* c, int slot, size_t bytes, void** out) {
       c->ws_size[slot] = 0;
     }
     void* p = nullptr;
-    if (c->alloc_hook_fail || hipMalloc(&p, bytes) != hipSuccess) {
+    const bool injected = c->fail_allocs > 0;
+    if (injected) --c->fail_allocs;
+    if (injected || hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
       return mpg_fail(c, MPG_ERR_NOMEM, "workspace allocation of %zu bytes failed", bytes);
     }
@@ -104,7 +106,13 @@ int mpg_launch(mpg_ctx* c, int kclass, const std::function<hipError_t()>& fn, co
     b = prof_event(c);
     if (a) (void)hipEventRecord(a, c->stream);
   }
-  hipError_t e = fn();
+  hipError_t e;
+  if (c->fail_launches > 0) {
+    --c->fail_launches;
+    e = hipErrorLaunchFailure;  // injected: nothing is launched
+  } else {
+    e = fn();
+  }
   if (c->prof && a && b) {
     (void)hipEventRecord(b, c->stream);
     c->prof_recs.push_back({kclass, a, b});
@@ -261,6 +269,15 @@ extern "C" int mpg_variant(int precision, int index, mpg_tile* t) {
   t->bk = v.bk;
   t->tm = v.tm;
   t->tn = v.tn;
+  return MPG_OK;
+}
+
+extern "C" int mpg_test_inject(mpg_ctx* c, int kind, int count) {
+  if (!c || count < 0 || (kind != 1 && kind != 2)) return MPG_ERR_ARG;
+  if (kind == 1)
+    c->fail_allocs = count;
+  else
+    c->fail_launches = count;
   return MPG_OK;
 }
 

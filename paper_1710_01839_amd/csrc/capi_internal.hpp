@@ -36,7 +36,10 @@ struct mpg_ctx {
   size_t batch_pin_size[2] = {0, 0};
   hipEvent_t batch_done[2] = {nullptr, nullptr};
   int batch_next = 0;
-  bool alloc_hook_fail = false;  // test seam: make the next allocations fail
+  // failure injection (mpg_test_inject): the next fail_allocs workspace
+  // allocations and fail_launches kernel launches fail without a HIP call
+  int fail_allocs = 0;
+  int fail_launches = 0;
 
   // kernel timing
   bool prof = false;

@@ -1235,7 +1235,9 @@ hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
 hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
                            const CrtResidueConsts* rc, hipStream_t s) {
-  if (S < 1 || S > kCrtMaxSlices || N < 1 || N > kCrtMaxModuli || Kp % 8) return hipErrorInvalidValue;
+  // the tiled plane layout (crt_plane_offset) needs whole 16-row x 64-k blocks
+  if (S < 1 || S > kCrtMaxSlices || N < 1 || N > kCrtMaxModuli || Kp % 64 || Rp % 16)
+    return hipErrorInvalidValue;
   const int64_t work = Rp * (Kp / 8);
   if (work <= 0) return hipSuccess;
   const dim3 grid((unsigned)((work + 255) / 256));

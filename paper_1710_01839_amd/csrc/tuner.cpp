@@ -248,34 +248,53 @@ extern "C" int mpg_time_candidate(mpg_ctx* c, int precision, int64_t m, int64_t 
   return st;
 }
 
-// Prediction of the full-size block-algorithm time from a partial product
-// (Section 3).  rule 0 (GPU): the slab holds enough tile rows to fill the
-// GPU once (all resident workgroups busy); time scales with the number of
-// waves of workgroups.  rule 1 (as printed for CPUs): the slab is two block
-// rows (2 bm rows) and time scales linearly in rows.
+// Slab of a prediction of the full-size block-algorithm time from a partial
+// product (Section 3): the rows of A whose product with the full B is timed,
+// and the factor that scales its time to the full size.  rule 1 (as printed
+// for CPUs): two block rows (2 bm rows), scaled linearly in rows.  rule 0
+// (GPU): enough tile rows to give every resident workgroup (num_cu x
+// resident) one tile, scaled by the ratio of workgroup waves of the full and
+// the partial product.
+static void slab_plan(int64_t m, int64_t n, const mpg_tile& t, int rule, int64_t num_cu, int64_t resident,
+                      int64_t* rows, double* scale) {
+  const int64_t tiles_n = (n + t.bn - 1) / t.bn, tiles_m = (m + t.bm - 1) / t.bm;
+  if (rule == 1) {
+    *rows = std::min<int64_t>(m, 2 * (int64_t)t.bm);
+    *scale = (double)m / (double)*rows;
+    return;
+  }
+  const int64_t W = std::max<int64_t>(1, num_cu * resident);
+  const int64_t tile_rows = std::min<int64_t>(tiles_m, std::max<int64_t>(1, (W + tiles_n - 1) / tiles_n));
+  *rows = std::min<int64_t>(m, tile_rows * t.bm);
+  const int64_t waves_full = (tiles_m * tiles_n + W - 1) / W;
+  const int64_t waves_slab = (((*rows + t.bm - 1) / t.bm) * tiles_n + W - 1) / W;
+  *scale = (double)waves_full / (double)std::max<int64_t>(1, waves_slab);
+}
+
 static int predict_block(mpg_ctx* c, Scratch& s, int prec, const mpg_tile& t, int rule,
                          double* pred, double* slab_ms) {
-  const int64_t m = s.m, n = s.n;
   Cand cd{};
   cd.algo = MPG_BLOCK;
   cd.tile = t;
-  const int64_t tiles_n = (n + t.bn - 1) / t.bn, tiles_m = (m + t.bm - 1) / t.bm;
-  int64_t rows;
-  double scale;
-  if (rule == 1) {
-    rows = std::min<int64_t>(m, 2 * (int64_t)t.bm);
-    scale = (double)m / (double)rows;
-  } else {
-    const int64_t W = (int64_t)c->num_cu * resident_per_cu(c, prec, t);
-    const int64_t tile_rows = std::min<int64_t>(tiles_m, std::max<int64_t>(1, (W + tiles_n - 1) / tiles_n));
-    rows = std::min<int64_t>(m, tile_rows * t.bm);
-    const int64_t waves_full = (tiles_m * tiles_n + W - 1) / W;
-    const int64_t waves_slab = (((rows + t.bm - 1) / t.bm) * tiles_n + W - 1) / W;
-    scale = (double)waves_full / (double)std::max<int64_t>(1, waves_slab);
-  }
+  int64_t rows = 0;
+  double scale = 1.0;
+  slab_plan(s.m, s.n, t, rule, c->num_cu, resident_per_cu(c, prec, t), &rows, &scale);
   int st = time_rows(c, s, rows, cd, 3, slab_ms);
   if (st != MPG_OK) return st;
   *pred = *slab_ms * scale;
+  return MPG_OK;
+}
+
+extern "C" int mpg_predict_slab(int precision, int64_t m, int64_t n, int64_t l, const mpg_tile* tile,
+                                int rule, int num_cu, int resident, int64_t* rows, double* scale) {
+  if (!rows || !scale || (precision != 2 && precision != 4) || m <= 0 || n <= 0 || l <= 0 ||
+      (rule != 0 && rule != 1) || num_cu < 1 || resident < 1)
+    return MPG_ERR_ARG;
+  int v = 0;
+  if (mpg_resolve_variant(nullptr, precision, tile, &v) != MPG_OK) return MPG_ERR_UNSUPPORTED;
+  mpg_tile t;
+  mpg_variant(precision, v, &t);
+  slab_plan(m, n, t, rule, num_cu, resident, rows, scale);
   return MPG_OK;
 }
 
@@ -318,11 +337,15 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
   Cand best{};
   double bms = INFINITY;
   // a candidate the shape does not admit (MPG_ERR_UNSUPPORTED, e.g. the
-  // split product's K limit above 24 slices) is skipped, not a failure
+  // split product's K limit above 24 slices) or whose workspace does not fit
+  // in memory (MPG_ERR_NOMEM) is skipped, not a failure
   auto trial = [&](const Cand& cd) -> int {
     double ms = 0.0;
     int r = time_rows(c, s, m, cd, 3, &ms);
-    if (r == MPG_ERR_UNSUPPORTED) return MPG_OK;
+    if (r == MPG_ERR_UNSUPPORTED || r == MPG_ERR_NOMEM) {
+      c->last_error.clear();
+      return MPG_OK;
+    }
     if (r != MPG_OK) return r;
     ++ntrials;
     db_append(c, precision, m, n, l, cd, ms, "trial");
@@ -380,7 +403,7 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
       std::vector<size_t> idx(cands.size());
       for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
       std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return y[a] < y[b]; });
-      // default: one timed candidate per 12 ranked, at least 2
+      // default: one timed candidate per 9 ranked, at least 2
       const int dflt = std::max(2, (int)((idx.size() + 8) / 9));  // 4 of 35 DD, 2 of 13 QD
       const int k = std::max(1, std::min<int>(topk > 0 ? topk : dflt, (int)idx.size()));
       for (int i = 0; i < k; ++i)

@@ -113,6 +113,8 @@ _sig("mpg_candidate", [_ci, _i64, _i64, _i64, _ci, ctypes.POINTER(_ci), ctypes.P
 _sig("mpg_tune_set_db", [_vp, ctypes.c_char_p])
 _sig("mpg_time_candidate", [_vp, _ci, _i64, _i64, _i64, _ci, ctypes.POINTER(mpg_tile), _ci, _d])
 _sig("mpg_predict_block", [_vp, _ci, _i64, _i64, _i64, ctypes.POINTER(mpg_tile), _ci, _d, _d])
+_sig("mpg_predict_slab", [_ci, _i64, _i64, _i64, ctypes.POINTER(mpg_tile), _ci, _ci, _ci,
+                          ctypes.POINTER(_i64), _d])
 _sig("mpg_tune", [_vp, _ci, _i64, _i64, _i64, _ci, _ci, ctypes.POINTER(_ci), ctypes.POINTER(mpg_tile),
                   _d, _d, ctypes.POINTER(_ci)])
 _sig("mpg_tune_table_set", [_vp, _ci, _i64, _i64, _i64, _ci, ctypes.POINTER(mpg_tile)])
@@ -128,6 +130,7 @@ _sig("mpg_mlp_save", [_vp, ctypes.c_char_p])
 _sig("mpg_mlp_load", [_vp, ctypes.c_char_p])
 _sig("mpg_prof_enable", [_vp, _ci])
 _sig("mpg_prof_read", [_vp, _ci, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
+_sig("mpg_test_inject", [_vp, _ci, _ci])
 
 
 def lib():
@@ -171,6 +174,13 @@ class Context:
         s = torch.cuda.current_stream(self.device).cuda_stream
         _lib.mpg_set_stream(self.handle, _vp(s))
 
+    def inject(self, kind: str, count: int):
+        """Failure injection for tests: the next `count` workspace
+        allocations ("alloc") or kernel launches ("launch") of this context
+        fail without touching the GPU."""
+        self.check(_lib.mpg_test_inject(self.handle, {"alloc": 1, "launch": 2}[kind], count),
+                   "mpg_test_inject")
+
     # --- kernel timing -------------------------------------------------
     def prof_enable(self, on: bool = True):
         self.check(_lib.mpg_prof_enable(self.handle, int(on)), "mpg_prof_enable")
@@ -194,8 +204,9 @@ def make_tile(tile=None) -> mpg_tile | None:
     return t
 
 
-def variants(precision: int = 2):
+def variants(precision=2):
     out = []
+    precision = _prec(precision)
     for i in range(_lib.mpg_num_variants(precision)):
         t = mpg_tile()
         _lib.mpg_variant(precision, i, ctypes.byref(t))
@@ -526,6 +537,18 @@ def candidates(precision, m, n, l):
         _lib.mpg_candidate(p, m, n, l, i, ctypes.byref(a), ctypes.byref(t))
         out.append((a.value, t.as_dict()))
     return out
+
+
+def predict_slab(precision, m, n, l, tile=None, rule=0, num_cu=256, resident=1):
+    """Rows of A the block-time prediction times and the scale applied to the
+    slab's time (host only)."""
+    rows, scale = _i64(), ctypes.c_double()
+    t = make_tile(tile)
+    st = _lib.mpg_predict_slab(_prec(precision), m, n, l, ctypes.byref(t) if t is not None else None,
+                               rule, num_cu, resident, ctypes.byref(rows), ctypes.byref(scale))
+    if st != MPG_OK:
+        raise MpgemmError(st, "mpg_predict_slab")
+    return rows.value, scale.value
 
 
 def mlp_features(precision, m, n, l, algo, tile=None, batch=1):

@@ -136,3 +136,53 @@ def test_int_words_needed_matches_oracle(lib):
             for l in (1, 2, 3, 4, 5, 1000, 1024, 1025, 1 << 20):
                 assert M.int_words_needed(wa, wb, l) == bigint.words_needed(wa, wb, l), (wa, wb, l)
     assert M.int_words_needed(0, 1, 5) == 0
+
+
+def test_printed_prediction_rule_matches_oracle(lib):
+    """The library's printed (CPU) slab rule (Section 3) is the oracle's: two
+    block rows against the full B, time scaled linearly in rows.  Where the
+    paper's Table 1 / 3 block size is a built tile's bm, the library's scale
+    applied to the printed prediction cost gives the printed prediction."""
+    import csv
+    from oracle import predict
+    from paper_1710_01839_amd import mpgemm as M
+    bms = set()
+    for prec in ("dd", "qd"):
+        for v in M.variants(prec):
+            bms.add((prec, v["bm"]))
+            for m in (1, 2, 63, 64, 65, 127, 128, 255, 256, 1000, 1024, 4096, 5001):
+                rows, scale = M.predict_slab(prec, m, 512, 300, v, rule=1)
+                assert rows == predict.slab_rows(m, v["bm"]), (prec, v, m)
+                t = 0.37
+                assert t * scale == pytest.approx(predict.predict_full_time(t, m, v["bm"]), rel=1e-15)
+    with open(os.path.join(ROOT, "tests", "golden", "prediction_tables.csv")) as f:
+        rows = list(csv.DictReader(line for line in f if not line.startswith("#")))
+    used = 0
+    for r in rows:
+        prec = r["prec"].lower()
+        if (prec, int(r["n_min"])) not in bms:
+            continue
+        tile = next(v for v in M.variants(prec) if v["bm"] == int(r["n_min"]))
+        _, scale = M.predict_slab(prec, 1024, 1024, 1024, tile, rule=1)
+        c, d = float(r["predict_cost_c"]), float(r["predicted_d"])
+        assert abs(c * scale - d) <= 0.01 * d + 0.05, r
+        used += 1
+    assert used >= 6
+
+
+def test_gpu_prediction_rule_host_plan(lib):
+    """The GPU slab rule: one full wave of workgroups, scaled by the ratio of
+    waves (hand-computed cases), and the printed rule's bad tiles."""
+    from paper_1710_01839_amd import mpgemm as M
+    t = {"bm": 64, "bn": 64, "bk": 16, "tm": 4, "tn": 4}
+    # 64 x 64 tiles of C at n = 4096: 64 per tile row; 256 CUs x 2 = 512
+    # workgroups = 8 tile rows = 512 rows; 4096 tiles = 8 waves
+    assert M.predict_slab("dd", 4096, 4096, 4096, t, 0, 256, 2) == (512, 8.0)
+    # 1000 x 4096: 16 tile rows (the last partial), 1024 tiles, 2 waves
+    assert M.predict_slab("dd", 1000, 4096, 4096, t, 0, 256, 2) == (512, 2.0)
+    # a product smaller than one wave is its own slab
+    assert M.predict_slab("dd", 100, 100, 100, t, 0, 256, 2) == (100, 1.0)
+    with pytest.raises(M.MpgemmError):
+        M.predict_slab("dd", 64, 64, 64, {"bm": 48}, 0)
+    with pytest.raises(M.MpgemmError):
+        M.predict_slab("dd", 64, 64, 64, t, 2)
