@@ -232,6 +232,24 @@ typedef struct mpg_batch_plan mpg_batch_plan;
 int mpgemm_dd_batched(mpg_ctx* ctx, int count, const mpg_dd_problem* problems,
                       const mpg_tile* tile);
 
+/* mpgemm_dd_batched for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * persistent launch and bitwise the same results, with the descriptors and
+ * the tile queue in a fixed 1 MiB device array per GPU (set up once per
+ * device by mpg_create) instead of context workspace and pinned staging.
+ * Makes no hipMalloc, hipFree, hipHostMalloc or other allocating call.
+ *   count      0..8192 problems (MPG_ERR_ARG beyond; devices 0..15).
+ *   problems   host array, read during the call only; the descriptors pass
+ *              through a fixed host staging array, so a call first waits
+ *              for the previous call's upload from it to complete.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * descriptors; the queue counter is zeroed by a kernel before each launch.
+ * Calls that overlap on one GPU (two streams, or two host threads) race on
+ * the array and the staging: order them on one stream.  Errors as for
+ * mpgemm_dd_batched. */
+int mpgemm_dd_batched_noalloc(mpg_ctx* ctx, int count, const mpg_dd_problem* problems,
+                              const mpg_tile* tile);
+
 /* Capture that persistent launch once in a HIP graph.  The plan owns the
  * graph and a device copy of the descriptors; `problems` is only read
  * during the call. */

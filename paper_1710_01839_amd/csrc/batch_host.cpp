@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -24,11 +25,11 @@ struct mpg_batch_plan {
 
 namespace {
 
-// Validate and lay out the problems: tiles of all problems end to end,
-// problems ordered by decreasing l (cost per tile) so that the strided walk
-// hands every workgroup a similar mix of long and short tiles.
-int build_desc(mpg_ctx* c, int count, const mpg_dd_problem* P, int variant,
-               std::vector<BatchProblem>& out) {
+// Validate and lay out the problems in out[0 .. count] (header, then the
+// descriptors): tiles of all problems end to end, problems ordered by
+// decreasing l (cost per tile) so that the strided walk hands every workgroup
+// a similar mix of long and short tiles.  Allocates nothing.
+int fill_desc(mpg_ctx* c, int count, const mpg_dd_problem* P, int variant, BatchProblem* out) {
   if (count < 0 || (count > 0 && !P)) return mpg_fail(c, MPG_ERR_ARG, "bad problem list");
   int bm, bn;
   batch_variant_tile(variant, &bm, &bn);
@@ -39,14 +40,11 @@ int build_desc(mpg_ctx* c, int count, const mpg_dd_problem* P, int variant,
     int st = mpg_check_gemm_args(c, 2, P[i].m, P[i].n, P[i].l, A, P[i].lda, B, P[i].ldb, C, P[i].ldc);
     if (st != MPG_OK) return mpg_fail(c, st, "problem %d: %s", i, c->last_error.c_str());
   }
-  std::vector<int> order(count);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P[a].l > P[b].l; });
-  out.assign(count + 1, BatchProblem{});
-  int64_t start = 0;
+  out[0] = BatchProblem{};
   for (int k = 0; k < count; ++k) {
-    const mpg_dd_problem& q = P[order[k]];
+    const mpg_dd_problem& q = P[k];
     BatchProblem& d = out[k + 1];
+    d = BatchProblem{};
     d.m = q.m;
     d.n = q.n;
     d.l = q.l;
@@ -59,11 +57,18 @@ int build_desc(mpg_ctx* c, int count, const mpg_dd_problem* P, int variant,
     d.B[1] = q.B_lo;
     d.C[0] = q.C_hi;
     d.C[1] = q.C_lo;
-    const int64_t tm = q.m > 0 && q.n > 0 ? (q.m + bm - 1) / bm : 0;
-    const int64_t tn = q.m > 0 && q.n > 0 ? (q.n + bn - 1) / bn : 1;
-    d.tiles_n = tn;
+    d.tile_start = k;  // the problem's index: keeps equal-l problems in call order
+  }
+  std::sort(out + 1, out + 1 + count, [](const BatchProblem& a, const BatchProblem& b) {
+    return a.l != b.l ? a.l > b.l : a.tile_start < b.tile_start;
+  });
+  int64_t start = 0;
+  for (int k = 1; k <= count; ++k) {
+    BatchProblem& d = out[k];
+    const int64_t tm = d.m > 0 && d.n > 0 ? (d.m + bm - 1) / bm : 0;
+    d.tiles_n = d.m > 0 && d.n > 0 ? (d.n + bn - 1) / bn : 1;
     d.tile_start = start;
-    start += tm * tn;
+    start += tm * d.tiles_n;
   }
   // the tile queue is an int that every workgroup advances once past the end
   if (start > (int64_t)INT_MAX / 2)
@@ -71,6 +76,12 @@ int build_desc(mpg_ctx* c, int count, const mpg_dd_problem* P, int variant,
   out[0].tile_start = start;
   out[0].tiles_n = count;
   return MPG_OK;
+}
+
+int build_desc(mpg_ctx* c, int count, const mpg_dd_problem* P, int variant,
+               std::vector<BatchProblem>& out) {
+  out.assign((size_t)std::max(count, 0) + 1, BatchProblem{});
+  return fill_desc(c, count, P, variant, out.data());
 }
 
 int batch_variant(mpg_ctx* c, const mpg_tile* tile, int* v) {
@@ -208,5 +219,101 @@ extern "C" int mpg_batch_plan_destroy(mpg_batch_plan* p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->d_desc) (void)hipFree(p->d_desc);
   delete p;
+  return MPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The batched product without allocation: descriptors and tile queue in a
+// fixed device array (one per GPU), staged through a fixed host array.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kNoAllocMaxProblems = 8192;
+constexpr size_t kNoAllocScratchBytes = (size_t)1 << 20;
+static_assert((kNoAllocMaxProblems + 1) * sizeof(BatchProblem) + sizeof(int) <= kNoAllocScratchBytes,
+              "descriptors and queue of the largest batch fit the scratch array");
+constexpr int kNoAllocMaxDevices = 16;
+
+}  // namespace
+
+// Device memory of the allocation-free entry point (each GPU holds its own
+// copy until the process ends).  In host code this name stands for the array
+// but is not its device address: the address comes from hipGetSymbolAddress,
+// once per device, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+struct NoAllocDevice {
+  std::once_flag once;
+  int status = MPG_ERR_STATE;      // MPG_OK once set up
+  hipError_t err = hipSuccess;     // the failing HIP call's error, if any
+  void* ptr = nullptr;             // device address of this GPU's scratch
+  hipEvent_t uploaded = nullptr;   // after the last upload from `staging`
+  bool pending = false;
+  alignas(256) BatchProblem staging[kNoAllocMaxProblems + 1];
+};
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+}  // namespace
+
+// Set-up of the allocation-free batched product for the current device
+// (called by mpg_create with that device current; the work runs once per
+// device): the device address of its scratch array and the event that
+// orders reuse of the host staging.
+void mpg_noalloc_setup(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return;
+  NoAllocDevice& d = g_noalloc[device];
+  std::call_once(d.once, [&d] {
+    void* p = nullptr;
+    hipError_t r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (r == hipSuccess) r = hipEventCreateWithFlags(&d.uploaded, hipEventDisableTiming);
+    if (r != hipSuccess) {
+      (void)hipGetLastError();
+      d.err = r;
+      d.status = MPG_ERR_HIP;
+      return;
+    }
+    d.ptr = p;
+    d.status = MPG_OK;
+  });
+}
+
+extern "C" int mpgemm_dd_batched_noalloc(mpg_ctx* c, int count, const mpg_dd_problem* problems,
+                                         const mpg_tile* tile) {
+  if (!c) return MPG_ERR_ARG;
+  if (count < 0 || count > kNoAllocMaxProblems)
+    return mpg_fail(c, MPG_ERR_ARG, "%d problems: the allocation-free batch holds 0..%d", count,
+                    kNoAllocMaxProblems);
+  if (c->device < 0 || c->device >= kNoAllocMaxDevices)
+    return mpg_fail(c, MPG_ERR_UNSUPPORTED, "device %d: the allocation-free batch serves devices 0..%d",
+                    c->device, kNoAllocMaxDevices - 1);
+  NoAllocDevice& d = g_noalloc[c->device];
+  if (d.status != MPG_OK)
+    return d.err != hipSuccess ? mpg_hip_fail(c, d.err, "scratch set-up")
+                               : mpg_fail(c, MPG_ERR_STATE, "scratch not set up");
+  int v, st;
+  if ((st = batch_variant(c, tile, &v)) != MPG_OK) return st;
+  if ((st = mpg_device_guard(c)) != MPG_OK) return st;
+  // the host staging is reused: the previous call's upload must have read it
+  hipError_t r = hipSuccess;
+  if (d.pending) {
+    if ((r = hipEventSynchronize(d.uploaded)) != hipSuccess) return mpg_hip_fail(c, r, "staging reuse");
+    d.pending = false;
+  }
+  if ((st = fill_desc(c, count, problems, v, d.staging)) != MPG_OK) return st;
+  const int64_t total = d.staging[0].tile_start;
+  if (count == 0 || total == 0) return MPG_OK;
+  BatchProblem* dev = static_cast<BatchProblem*>(d.ptr);
+  r = hipMemcpyAsync(dev, d.staging, (size_t)(count + 1) * sizeof(BatchProblem), hipMemcpyHostToDevice,
+                     c->stream);
+  if (r == hipSuccess) r = hipEventRecord(d.uploaded, c->stream);
+  if (r != hipSuccess) return mpg_hip_fail(c, r, "descriptor upload");
+  d.pending = true;
+  // the queue counter behind the descriptors is zeroed by a fill kernel
+  // before the persistent launch
+  r = launch_batch_persistent(v, dev, count, grid_for(c, v, total), c->stream);
+  if (r != hipSuccess) return mpg_hip_fail(c, r, "persistent batch kernel");
   return MPG_OK;
 }

@@ -207,6 +207,7 @@ extern "C" int mpg_create(mpg_ctx** ctx, int device) {
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+  mpg_noalloc_setup(device);
   *ctx = c;
   return MPG_OK;
 }

@@ -90,5 +90,8 @@ int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
 // tuning table (tuner.cpp)
 bool mpg_table_lookup(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l, int* algo,
                       mpg_tile* tile);
+// set-up of the allocation-free batched product on the current device
+// (batch_host.cpp), once per device
+void mpg_noalloc_setup(int device);
 // cached objects owned by the context (MLP state)
 void mpg_destroy_cached(mpg_ctx* c);

@@ -101,6 +101,7 @@ _sig("mpg_zgemm_dd", [_vp, _ci, _ci, _i64, _i64, _i64, _pd, _pp, _i64, _pp, _i64
 _sig("mpg_int_gemm", [_vp, _i64, _i64, _i64, _vp, _ci, _i64, _i64, _vp, _ci, _i64, _i64, _vp, _ci, _i64, _i64])
 _sig("mpg_int_words_needed", [_ci, _ci, _i64])
 _sig("mpgemm_dd_batched", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile)])
+_sig("mpgemm_dd_batched_noalloc", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile)])
 _sig("mpg_batch_plan_create", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile),
                                ctypes.POINTER(_vp)])
 _sig("mpg_batch_plan_launch", [_vp, _vp])
@@ -479,6 +480,16 @@ def mpgemm_dd_batched(ctx: Context, probs, tile=None):
     ctx.bind_stream()
     ctx.check(_lib.mpgemm_dd_batched(ctx.handle, len(probs), arr,
                                      ctypes.byref(t) if t is not None else None), "mpgemm_dd_batched")
+
+
+def mpgemm_dd_batched_noalloc(ctx: Context, probs, tile=None):
+    """mpgemm_dd_batched without allocation (a fixed device array per GPU)."""
+    arr = _problems(probs)
+    t = make_tile(tile)
+    ctx.bind_stream()
+    ctx.check(_lib.mpgemm_dd_batched_noalloc(ctx.handle, len(probs), arr,
+                                             ctypes.byref(t) if t is not None else None),
+              "mpgemm_dd_batched_noalloc")
 
 
 class BatchPlan:
