@@ -263,6 +263,7 @@ int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, 
     return mpg_fail(c, MPG_ERR_UNSUPPORTED, "l = %lld too large for exact INT32 sums with %d slices",
                     (long long)l, S);
   c->last_slices = S;
+  c->last_moduli = 0;
   void* big = nullptr;
   const int64_t planeA = mp * lp, planeB = np * lp;
   if ((st = mpg_workspace(c, 0, (size_t)S * (size_t)(planeA + planeB), &big)) != MPG_OK) return st;

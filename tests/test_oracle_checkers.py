@@ -275,3 +275,33 @@ def test_helpers_normwise_and_sampled(oracle):
         c, gg = brute_entry(A, B, i, j)
         assert e == float(abs(value(C, (i, j)) - c)) and g == float(gg)
     assert errs[0] >= abs(float(delta)) * 0.5
+
+
+def test_rows_cols_random_sampler_matches_full_check(oracle):
+    """The sampled checker used at full sizes (full rows and columns through
+    transposed slabs, random entries one by one) gives, entry for entry, the
+    ratios of the full check, and reports a planted one-ulp change of a lower
+    limb in a checked row and in a checked column."""
+    import numpy as np
+    from paper_1710_01839_amd import inputs
+    from tests.helpers import rows_cols_random_errors, rows_cols_random_ratios
+    from fractions import Fraction
+    from oracle import exact
+    A, B = inputs.dd_illcond(40, 31, 3), inputs.dd_illcond(31, 27, 4)
+    C = oracle.gemm_simple(A, B)
+    I, J, err, G = rows_cols_random_errors(C, A, B, nrand=50, seed=3)
+    pairs = list(zip(I.tolist(), J.tolist()))
+    vals, mags = exact.entries_exact(A, B, pairs)
+    for (i, j), v, mg, e, g in zip(pairs, vals, mags, err, G):
+        d = abs(exact.limbs_fraction(C, (i, j)) - v)        # the exact error
+        assert Fraction(e) >= d and Fraction(e) <= d * (1 + Fraction(1, 2 ** 50)) + abs(v) * Fraction(1, 2 ** 150)
+        assert abs(Fraction(g) - mg) <= mg * Fraction(1, 2 ** 52)
+    assert set(zip(I[:27].tolist(), J[:27].tolist())) == {(0, j) for j in range(27)}
+    I0, J0, err0, _ = rows_cols_random_errors(C, A, B, nrand=0)
+    for (i, j) in ((39, 11), (17, 26)):         # last row, last column
+        P = (C[0].copy(), C[1].copy())
+        P[1][i, j] = np.nextafter(P[1][i, j], np.inf)
+        I1, J1, err1, _ = rows_cols_random_errors(P, A, B, nrand=0)
+        at = (I0 == i) & (J0 == j)
+        assert at.any() and np.all(err1[at] != err0[at]) and np.all(err1[~at] == err0[~at])
+    assert rows_cols_random_ratios(C, A, B, -104, nrand=0)[0] <= 8.0
