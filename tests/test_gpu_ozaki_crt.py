@@ -52,8 +52,9 @@ def worst_relative(C, A, B, S):
 @pytest.mark.parametrize("kind,S", [("dd", 0), ("dd", 3), ("dd", 9), ("uniform", 0), ("wide", 0),
                                     ("wide", 5), ("illcond", 0)])
 def test_matches_oracle(gpu, kind, S):
-    """Ragged shapes spanning several 64-wide tiles; a zero row of A and a
-    zero column of B."""
+    """A ragged shape inside one 256 x 256 residue-product tile (several K
+    steps of 64); a zero row of A and a zero column of B.  Shapes spanning
+    several tiles are checked entry by entry in the full-size tests."""
     M, ctx = gpu
     m, n, l = 130, 98, 150
     if kind == "dd":
