@@ -20,6 +20,8 @@ Also measured on the same GPU and reported in the same line:
                   above; INT8 MFMA roofline of its product launch; and the
                   same for its residue (Chinese remainder) form, one INT8
                   product per modulus;
+  skinny_splitk   a 64 x 64 x 2^20 DD product by the block kernel and by
+                  split-K (FP64 issue roofline of its chunk launch);
   tuning          wall-clock tuning time at n = 4096 (DD): exhaustive, the
                   paper's prediction procedure and MLP-pruned (default top-k; the
                   model trained on exhaustive timings of smaller shapes), with
@@ -69,6 +71,7 @@ def parse():
                    help="also run a plain 1 GiB device copy (PMC traffic calibration)")
     p.add_argument("--no-ozaki", action="store_true", help="skip the split-precision comparison")
     p.add_argument("--no-tuning", action="store_true", help="skip the tuning-time measurement")
+    p.add_argument("--no-skinny", action="store_true", help="skip the skinny split-K measurement")
     return p.parse_args()
 
 
@@ -140,6 +143,41 @@ def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
                                                    "kernel": "INT8 MFMA residue products",
                                                    "launch_ms": round(crt_launch, 3)}}}
         del Ad, Bd
+    return out
+
+
+def skinny_splitk(M, ctx, m=64, n=64, l=1 << 20, reps=5):
+    """A skinny DD product (one 64 x 64 C tile, K = 2^20): the block kernel
+    (one workgroup walks all of K) against split-K (the K chunks as one
+    grouped launch of the block kernel, then the fixed-order reduction).
+    Roofline of the chunk launch: m n l multiply-adds x DD_OPS_PER_MADD."""
+    import torch
+    from paper_1710_01839_amd import inputs
+    A = M.to_device(inputs.dd_uniform(m, l, 60))
+    B = M.to_device(inputs.dd_uniform(l, n, 61))
+    C = M.empty_like_limbs(m, n, 2)
+    out = {"workload": f"double-double C=AB, {m}x{n}x{l} (hi~U[-1,1], lo in hi's half-ulp)"}
+    for algo in ("block", "splitk"):
+        M.mpgemm_dd(ctx, A, B, C, algo=algo)
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps if algo == "splitk" else 1):
+            M.mpgemm_dd(ctx, A, B, C, algo=algo)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / (reps if algo == "splitk" else 1) * 1e3
+        gms, gn = ctx.prof_read(M.MPG_KCLASS_GEMM)
+        ams, an = ctx.prof_read(M.MPG_KCLASS_AUX)
+        ctx.prof_enable(False)
+        calls = reps if algo == "splitk" else 1
+        gemm_ms = gms / calls
+        achieved = m * n * l * DD_OPS_PER_MADD / (gemm_ms * 1e-3) / 1e12
+        out[algo] = {"ms": round(wall, 3), "gemm_ms": round(gemm_ms, 3), "reduce_ms": round(ams / calls, 4),
+                     "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_ISSUE_PEAK_TOPS,
+                                  "unit": "TOP/s (FP64 VALU lane-ops)",
+                                  "frac": round(achieved / FP64_ISSUE_PEAK_TOPS, 4)}}
+    out["speedup"] = round(out["block"]["ms"] / out["splitk"]["ms"], 2)
+    del A, B, C
     return out
 
 
@@ -331,6 +369,8 @@ def main():
         plain_algo, plain_tile = cands[key]
         rec["ozaki_vs_plain"] = ozaki_vs_plain(
             M, ctx, n, lambda A_, B_, C_: M.mpgemm_dd(ctx, A_, B_, C_, algo=plain_algo, tile=plain_tile))
+    if not args.no_skinny:
+        rec["skinny_splitk"] = skinny_splitk(M, ctx)
     if not args.no_tuning:
         rec["tuning"] = tuning_time(M, ctx, n)
     if not args.no_cpu_baseline:

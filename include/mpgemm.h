@@ -59,9 +59,16 @@ typedef enum {
   MPG_STRASSEN = 3, /* Eq. (3), Winograd's form, `depth` levels over MPG_BLOCK */
   MPG_OZAKI = 4,    /* split-precision INT8 product (DD only: mpgemm_dd_ozaki with
                        tile->slices, all pairs) */
-  MPG_OZAKI_CRT = 5 /* its residue form: DD through mpgemm_dd_ozaki with tile->slices,
+  MPG_OZAKI_CRT = 5, /* its residue form: DD through mpgemm_dd_ozaki with tile->slices,
                        pairs_mode 2; QD as three residue-form products of the
                        operands' double-double parts (mpgemm_qd) */
+  MPG_SPLITK = 6    /* Eq. (2) with K cut into tile->splits consecutive chunks (0: as
+                       many as fill the GPU twice with workgroups, chunks of at least
+                       256), each chunk's product by MPG_BLOCK of the tile into
+                       workspace, the partials of every entry added in a fixed order
+                       (lanes of a wavefront sum interleaved partials in order, then a
+                       butterfly across the lanes); for skinny shapes (few C tiles,
+                       long K) */
 } mpg_algo;
 
 /* Tile / algorithm parameters.  Zero fields mean "library default" (DD:
@@ -76,6 +83,7 @@ typedef struct {
   int tm, tn;     /* per-thread register block */
   int depth;      /* Strassen recursion depth (MPG_STRASSEN), 1..3 */
   int slices;     /* Ozaki slice count (MPG_OZAKI) */
+  int splits;     /* K chunks of MPG_SPLITK (0: chosen from the shape) */
 } mpg_tile;
 
 /* ---- context ---------------------------------------------------------- */
@@ -103,12 +111,15 @@ int mpg_variant(int precision, int index, mpg_tile* tile);
 /* ---- DD GEMM ---------------------------------------------------------- */
 
 /* C := A B in double-double.  A = A_hi + A_lo (m x l), B = B_hi + B_lo
- * (l x n), C = C_hi + C_lo (m x n).  algo MPG_SIMPLE, MPG_BLOCK or
+ * (l x n), C = C_hi + C_lo (m x n).  algo MPG_SIMPLE, MPG_BLOCK,
  * MPG_STRASSEN (tile->depth levels of Winograd's recursion over the block
- * kernel, odd or non-tile dimensions zero-padded in workspace), or MPG_AUTO.
- * tile may be NULL.  Error: componentwise |C - AB|_ij <= 8 l 2^-104
- * (|A||B|)_ij for SIMPLE and BLOCK; STRASSEN obeys a normwise bound that
- * grows with depth.  SIMPLE and BLOCK give bitwise identical results. */
+ * kernel, odd or non-tile dimensions zero-padded in workspace), MPG_SPLITK
+ * or MPG_AUTO.  tile may be NULL.  Error: componentwise |C - AB|_ij <=
+ * 8 l 2^-104 (|A||B|)_ij for SIMPLE, BLOCK and SPLITK; STRASSEN obeys a
+ * normwise bound that grows with depth.  SIMPLE and BLOCK give bitwise
+ * identical results; SPLITK is deterministic (a fixed order for each
+ * shape and chunk count) and exact wherever the block kernel is (integer
+ * data). */
 int mpgemm_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
               const double* A_hi, const double* A_lo, int64_t lda,
               const double* B_hi, const double* B_lo, int64_t ldb,
@@ -119,9 +130,10 @@ int mpgemm_dd(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
 
 /* C := A B in quad-double.  A, B and C are arrays of four limb-plane
  * pointers (leading limb first), each plane row-major with the given
- * leading dimension.  algo MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN or MPG_AUTO
- * as for mpgemm_dd.  Error: componentwise |C - AB|_ij <= 8 l 2^-208
- * (|A||B|)_ij for SIMPLE and BLOCK (bitwise identical to each other).
+ * leading dimension.  algo MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN, MPG_SPLITK
+ * or MPG_AUTO as for mpgemm_dd.  Error: componentwise |C - AB|_ij <=
+ * 8 l 2^-208 (|A||B|)_ij for SIMPLE, BLOCK (bitwise identical to each
+ * other) and SPLITK.
  * MPG_OZAKI_CRT: each operand is split exactly into its double-double parts
  * (limbs 0 + 1, limbs 2 + 3); A_H B_H, A_H B_L and A_L B_H are formed
  * exactly by the residue form (one slice count, the largest exact count of

@@ -11,6 +11,7 @@
 #include "../../include/mpgemm.h"
 #include "capi_internal.hpp"
 #include "internal.hpp"
+#include "splitk_internal.hpp"
 
 using namespace mpg;
 
@@ -436,6 +437,104 @@ int mpg_strassen(mpg_ctx* c, int limbs, int depth, int variant, int64_t m, int64
 }
 
 // ---------------------------------------------------------------------------
+// split-K driver (skinny shapes), shared by DD and QD
+// ---------------------------------------------------------------------------
+
+void mpg_splitk_plan(int64_t m, int64_t n, int64_t l, int bm, int bn, int bk, int resident, int num_cu,
+                     int splits, int64_t* P, int64_t* Kc) {
+  int64_t p = splits;
+  if (p <= 0) {
+    // enough chunks for two waves of resident workgroups, chunks of >= 256
+    const int64_t tiles = ((m + bm - 1) / bm) * ((n + bn - 1) / bn);
+    const int64_t target = 2 * (int64_t)std::max(num_cu, 1) * std::max(resident, 1);
+    p = std::min((target + tiles - 1) / tiles, l / 256);
+  }
+  p = std::max<int64_t>(1, std::min(p, l));
+  // chunk length: a multiple of the K step, so every chunk but the last is
+  // whole K steps
+  int64_t kc = (l + p - 1) / p;
+  kc = (kc + bk - 1) / bk * bk;
+  *Kc = kc;
+  *P = (l + kc - 1) / kc;
+}
+
+int mpg_splitk(mpg_ctx* c, int limbs, int splits, int variant, int64_t m, int64_t n, int64_t l,
+               const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
+               double* const* C, int64_t ldc) {
+  if (splits < 0) return mpg_fail(c, MPG_ERR_ARG, "splits must be >= 0");
+  const TileVariant& tv = limbs == 2 ? dd_variant(variant) : qd_variant(variant);
+  const int resident = limbs == 2 ? dd_variant_resident(variant) : qd_variant_resident(variant);
+  int64_t P = 1, Kc = l;
+  mpg_splitk_plan(m, n, l, tv.bm, tv.bn, tv.bk, resident, c->num_cu, splits, &P, &Kc);
+  auto gemm = limbs == 2 ? launch_dd_block : launch_qd_block;
+  GemmBatch g{};
+  g.m = m;
+  g.n = n;
+  g.count = 1;
+  if (P <= 1) {  // one chunk: the block kernel straight into C
+    g.l = l;
+    for (int q = 0; q < limbs; ++q) {
+      g.A[q] = A[q];
+      g.B[q] = B[q];
+      g.C[q] = C[q];
+    }
+    g.lda = lda;
+    g.ldb = ldb;
+    g.ldc = ldc;
+    return mpg_launch(c, MPG_KCLASS_GEMM, [&] { return gemm(variant, g, c->stream); }, "block kernel");
+  }
+  const size_t plane = (size_t)(m * n) * (size_t)P;
+  void* ws = nullptr;
+  int st = mpg_workspace(c, 9, plane * limbs * sizeof(double), &ws);
+  if (st != MPG_OK) return st;
+  double* W[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int q = 0; q < limbs; ++q) W[q] = (double*)ws + (size_t)q * plane;
+  const int64_t full = l / Kc, tail = l - full * Kc;
+  // the whole chunks as one grouped launch: problem p reads columns
+  // [p Kc, (p + 1) Kc) of A and those rows of B, and writes partial p
+  g.l = Kc;
+  g.lda = lda;
+  g.sA = Kc;
+  g.ldb = ldb;
+  g.sB = Kc * ldb;
+  g.ldc = n;
+  g.sC = m * n;
+  g.count = (int)full;
+  for (int q = 0; q < limbs; ++q) {
+    g.A[q] = A[q];
+    g.B[q] = B[q];
+    g.C[q] = W[q];
+  }
+  if (full > 0 &&
+      (st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return gemm(variant, g, c->stream); }, "split-K chunks")) !=
+          MPG_OK)
+    return st;
+  if (tail > 0) {  // the shorter last chunk
+    g.l = tail;
+    g.count = 1;
+    for (int q = 0; q < limbs; ++q) {
+      g.A[q] = A[q] + full * Kc;
+      g.B[q] = B[q] + full * Kc * ldb;
+      g.C[q] = W[q] + (size_t)full * (size_t)(m * n);
+    }
+    if ((st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return gemm(variant, g, c->stream); },
+                         "split-K last chunk")) != MPG_OK)
+      return st;
+  }
+  SplitKReduceArgs r{};
+  for (int q = 0; q < limbs; ++q) {
+    r.W[q] = W[q];
+    r.C[q] = C[q];
+  }
+  r.m = m;
+  r.n = n;
+  r.ldc = ldc;
+  r.P = P;
+  return mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_splitk_reduce(limbs, r, c->stream); },
+                    "split-K reduction");
+}
+
+// ---------------------------------------------------------------------------
 // public: GEMM entry points
 // ---------------------------------------------------------------------------
 
@@ -508,6 +607,8 @@ int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
     case MPG_STRASSEN:
       return mpg_strassen(c, limbs, chosen.depth > 0 ? chosen.depth : 1, variant, m, n, l, A, lda,
                           B, ldb, C, ldc);
+    case MPG_SPLITK:
+      return mpg_splitk(c, limbs, chosen.splits, variant, m, n, l, A, lda, B, ldb, C, ldc);
     default:
       return mpg_fail(c, MPG_ERR_UNSUPPORTED, "algorithm %d not available for this call",
                       (int)algo);

@@ -25,8 +25,8 @@ struct mpg_ctx {
   // 2, 3 = batch descriptors (two calls in flight), 4, 5 = packed operands
   // of the BLAS-style calls, 6 = their product before scaling, 7 = residue
   // planes of the residue-form split product, 8 = its product residues and
-  // reconstruction table
-  static constexpr int kSlots = 9;
+  // reconstruction table, 9 = split-K partials
+  static constexpr int kSlots = 10;
   void* ws[kSlots] = {};
   size_t ws_size[kSlots] = {};
   // batch descriptor uploads: pinned host staging per descriptor slot, and
@@ -80,6 +80,14 @@ int mpg_resolve_variant(mpg_ctx* c, int precision, const mpg_tile* t, int* varia
 int mpg_strassen(mpg_ctx* c, int limbs, int depth, int variant, int64_t m, int64_t n, int64_t l,
                  const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
                  double* const* C, int64_t ldc);
+// K chunks of a split-K product (splits 0: chosen from the shape and the
+// variant's occupancy on num_cu CUs; at least 1, chunks of at least 256
+// unless splits asks for shorter ones) and the chunk length.
+void mpg_splitk_plan(int64_t m, int64_t n, int64_t l, int bm, int bn, int bk, int resident, int num_cu,
+                     int splits, int64_t* P, int64_t* Kc);
+int mpg_splitk(mpg_ctx* c, int limbs, int splits, int variant, int64_t m, int64_t n, int64_t l,
+               const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
+               double* const* C, int64_t ldc);
 // Quad-double product through the residue form (C := A B, four limbs).
 int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const* A, int64_t lda,
                const double* const* B, int64_t ldb, double* const* C, int64_t ldc);

@@ -141,14 +141,23 @@ extern "C" int mpg_mlp_features(int precision, int64_t m, int64_t n, int64_t l, 
   f[3] = precision == 2 ? 1.f : 0.f;
   f[4] = precision == 4 ? 1.f : 0.f;
   f[5] = algo == MPG_SIMPLE ? 1.f : 0.f;
-  f[6] = algo == MPG_BLOCK ? 1.f : 0.f;
+  f[6] = algo == MPG_BLOCK || algo == MPG_SPLITK ? 1.f : 0.f;
   f[7] = algo == MPG_STRASSEN ? 1.f : 0.f;
   f[8] = (float)(lg((double)t.bm) / 8.0);
   f[9] = (float)(lg((double)t.bn) / 8.0);
   f[10] = (float)(lg((double)t.bk) / 5.0);
   f[11] = (float)(t.tm * t.tn) / 64.f;
   f[12] = (float)(algo == MPG_STRASSEN ? t.depth : 0) / 3.f;
-  f[13] = (float)(lg((double)batch) / 10.0);
+  // split-K: its chunks are a batch of problems (the planned count with two
+  // resident workgroups on 256 CUs when the tile leaves it to the shape)
+  int64_t chunks = batch;
+  if (algo == MPG_SPLITK) {
+    int64_t P = 1, Kc = l;
+    mpg_splitk_plan(m, n, l, t.bm > 0 ? t.bm : 64, t.bn > 0 ? t.bn : 64, t.bk > 0 ? t.bk : 8, 2, 256,
+                    t.splits, &P, &Kc);
+    chunks = P;
+  }
+  f[13] = (float)(lg((double)chunks) / 10.0);
   f[14] = algo == MPG_OZAKI ? 1.f : algo == MPG_OZAKI_CRT ? 2.f : 0.f;  // split product, residue form
   std::memcpy(out, f, sizeof f);
   return MPG_OK;

@@ -57,6 +57,19 @@ std::vector<Cand> candidates(int prec, int64_t m, int64_t n, int64_t l) {
       out.push_back(t);
     }
   }
+  // split-K for skinny shapes: fewer C tiles than two waves of workgroups
+  // and a K of at least two 256-long chunks
+  if (l >= 512 && ((m + 63) / 64) * ((n + 63) / 64) < 512) {
+    const int vs_dd[2] = {dd_default_variant(), 1}, vs_qd[1] = {0};
+    const int* vs = prec == 2 ? vs_dd : vs_qd;
+    for (int k = 0; k < (prec == 2 ? 2 : 1); ++k) {
+      Cand t{};
+      t.algo = MPG_SPLITK;
+      mpg_variant(prec, vs[k], &t.tile);
+      t.tile.splits = 0;
+      out.push_back(t);
+    }
+  }
   if (prec == 2) {
     Cand z{};
     z.algo = MPG_OZAKI;
@@ -192,11 +205,12 @@ void db_append(mpg_ctx* c, int prec, int64_t m, int64_t n, int64_t l, const Cand
   if (!f) return;
   std::fprintf(f,
                "{\"prec\":%d,\"m\":%lld,\"n\":%lld,\"l\":%lld,\"algo\":%d,\"bm\":%d,\"bn\":%d,"
-               "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"slices\":%d,\"ms\":%.6f,"
+               "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"slices\":%d,\"splits\":%d,\"ms\":%.6f,"
                "\"kind\":\"%s\"}\n",
                prec, (long long)m, (long long)n, (long long)l, cd.algo, cd.tile.bm, cd.tile.bn,
                cd.tile.bk, cd.tile.tm, cd.tile.tn, cd.algo == MPG_STRASSEN ? cd.tile.depth : 0,
-               cd.algo == MPG_OZAKI || cd.algo == MPG_OZAKI_CRT ? cd.tile.slices : 0, ms, kind);
+               cd.algo == MPG_OZAKI || cd.algo == MPG_OZAKI_CRT ? cd.tile.slices : 0,
+               cd.algo == MPG_SPLITK ? cd.tile.splits : 0, ms, kind);
   std::fclose(f);
 }
 
@@ -426,7 +440,7 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
 
 extern "C" int mpg_tune_table_set(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l,
                                   int algo, const mpg_tile* tile) {
-  if (!c || (precision != 2 && precision != 4) || algo < MPG_SIMPLE || algo > MPG_OZAKI_CRT ||
+  if (!c || (precision != 2 && precision != 4) || algo < MPG_SIMPLE || algo > MPG_SPLITK ||
       (algo == MPG_OZAKI && precision != 2))
     return MPG_ERR_ARG;
   mpg_tile t{};
@@ -445,19 +459,19 @@ extern "C" int mpg_mlp_train_db(mpg_ctx* c, const char* path, int epochs, float 
   std::vector<float> X, y;
   char line[1024];
   while (std::fgets(line, sizeof line, f)) {
-    int prec, algo, bm, bn, bk, tm, tn, depth, slices;
+    int prec, algo, bm, bn, bk, tm, tn, depth, slices, splits;
     long long m, n, l;
     double ms;
     char kind[32];
     if (std::sscanf(line,
                     "{\"prec\":%d,\"m\":%lld,\"n\":%lld,\"l\":%lld,\"algo\":%d,\"bm\":%d,\"bn\":%d,"
-                    "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"slices\":%d,\"ms\":%lf,"
+                    "\"bk\":%d,\"tm\":%d,\"tn\":%d,\"depth\":%d,\"slices\":%d,\"splits\":%d,\"ms\":%lf,"
                     "\"kind\":\"%31[a-z]\"",
-                    &prec, &m, &n, &l, &algo, &bm, &bn, &bk, &tm, &tn, &depth, &slices, &ms,
-                    kind) != 14)
+                    &prec, &m, &n, &l, &algo, &bm, &bn, &bk, &tm, &tn, &depth, &slices, &splits, &ms,
+                    kind) != 15)
       continue;
     if (std::strcmp(kind, "trial") != 0 || !(ms > 0.0)) continue;
-    mpg_tile t{bm, bn, bk, tm, tn, depth, slices};
+    mpg_tile t{bm, bn, bk, tm, tn, depth, slices, splits};
     float feat[MPG_MLP_FEATURES];
     if (mpg_mlp_features(prec, m, n, l, algo, &t, 1, feat) != MPG_OK) continue;
     X.insert(X.end(), feat, feat + MPG_MLP_FEATURES);
@@ -572,7 +586,7 @@ extern "C" double mpg_method_bound(int in_limbs, int precision, int algo, const 
       m <= 0 || n <= 0 || l <= 0 || (algo == MPG_STRASSEN && (!tile || tile->depth < 1 || tile->depth > 3 ||
                                                               m != n || n != l)) ||
       (algo == MPG_OZAKI && (precision != 2 || !tile)) || (algo == MPG_OZAKI_CRT && precision == 2 && !tile) ||
-      algo < MPG_SIMPLE || algo > MPG_OZAKI_CRT)
+      algo < MPG_SIMPLE || algo > MPG_SPLITK)
     return INFINITY;
   mpg_tile t{};
   if (tile) t = *tile;

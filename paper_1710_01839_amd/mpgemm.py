@@ -24,10 +24,10 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 MPG_OK, MPG_ERR_ARG, MPG_ERR_UNSUPPORTED, MPG_ERR_HIP, MPG_ERR_NOMEM, MPG_ERR_ALIAS, MPG_ERR_STATE = \
     0, -1, -2, -3, -4, -5, -6
-MPG_AUTO, MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN, MPG_OZAKI, MPG_OZAKI_CRT = 0, 1, 2, 3, 4, 5
+MPG_AUTO, MPG_SIMPLE, MPG_BLOCK, MPG_STRASSEN, MPG_OZAKI, MPG_OZAKI_CRT, MPG_SPLITK = 0, 1, 2, 3, 4, 5, 6
 MPG_KCLASS_GEMM, MPG_KCLASS_AUX = 0, 1
 ALGOS = {"auto": MPG_AUTO, "simple": MPG_SIMPLE, "block": MPG_BLOCK,
-         "strassen": MPG_STRASSEN, "ozaki": MPG_OZAKI, "ozaki_crt": MPG_OZAKI_CRT}
+         "strassen": MPG_STRASSEN, "ozaki": MPG_OZAKI, "ozaki_crt": MPG_OZAKI_CRT, "splitk": MPG_SPLITK}
 # pairs_mode of the split product: all digit pairs, the triangle, the residue form
 PAIR_MODES = {"all": 0, "triangle": 1, "crt": 2}
 
@@ -35,7 +35,7 @@ PAIR_MODES = {"all": 0, "triangle": 1, "crt": 2}
 class mpg_tile(ctypes.Structure):
     _fields_ = [("bm", ctypes.c_int), ("bn", ctypes.c_int), ("bk", ctypes.c_int),
                 ("tm", ctypes.c_int), ("tn", ctypes.c_int), ("depth", ctypes.c_int),
-                ("slices", ctypes.c_int)]
+                ("slices", ctypes.c_int), ("splits", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

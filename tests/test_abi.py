@@ -61,7 +61,7 @@ def test_tuner_host_logic(lib):
     assert len(M.candidates("dd", 4096, 4096, 4096)) == 1 + nv_dd * 4 + 2
     assert len(M.candidates("qd", 2048, 2048, 2048)) == 1 + nv_qd * 3 + 1
     assert len(M.candidates("dd", 200, 200, 200)) == 1 + nv_dd * 2 + 2  # leaves >= 64: depth 1 only
-    assert len(M.candidates("dd", 100, 5000, 5000)) == 1 + nv_dd + 2
+    assert len(M.candidates("dd", 100, 5000, 5000)) == 1 + nv_dd + 2 + 2   # split-K: 158 tiles
     (a1, t1), (a2, t2) = M.candidates("dd", 512, 512, 512)[-2:]
     assert (a1, a2) == (M.MPG_OZAKI, M.MPG_OZAKI_CRT) and t1["slices"] == t2["slices"] == 0
     assert all(a != M.MPG_OZAKI for a, _ in M.candidates("qd", 512, 512, 512))
@@ -186,3 +186,22 @@ def test_gpu_prediction_rule_host_plan(lib):
         M.predict_slab("dd", 64, 64, 64, {"bm": 48}, 0)
     with pytest.raises(M.MpgemmError):
         M.predict_slab("dd", 64, 64, 64, t, 2)
+
+
+def test_splitk_plan_and_candidates(lib):
+    """Split-K candidates appear for skinny shapes only (fewer than 512
+    64 x 64 tiles, K of at least 512); the MLP sees their chunk count as the
+    batch feature."""
+    import math
+    from paper_1710_01839_amd import mpgemm as M
+    sk = [t for a, t in M.candidates("dd", 64, 64, 1 << 20) if a == M.MPG_SPLITK]
+    assert len(sk) == 2 and all(t["splits"] == 0 for t in sk)
+    assert [a for a, _ in M.candidates("qd", 32, 32, 4096)].count(M.MPG_SPLITK) == 1
+    assert M.MPG_SPLITK not in [a for a, _ in M.candidates("dd", 4096, 4096, 4096)]
+    assert M.MPG_SPLITK not in [a for a, _ in M.candidates("dd", 64, 64, 511)]
+    # 64 x 64 x 2^20 with the default tile: two waves of 2 x 256 workgroups
+    # -> 1024 chunks of 1024
+    f = M.mlp_features("dd", 64, 64, 1 << 20, "splitk", M.variants(2)[7])
+    assert f[6] == 1 and math.isclose(f[13], 1.0)
+    f = M.mlp_features("dd", 64, 64, 1 << 20, "splitk", dict(M.variants(2)[7], splits=32))
+    assert math.isclose(f[13], 0.5)
