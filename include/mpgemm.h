@@ -107,6 +107,10 @@ const char* mpg_last_error(const mpg_ctx* ctx);
 int mpg_num_variants(int precision);
 /* Fill *tile with variant `index` of the given precision. */
 int mpg_variant(int precision, int index, mpg_tile* tile);
+/* Workgroups of block variant `index` that the runtime's occupancy
+ * calculator places on one CU of the context's device (the wave size of the
+ * GPU form of the time prediction is this times the CU count). */
+int mpg_variant_resident(mpg_ctx* ctx, int precision, int index, int* blocks);
 
 /* ---- DD GEMM ---------------------------------------------------------- */
 
@@ -387,8 +391,9 @@ typedef enum {
   MPG_TUNE_EXHAUSTIVE = 0, /* time every candidate at full size */
   MPG_TUNE_PAPER = 1,      /* the paper's procedure: (1) predict the block time of
                               every tile from a slab product, keep the best tile;
-                              (2) time simple, block and Strassen over that tile
-                              and the split-product candidates (DD: MPG_OZAKI and
+                              (2) time simple, block and Strassen over that tile,
+                              the split-K candidates (skinny shapes) and the
+                              split-product candidates (DD: MPG_OZAKI and
                               MPG_OZAKI_CRT; QD: MPG_OZAKI_CRT);
                               (3) take the fastest */
   MPG_TUNE_MLP = 2         /* the run-time model ranks every candidate; only the
@@ -397,7 +402,9 @@ typedef enum {
 
 /* Candidates for a shape: MPG_SIMPLE, MPG_BLOCK with every built tile,
  * MPG_STRASSEN with every tile and depth 1..3 (DD) / 1..2 (QD) while the
- * leaves keep at least 64 per side, and last, for DD, MPG_OZAKI and
+ * leaves keep at least 64 per side, MPG_SPLITK (splits 0) with the default
+ * and the 32 x 32 x 16 DD tiles (the default QD tile) when C has fewer than
+ * 512 64 x 64 tiles and l >= 512, and last, for DD, MPG_OZAKI and
  * MPG_OZAKI_CRT with slices = 0 (exact slice count; all pairs, residue
  * form), for QD MPG_OZAKI_CRT.  precision: 2 (DD) or 4 (QD).
  * The tuner times them on its own buffers: limb 0 uniform in (-1, 1), each
@@ -415,21 +422,25 @@ int mpg_tune_set_db(mpg_ctx* ctx, const char* path);
 int mpg_time_candidate(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
                        int algo, const mpg_tile* tile, int reps, double* ms);
 
-/* Section 3's prediction of the full-size block time from a partial
- * product: time A[0:r, :] B and scale.  rule 1: r = 2 bm (two block rows)
- * scaled by m / r, as printed for CPUs; rule 0 (GPU form): r holds enough
- * tile rows to occupy every resident workgroup once, scaled by the ratio of
- * workgroup waves of the full and the partial product. */
+/* Section 3's prediction of the full-size block time from partial
+ * products: time A[0:r, :] B and extrapolate.  rule 1: r = 2 bm (two block
+ * rows) scaled by m / r, as printed for CPUs; rule 0 (GPU form): slabs of
+ * one and of two waves of workgroups (a wave gives every resident
+ * workgroup one tile), extrapolated linearly in waves to the full product;
+ * a product of at most two waves is timed whole.  *slab_ms (nullable): the
+ * time of the timed slabs (the prediction's cost). */
 int mpg_predict_block(mpg_ctx* ctx, int precision, int64_t m, int64_t n, int64_t l,
                       const mpg_tile* tile, int rule, double* predicted_ms, double* slab_ms);
-/* The slab mpg_predict_block times and its scale, host only: *rows of A
- * (against the full B) and the factor applied to the slab's time.  rule 1:
- * rows = min(m, 2 bm), scale m / rows.  rule 0: the rows of enough tile rows
- * for num_cu x resident workgroups, scale = waves of the full product /
- * waves of the slab.  tile as for mpgemm_dd (NULL: the default); an
+/* The slabs mpg_predict_block times, host only, for num_cu CUs with
+ * `resident` workgroups each.  rule 1: *rows = min(m, 2 bm), *rows2 = 0,
+ * *scale = m / rows (prediction t(rows) scale).  rule 0: *rows and *rows2
+ * the rows of one and two waves (whole tile rows), *scale the full
+ * product's tiles over the tiles of the one-wave slab, not rounded
+ * (prediction t1 + (t2 - t1)(scale - 1)); at most two waves: *rows = m,
+ * *rows2 = 0, *scale = 1.  tile as for mpgemm_dd (NULL: the default); an
  * unbuilt tile gives MPG_ERR_UNSUPPORTED. */
 int mpg_predict_slab(int precision, int64_t m, int64_t n, int64_t l, const mpg_tile* tile, int rule,
-                     int num_cu, int resident, int64_t* rows, double* scale);
+                     int num_cu, int resident, int64_t* rows, int64_t* rows2, double* scale);
 
 /* Tune one shape; the winner also enters the context's table used by
  * MPG_AUTO.  topk: candidates timed in MLP mode (0: one per 9 candidates,

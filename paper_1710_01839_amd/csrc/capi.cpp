@@ -283,6 +283,14 @@ extern "C" int mpg_test_inject(mpg_ctx* c, int kind, int count) {
   return MPG_OK;
 }
 
+extern "C" int mpg_variant_resident(mpg_ctx* c, int precision, int index, int* blocks) {
+  if (!c || !blocks || index < 0 || index >= mpg_num_variants(precision)) return MPG_ERR_ARG;
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  *blocks = precision == 2 ? dd_variant_resident(index) : qd_variant_resident(index);
+  return MPG_OK;
+}
+
 extern "C" int mpg_prof_enable(mpg_ctx* c, int on) {
   if (!c) return MPG_ERR_ARG;
   int st = prof_resolve(c);

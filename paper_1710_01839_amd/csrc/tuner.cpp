@@ -262,27 +262,39 @@ extern "C" int mpg_time_candidate(mpg_ctx* c, int precision, int64_t m, int64_t 
   return st;
 }
 
-// Slab of a prediction of the full-size block-algorithm time from a partial
-// product (Section 3): the rows of A whose product with the full B is timed,
-// and the factor that scales its time to the full size.  rule 1 (as printed
-// for CPUs): two block rows (2 bm rows), scaled linearly in rows.  rule 0
-// (GPU): enough tile rows to give every resident workgroup (num_cu x
-// resident) one tile, scaled by the ratio of workgroup waves of the full and
-// the partial product.
+// Slabs of a prediction of the full-size block-algorithm time from partial
+// products (Section 3): rows of A whose product with the full B is timed.
+// rule 1 (as printed for CPUs): one slab of two block rows (2 bm rows), its
+// time scaled linearly in rows (*scale = m / rows).  rule 0 (GPU): with
+// W = num_cu x resident workgroups in flight, a wave is enough tile rows to
+// give each of them one tile; the slabs are one wave (*rows) and two waves
+// (*rows2) and the time is extrapolated linearly in waves to the full
+// product's *scale = tiles / W waves, t1 + (t2 - t1)(waves - 1), which
+// leaves out the fixed cost of a launch (start-up, the last tiles' tail)
+// that a single scaled slab would multiply.  The count of waves is not
+// rounded up: a last, partial wave runs fewer tiles per CU, and each of
+// them faster (measured: time follows the tile count).  A product of at
+// most two waves is timed whole (*rows = m, *rows2 = 0, *scale = 1).
 static void slab_plan(int64_t m, int64_t n, const mpg_tile& t, int rule, int64_t num_cu, int64_t resident,
-                      int64_t* rows, double* scale) {
+                      int64_t* rows, int64_t* rows2, double* scale) {
   const int64_t tiles_n = (n + t.bn - 1) / t.bn, tiles_m = (m + t.bm - 1) / t.bm;
+  *rows2 = 0;
   if (rule == 1) {
     *rows = std::min<int64_t>(m, 2 * (int64_t)t.bm);
     *scale = (double)m / (double)*rows;
     return;
   }
   const int64_t W = std::max<int64_t>(1, num_cu * resident);
-  const int64_t tile_rows = std::min<int64_t>(tiles_m, std::max<int64_t>(1, (W + tiles_n - 1) / tiles_n));
-  *rows = std::min<int64_t>(m, tile_rows * t.bm);
-  const int64_t waves_full = (tiles_m * tiles_n + W - 1) / W;
-  const int64_t waves_slab = (((*rows + t.bm - 1) / t.bm) * tiles_n + W - 1) / W;
-  *scale = (double)waves_full / (double)std::max<int64_t>(1, waves_slab);
+  const int64_t wave_rows = std::max<int64_t>(1, (W + tiles_n - 1) / tiles_n);  // tile rows per wave
+  if (tiles_m * tiles_n <= 2 * W || 2 * wave_rows >= tiles_m) {
+    *rows = m;
+    *scale = 1.0;
+    return;
+  }
+  *rows = wave_rows * t.bm;
+  *rows2 = 2 * wave_rows * t.bm;
+  // waves of the full product in units of the slabs' waves
+  *scale = (double)(tiles_m * tiles_n) / (double)(wave_rows * tiles_n);
 }
 
 static int predict_block(mpg_ctx* c, Scratch& s, int prec, const mpg_tile& t, int rule,
@@ -290,25 +302,29 @@ static int predict_block(mpg_ctx* c, Scratch& s, int prec, const mpg_tile& t, in
   Cand cd{};
   cd.algo = MPG_BLOCK;
   cd.tile = t;
-  int64_t rows = 0;
+  int64_t rows = 0, rows2 = 0;
   double scale = 1.0;
-  slab_plan(s.m, s.n, t, rule, c->num_cu, resident_per_cu(c, prec, t), &rows, &scale);
-  int st = time_rows(c, s, rows, cd, 3, slab_ms);
+  slab_plan(s.m, s.n, t, rule, c->num_cu, resident_per_cu(c, prec, t), &rows, &rows2, &scale);
+  double t1 = 0.0, t2 = 0.0;
+  int st = time_rows(c, s, rows, cd, 5, &t1);
+  if (st == MPG_OK && rows2 > 0) st = time_rows(c, s, rows2, cd, 5, &t2);
   if (st != MPG_OK) return st;
-  *pred = *slab_ms * scale;
+  *slab_ms = t1 + t2;
+  *pred = rows2 > 0 ? t1 + (t2 - t1) * (scale - 1.0) : t1 * scale;
   return MPG_OK;
 }
 
 extern "C" int mpg_predict_slab(int precision, int64_t m, int64_t n, int64_t l, const mpg_tile* tile,
-                                int rule, int num_cu, int resident, int64_t* rows, double* scale) {
-  if (!rows || !scale || (precision != 2 && precision != 4) || m <= 0 || n <= 0 || l <= 0 ||
+                                int rule, int num_cu, int resident, int64_t* rows, int64_t* rows2,
+                                double* scale) {
+  if (!rows || !rows2 || !scale || (precision != 2 && precision != 4) || m <= 0 || n <= 0 || l <= 0 ||
       (rule != 0 && rule != 1) || num_cu < 1 || resident < 1)
     return MPG_ERR_ARG;
   int v = 0;
   if (mpg_resolve_variant(nullptr, precision, tile, &v) != MPG_OK) return MPG_ERR_UNSUPPORTED;
   mpg_tile t;
   mpg_variant(precision, v, &t);
-  slab_plan(m, n, t, rule, num_cu, resident, rows, scale);
+  slab_plan(m, n, t, rule, num_cu, resident, rows, rows2, scale);
   return MPG_OK;
 }
 
@@ -386,8 +402,8 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
         bt = cd.tile;
       }
     }
-    // (2) simple, block with that tile, Strassen over it and (DD) the
-    // split-precision product, at full size
+    // (2) simple, block with that tile, Strassen over it, split-K (skinny
+    // shapes) and the split-precision products, at full size
     if (st == MPG_OK) {
       std::vector<Cand> finals;
       Cand x{};
@@ -401,7 +417,7 @@ extern "C" int mpg_tune(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t
             cd.tile.bk == bt.bk && cd.tile.tm == bt.tm && cd.tile.tn == bt.tn)
           finals.push_back(cd);
       for (const auto& cd : cands)
-        if (cd.algo == MPG_OZAKI || cd.algo == MPG_OZAKI_CRT) finals.push_back(cd);
+        if (cd.algo == MPG_SPLITK || cd.algo == MPG_OZAKI || cd.algo == MPG_OZAKI_CRT) finals.push_back(cd);
       // (3) the fastest of them
       for (const auto& cd : finals)
         if ((st = trial(cd)) != MPG_OK) break;

@@ -76,6 +76,7 @@ _sig("mpg_status_string", [_ci], ctypes.c_char_p)
 _sig("mpg_last_error", [_vp], ctypes.c_char_p)
 _sig("mpg_num_variants", [_ci])
 _sig("mpg_variant", [_ci, _ci, ctypes.POINTER(mpg_tile)])
+_sig("mpg_variant_resident", [_vp, _ci, _ci, ctypes.POINTER(_ci)])
 _sig("mpgemm_dd", [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _ci,
                    ctypes.POINTER(mpg_tile)])
 _sig("mpgemm_qd", [_vp, _i64, _i64, _i64, _pp, _i64, _pp, _i64, _pp, _i64, _ci,
@@ -115,7 +116,7 @@ _sig("mpg_tune_set_db", [_vp, ctypes.c_char_p])
 _sig("mpg_time_candidate", [_vp, _ci, _i64, _i64, _i64, _ci, ctypes.POINTER(mpg_tile), _ci, _d])
 _sig("mpg_predict_block", [_vp, _ci, _i64, _i64, _i64, ctypes.POINTER(mpg_tile), _ci, _d, _d])
 _sig("mpg_predict_slab", [_ci, _i64, _i64, _i64, ctypes.POINTER(mpg_tile), _ci, _ci, _ci,
-                          ctypes.POINTER(_i64), _d])
+                          ctypes.POINTER(_i64), ctypes.POINTER(_i64), _d])
 _sig("mpg_tune", [_vp, _ci, _i64, _i64, _i64, _ci, _ci, ctypes.POINTER(_ci), ctypes.POINTER(mpg_tile),
                   _d, _d, ctypes.POINTER(_ci)])
 _sig("mpg_tune_table_set", [_vp, _ci, _i64, _i64, _i64, _ci, ctypes.POINTER(mpg_tile)])
@@ -174,6 +175,13 @@ class Context:
     def bind_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
         _lib.mpg_set_stream(self.handle, _vp(s))
+
+    def variant_resident(self, precision, index: int) -> int:
+        """Workgroups of a block variant resident per CU (occupancy calculator)."""
+        b = _ci()
+        self.check(_lib.mpg_variant_resident(self.handle, _prec(precision), index, ctypes.byref(b)),
+                   "mpg_variant_resident")
+        return b.value
 
     def inject(self, kind: str, count: int):
         """Failure injection for tests: the next `count` workspace
@@ -551,15 +559,16 @@ def candidates(precision, m, n, l):
 
 
 def predict_slab(precision, m, n, l, tile=None, rule=0, num_cu=256, resident=1):
-    """Rows of A the block-time prediction times and the scale applied to the
-    slab's time (host only)."""
-    rows, scale = _i64(), ctypes.c_double()
+    """Slabs the block-time prediction times (host only): (rows, rows2,
+    scale); rows2 = 0 for a single slab."""
+    rows, rows2, scale = _i64(), _i64(), ctypes.c_double()
     t = make_tile(tile)
     st = _lib.mpg_predict_slab(_prec(precision), m, n, l, ctypes.byref(t) if t is not None else None,
-                               rule, num_cu, resident, ctypes.byref(rows), ctypes.byref(scale))
+                               rule, num_cu, resident, ctypes.byref(rows), ctypes.byref(rows2),
+                               ctypes.byref(scale))
     if st != MPG_OK:
         raise MpgemmError(st, "mpg_predict_slab")
-    return rows.value, scale.value
+    return rows.value, rows2.value, scale.value
 
 
 def mlp_features(precision, m, n, l, algo, tile=None, batch=1):

@@ -151,8 +151,8 @@ def test_printed_prediction_rule_matches_oracle(lib):
         for v in M.variants(prec):
             bms.add((prec, v["bm"]))
             for m in (1, 2, 63, 64, 65, 127, 128, 255, 256, 1000, 1024, 4096, 5001):
-                rows, scale = M.predict_slab(prec, m, 512, 300, v, rule=1)
-                assert rows == predict.slab_rows(m, v["bm"]), (prec, v, m)
+                rows, rows2, scale = M.predict_slab(prec, m, 512, 300, v, rule=1)
+                assert rows == predict.slab_rows(m, v["bm"]) and rows2 == 0, (prec, v, m)
                 t = 0.37
                 assert t * scale == pytest.approx(predict.predict_full_time(t, m, v["bm"]), rel=1e-15)
     with open(os.path.join(ROOT, "tests", "golden", "prediction_tables.csv")) as f:
@@ -163,7 +163,7 @@ def test_printed_prediction_rule_matches_oracle(lib):
         if (prec, int(r["n_min"])) not in bms:
             continue
         tile = next(v for v in M.variants(prec) if v["bm"] == int(r["n_min"]))
-        _, scale = M.predict_slab(prec, 1024, 1024, 1024, tile, rule=1)
+        _, _, scale = M.predict_slab(prec, 1024, 1024, 1024, tile, rule=1)
         c, d = float(r["predict_cost_c"]), float(r["predicted_d"])
         assert abs(c * scale - d) <= 0.01 * d + 0.05, r
         used += 1
@@ -171,17 +171,22 @@ def test_printed_prediction_rule_matches_oracle(lib):
 
 
 def test_gpu_prediction_rule_host_plan(lib):
-    """The GPU slab rule: one full wave of workgroups, scaled by the ratio of
-    waves (hand-computed cases), and the printed rule's bad tiles."""
+    """The GPU slab rule: slabs of one and two waves of workgroups,
+    extrapolated in waves (hand-computed cases); small products whole."""
     from paper_1710_01839_amd import mpgemm as M
     t = {"bm": 64, "bn": 64, "bk": 16, "tm": 4, "tn": 4}
     # 64 x 64 tiles of C at n = 4096: 64 per tile row; 256 CUs x 2 = 512
-    # workgroups = 8 tile rows = 512 rows; 4096 tiles = 8 waves
-    assert M.predict_slab("dd", 4096, 4096, 4096, t, 0, 256, 2) == (512, 8.0)
-    # 1000 x 4096: 16 tile rows (the last partial), 1024 tiles, 2 waves
-    assert M.predict_slab("dd", 1000, 4096, 4096, t, 0, 256, 2) == (512, 2.0)
-    # a product smaller than one wave is its own slab
-    assert M.predict_slab("dd", 100, 100, 100, t, 0, 256, 2) == (100, 1.0)
+    # workgroups = 8 tile rows = 512 rows per wave; 4096 tiles = 8 waves
+    assert M.predict_slab("dd", 4096, 4096, 4096, t, 0, 256, 2) == (512, 1024, 8.0)
+    # 3000 x 4096: 47 tile rows, 3008 tiles, 5.875 waves (the last partial)
+    assert M.predict_slab("dd", 3000, 4096, 4096, t, 0, 256, 2) == (512, 1024, 5.875)
+    # 2048 x 2048 QD on 32 x 32 tiles, 3 per CU: a wave is 768 tiles = 12 tile
+    # rows (384 rows); 4096 tiles = 5.33 waves
+    r, r2, w = M.predict_slab("qd", 2048, 2048, 2048, {"bm": 32, "bn": 32, "bk": 8, "tm": 2, "tn": 2}, 0, 256, 3)
+    assert (r, r2) == (384, 768) and abs(w - 4096 / 768) < 1e-12
+    # two waves or fewer: the product itself
+    assert M.predict_slab("dd", 1000, 4096, 4096, t, 0, 256, 2) == (1000, 0, 1.0)
+    assert M.predict_slab("dd", 100, 100, 100, t, 0, 256, 2) == (100, 0, 1.0)
     with pytest.raises(M.MpgemmError):
         M.predict_slab("dd", 64, 64, 64, {"bm": 48}, 0)
     with pytest.raises(M.MpgemmError):

@@ -102,50 +102,78 @@ def test_mlp_learns_and_saves(gpu, tmp_path):
     assert np.array_equal(mlp.predict(X[:20]), before)
 
 
-@pytest.mark.parametrize("variant", [0, 2])
-def test_slab_prediction_gpu_rule(gpu, variant):
-    """Section 3's prediction in GPU form (slab = one full wave of tiles,
-    scaled by wave counts) predicts the full-size block time."""
+@pytest.mark.parametrize("prec,n,variant", [("dd", 4096, 0), ("dd", 4096, 1), ("dd", 4096, 2), ("dd", 4096, 3),
+                                             ("dd", 4096, 7), ("qd", 1024, 0), ("qd", 2048, 0)])
+def test_slab_prediction_gpu_rule(gpu, prec, n, variant):
+    """Section 3's prediction in GPU form (slabs of one and two waves of
+    workgroups, extrapolated in waves) is within 10% of the measured
+    full-size block time (Section 4.1 reports under 10%); where the product
+    has more than two waves the slabs cost less than the product."""
     M, ctx = gpu
     T = M.Tuner(ctx)
-    v = M.variants(2)[variant]
-    n = 2048
-    real = T.time("dd", n, n, n, "block", v, reps=5)
-    pred, slab = T.predict_block("dd", n, n, n, v, rule=0)
-    print("variant", v, "real", real, "predicted", pred, "slab", slab)
-    assert slab < real
-    assert abs(pred - real) <= 0.25 * real
+    v = M.variants(prec)[variant]
+    real = T.time(prec, n, n, n, "block", v, reps=5)
+    pred, slab = T.predict_block(prec, n, n, n, v, rule=0)
+    print(prec, n, "variant", v, "real", real, "predicted", pred, "slabs", slab,
+          "error %.1f%%" % (100 * abs(pred - real) / real))
+    assert abs(pred - real) <= 0.10 * real
+    if n >= 2048:     # eight or more waves: the two slabs are three of them
+        assert slab < 0.6 * real
+
+
+def _regret(T, prec, shape, pick, best_ms):
+    got = T.time(prec, *shape, pick["algo"], pick["tile"], reps=7)
+    return got / best_ms - 1.0
 
 
 def test_tuner_modes(gpu, tmp_path):
-    """Exhaustive, paper and MLP-pruned tuning on held-out shapes: the MLP
-    (trained on exhaustive timings of other shapes) times a few candidates
-    and stays close to the exhaustive best."""
+    """Exhaustive, paper and MLP-pruned tuning on held-out shapes.  The MLP
+    (trained on exhaustive timings of other shapes) times a few candidates:
+    its pick is within 5% of the exhaustive best at no more than 20% of the
+    exhaustive tuning time, and against the paper's procedure (the method
+    without the model) it tunes faster at no worse regret."""
     M, ctx = gpu
     T = M.Tuner(ctx)
     db = str(tmp_path / "db.jsonl")
     T.set_db(db)
     for n in (256, 384, 512, 768, 1024, 1536):
         T.tune("dd", n, n, n, "exhaustive")
+    for shape in ((64, 64, 16384), (128, 64, 32768)):
+        T.tune("dd", *shape, "exhaustive")
     for n in (256, 512, 1024):
         T.tune("qd", n, n, n, "exhaustive")
     T.set_db(None)
     mlp = M.MLP(ctx)
     loss, rows = mlp.train_db(db, 3000, 3e-3)
     assert rows > 100 and loss < 0.05
-    for prec, n in (("dd", 640), ("dd", 1280), ("qd", 768)):
-        ex = T.tune(prec, n, n, n, "exhaustive")
-        pa = T.tune(prec, n, n, n, "paper")
-        ml = T.tune(prec, n, n, n, "mlp", 3)
-        assert ml["trials"] == 3 and ex["trials"] == len(M.candidates(prec, n, n, n))
-        # simple, block, up to three Strassen depths, and the split product
-        # (digit and residue forms) for DD
-        assert pa["trials"] <= 1 + 1 + 3 + 2 * (prec == "dd")
-        best = T.time(prec, n, n, n, ex["algo"], ex["tile"], reps=5)
-        got = T.time(prec, n, n, n, ml["algo"], ml["tile"], reps=5)
-        print(prec, n, "exhaustive", ex, "paper", pa, "mlp", ml)
-        assert got <= 1.15 * best
-        assert ml["seconds"] <= 0.5 * ex["seconds"]
+    regrets = {"paper": [], "mlp": []}
+    seconds = {"exhaustive": 0.0, "paper": 0.0, "mlp": 0.0}
+    for prec, shape in (("dd", (640, 640, 640)), ("dd", (1280, 1280, 1280)), ("qd", (768, 768, 768)),
+                        ("dd", (64, 128, 65536))):
+        ex = T.tune(prec, *shape, "exhaustive")
+        pa = T.tune(prec, *shape, "paper")
+        ml = T.tune(prec, *shape, "mlp")          # default: one timed candidate per 9 ranked
+        ncand = len(M.candidates(prec, *shape))
+        assert ex["trials"] == ncand and ml["trials"] == max(2, (ncand + 8) // 9)
+        # the paper's finals: simple, block, up to three Strassen depths,
+        # split-K (two DD tiles, one QD) and the split products
+        assert pa["trials"] <= 1 + 1 + 3 + 2 + 2
+        best = T.time(prec, *shape, ex["algo"], ex["tile"], reps=7)
+        r_pa, r_ml = _regret(T, prec, shape, pa, best), _regret(T, prec, shape, ml, best)
+        print(prec, shape, "exhaustive", ex, "paper", pa, "regret %.3f" % r_pa, "mlp", ml, "regret %.3f" % r_ml)
+        assert r_ml <= 0.05
+        assert ml["seconds"] <= 0.2 * ex["seconds"]
+        regrets["paper"].append(r_pa)
+        regrets["mlp"].append(r_ml)
+        for k, r in (("exhaustive", ex), ("paper", pa), ("mlp", ml)):
+            seconds[k] += r["seconds"]
+    # what the model gains over the method without it: less tuning time, and
+    # a pick as good (mean regret, negative timings noise counted as 0,
+    # within 1% of the paper procedure's)
+    mean = {k: float(np.mean(np.maximum(v, 0.0))) for k, v in regrets.items()}
+    print("tuning seconds", seconds, "mean regrets", mean)
+    assert seconds["mlp"] < 0.5 * seconds["paper"]
+    assert mean["mlp"] <= mean["paper"] + 0.01
 
 
 def test_auto_uses_tuning_table(gpu):
@@ -158,7 +186,7 @@ def test_auto_uses_tuning_table(gpu):
     A, B = M.to_device(inputs.dd_uniform(n, n, 1)), M.to_device(inputs.dd_uniform(n, n, 2))
     C1, C2 = M.empty_like_limbs(n, n, 2), M.empty_like_limbs(n, n, 2)
     M.mpgemm_dd(ctx, A, B, C1, algo="auto")
-    algo = {1: "simple", 2: "block", 3: "strassen", 4: "ozaki", 5: "ozaki_crt"}[r["algo"]]
+    algo = {1: "simple", 2: "block", 3: "strassen", 4: "ozaki", 5: "ozaki_crt", 6: "splitk"}[r["algo"]]
     M.mpgemm_dd(ctx, A, B, C2, algo=algo, tile=r["tile"])
     torch.cuda.synchronize()
     assert torch.equal(C1[0], C2[0]) and torch.equal(C1[1], C2[1])
