@@ -970,16 +970,22 @@ __global__ __launch_bounds__(256, 1) void ozaki_band_kernel(OzakiGemmArgs a, int
 // Residue form: one INT8 product per modulus.  Workgroup w (after the XCD
 // remap) takes modulus z = w / tiles and tile w % tiles, so the workgroups
 // of one XCD share one modulus' planes.  Every 2047 K steps the INT32 sums
-// are reduced into [0, p_z) (exact integer arithmetic; the quotient comes
-// from a double division that is exact except when the sum is a multiple
-// of p_z, which the range check repairs), and the final residues are
-// stored as bytes.
+// are reduced into [0, p_z) (exact integer arithmetic), and the final
+// residues are stored as bytes.
 // ---------------------------------------------------------------------
-__device__ __forceinline__ int crt_mod(int v, int p, double inv_p) {
-  int r = v - (int)floor((double)v * inv_p) * p;
-  if (r >= p) r -= p;
-  if (r < 0) r += p;
-  return r;
+// v mod p in [0, p) for |v| < 2^31 and 29 <= p <= 256 (every modulus), in
+// 32-bit arithmetic: v = hi 2^16 + lo folds to t = hi (2^16 mod p) + lo
+// with |t| < 2^24, exact in FP32; the FP32 quotient t (1/p) is within 0.07
+// of t / p (two roundings of relative 2^-24 on a quotient below 2^24 / 29),
+// so its floor is off by at most one and t - q p lies in [-p, 2p); as
+// unsigned numbers the one of r, r + p, r - p inside [0, p) is the smallest.
+// (An FP64 quotient with two corrections cost 15% of the product kernel's
+// time in the epilogue's 128 reductions per lane.)
+__device__ __forceinline__ int crt_mod(int v, int p, int c16, float inv_pf) {
+  const int t = (v >> 16) * c16 + (v & 0xffff);
+  const int q = (int)floorf((float)t * inv_pf);
+  const int r = t - q * p;
+  return (int)min(min((unsigned)r, (unsigned)(r + p)), (unsigned)(r - p));
 }
 
 // Residue products on 256 x 256 workgroup tiles: with one digit pair per
@@ -1021,7 +1027,8 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
     tn = in / gsize;
   }
   const int p = c.mods[z];
-  const double inv_p = 1.0 / (double)p;
+  const int c16 = 65536 % p;
+  const float inv_pf = 1.0f / (float)p;
   const int8_t* A = c.A + (int64_t)z * c.planeA;
   const int8_t* B = c.B + (int64_t)z * c.planeB;
   const int64_t lp = c.l_pad;
@@ -1090,7 +1097,7 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
 #pragma unroll
         for (int bj = 0; bj < kCrtWN; ++bj)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc[bi][bj][i] = crt_mod(acc[bi][bj][i], p, inv_p);
+          for (int i = 0; i < 4; ++i) acc[bi][bj][i] = crt_mod(acc[bi][bj][i], p, c16, inv_pf);
     }
   }
   uint8_t* R = c.R + (int64_t)z * c.planeR;
@@ -1103,7 +1110,7 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t r = r0 + 16 * bi + 4 * (lane / 16) + i;
-        if (r < c.m && col < c.n) R[r * c.ldr + col] = (uint8_t)crt_mod(acc[bi][bj][i], p, inv_p);
+        if (r < c.m && col < c.n) R[r * c.ldr + col] = (uint8_t)crt_mod(acc[bi][bj][i], p, c16, inv_pf);
       }
     }
 }

@@ -27,3 +27,27 @@ def test_uncentred_remainder_fits_a_signed_byte():
         assert np.all(np.abs(r) <= (p + 1) // 2), p
         assert np.all(np.abs(r) <= 127), p
         assert np.array_equal(np.mod(r, p), np.mod(acc, p))
+
+
+def test_product_residue_reduction_in_32_bits():
+    """The residue products reduce their INT32 sums (|v| < 2^31) modulo each
+    modulus in 32-bit arithmetic: t = (v >> 16)(2^16 mod p) + (v & 0xffff)
+    is below 2^24 (exact in FP32), the FP32 quotient t (1/p) floors to within
+    one of t / p, and the smallest of r, r + p, r - p as unsigned numbers is
+    v mod p.  Checked on the host with FP32 rounding for every modulus, the
+    extremes of the INT32 range and random values."""
+    import numpy as np
+    mods = crt.moduli()
+    assert min(mods) == 29 and max(mods) == 256
+    g = np.random.default_rng(11)
+    for p in mods:
+        v = np.concatenate([g.integers(-2 ** 31, 2 ** 31, size=200_000, dtype=np.int64),
+                            np.arange(-2 ** 31, -2 ** 31 + 5000), np.arange(2 ** 31 - 5000, 2 ** 31),
+                            np.arange(-5000, 5000)]).astype(np.int32)
+        t = (v >> 16).astype(np.int64) * (65536 % p) + (v & 0xffff).astype(np.int64)
+        assert np.all(np.abs(t) < 2 ** 24)
+        q = np.floor(t.astype(np.float32) * (np.float32(1.0) / np.float32(p))).astype(np.int64)
+        r = t - q * p
+        assert np.all((r >= -p) & (r < 2 * p)), p
+        got = (np.stack([r, r + p, r - p]) & 0xffffffff).min(axis=0)
+        assert np.array_equal(got, np.mod(v.astype(np.int64), p)), p
