@@ -226,6 +226,68 @@ int mpg_int_gemm(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
  * bit length of l) / 32) (0 for bad arguments).  Host only. */
 int mpg_int_words_needed(int words_a, int words_b, int64_t l);
 
+/* How the long-integer product is formed (all choices give the same exact
+ * result):
+ *   chunk_words      3, 4 or 5: entries are cut into chunks of 96, 128 or
+ *                    160 bits; wider chunks mean fewer chunk pairs but more
+ *                    moduli per product (the diagonal sums have
+ *                    64 chunk_words + log2 l + log2 chunks + 1 bits, at most
+ *                    the 342 bits of the 49 moduli);
+ *   karatsuba_depth  0..3 levels of Karatsuba's splitting of the chunk
+ *                    polynomials (x = 2^(32 chunk_words)): each level forms
+ *                    the residues of the chunk sums of the two halves and
+ *                    needs three half-length products instead of four; the
+ *                    leaf products' diagonals are kept and each diagonal of
+ *                    the product is rebuilt from its signed combination
+ *                    (residues combined modulo each modulus first).
+ * A plan that does not fit (chunks too wide for l, more than 16 chunk pairs
+ * per diagonal, sums of more than eight chunks) gives MPG_ERR_UNSUPPORTED. */
+typedef struct {
+  int chunk_words;
+  int karatsuba_depth;
+} mpg_int_algo;
+
+/* mpg_int_gemm with an explicit plan (algo) or, with algo NULL, the
+ * context's tuning table for this shape and these word counts (filled by
+ * mpg_int_tune), else 128-bit chunks without splitting.  mpg_int_gemm is
+ * this call with algo NULL. */
+int mpg_int_gemm_ex(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l,
+                    const uint32_t* A, int words_a, int64_t lda, int64_t plane_a,
+                    const uint32_t* B, int words_b, int64_t ldb, int64_t plane_b,
+                    uint32_t* C, int words_c, int64_t ldc, int64_t plane_c,
+                    const mpg_int_algo* algo);
+
+/* Candidate plans of a product (every chunk width and Karatsuba depth 0..2
+ * that fits), host only; and the INT8 products a plan runs (chunk pairs of
+ * all leaf diagonals times moduli, each of m x n x l), 0 if it does not fit. */
+int mpg_int_num_candidates(int words_a, int words_b, int64_t l);
+int mpg_int_candidate(int words_a, int words_b, int64_t l, int index, mpg_int_algo* algo);
+int64_t mpg_int_products(int words_a, int words_b, int64_t l, const mpg_int_algo* algo);
+
+/* Median of `reps` timings (after a warm-up) of the plan on library buffers
+ * of the shape (uniform random words); milliseconds. */
+int mpg_int_time(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l, int words_a, int words_b,
+                 const mpg_int_algo* algo, int reps, double* ms);
+
+/* Section 3's prediction for the long-integer product, GPU form: the plan's
+ * time on slabs of A's rows against the full B, one and two waves of the
+ * residue products (a wave: enough 256-row tile rows that the tile rows x
+ * column tiles x moduli workgroups of a product occupy every CU once),
+ * extrapolated linearly in tile rows to m; a product of at most two waves is
+ * timed whole.  Timed on library buffers (uniform random words; the time
+ * does not depend on the values).  *slab_ms (nullable): the slabs' time. */
+int mpg_int_predict(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l, int words_a, int words_b,
+                    const mpg_int_algo* algo, double* predicted_ms, double* slab_ms);
+
+/* Tunes the plan of one product (mode as mpg_tune: exhaustive; the paper's
+ * procedure: predict every candidate from slabs, then time the best
+ * predicted one and the default plan at full size and keep the faster; or
+ * the run-time model ranks the candidates and the best topk (0: one per 4,
+ * at least 2) are timed).  The winner enters the table used by
+ * mpg_int_gemm.  Outputs nullable, as for mpg_tune. */
+int mpg_int_tune(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l, int words_a, int words_b, int mode,
+                 int topk, mpg_int_algo* best, double* best_ms, double* seconds, int* trials);
+
 /* ---- batches of uneven DD products ------------------------------------ */
 
 /* One problem C := A B of a batch (same conventions as mpgemm_dd). */
@@ -503,10 +565,14 @@ int mpg_select_method(mpg_ctx* ctx, int64_t m, int64_t n, int64_t l, int in_limb
 /* ---- run-time model (MLP) -------------------------------------------- */
 
 /* Features of one candidate (MPG_MLP_FEATURES floats): log2 m, n, l / 12;
- * DD and QD indicators; simple / block / Strassen indicators; log2 bm / 8,
- * log2 bn / 8, log2 bk / 5, tm tn / 64, Strassen depth / 3, log2 batch / 10;
- * split product: 1 digit form, 2 residue form, else 0.  Target of the
- * model: natural log of milliseconds. */
+ * DD and QD indicators; simple / block / Strassen indicators (split-K:
+ * block); log2 bm / 8, log2 bn / 8, log2 bk / 5, tm tn / 64, Strassen
+ * depth / 3, log2 batch / 10 (split-K: its chunk count); split product:
+ * 1 digit form, 2 residue form, else 0.  The long-integer product
+ * (precision 0; tile: bm, bn = operand words, bk = chunk words, depth =
+ * Karatsuba depth): log2 of the operand bits / 12 in the bm and bn slots,
+ * chunk words / 8 in the bk slot, the depth / 3, and 3 in the last.  Target
+ * of the model: natural log of milliseconds. */
 #define MPG_MLP_FEATURES 15
 int mpg_mlp_features(int precision, int64_t m, int64_t n, int64_t l, int algo,
                      const mpg_tile* tile, int batch, float* out);

@@ -54,6 +54,8 @@ struct mpg_ctx {
 
   // tuning table: (precision, m, n, l) -> (algo, tile)
   std::map<std::tuple<int, int64_t, int64_t, int64_t>, std::pair<int, mpg_tile>> table;
+  // long-integer product plans: (m, n, l, words_a, words_b) -> plan
+  std::map<std::tuple<int64_t, int64_t, int64_t, int, int>, mpg_int_algo> int_table;
 
   // JSONL timing database of the tuner (empty: none)
   std::string db_path;
@@ -101,5 +103,13 @@ bool mpg_table_lookup(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l
 // set-up of the allocation-free batched product on the current device
 // (batch_host.cpp), once per device
 void mpg_noalloc_setup(int device);
+// long-integer product plans (intgemm_host.cpp / tuner.cpp)
+bool mpg_int_table_lookup(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int words_a, int words_b,
+                          mpg_int_algo* algo);
+int mpg_int_run(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const uint32_t* A, int words_a, int64_t lda,
+                int64_t plane_a, const uint32_t* B, int words_b, int64_t ldb, int64_t plane_b, uint32_t* C,
+                int words_c, int64_t ldc, int64_t plane_c, int cw, int depth);
+int64_t mpg_int_plan_products(int words_a, int words_b, int64_t l, int cw, int depth);
+int mpg_int_plan_moduli(int words_a, int words_b, int64_t l, int cw, int depth);
 // cached objects owned by the context (MLP state)
 void mpg_destroy_cached(mpg_ctx* c);

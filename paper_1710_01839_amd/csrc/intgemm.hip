@@ -2,13 +2,16 @@
 // fixed-point analog of the paper's arbitrary-precision runs.
 //
 // Entries are two's complement integers of `words` 32-bit words, stored as
-// word planes (plane w: word w of every entry).  An entry is cut into 128-bit
-// chunks, x = sum_c U_c 2^(128 c) with U_c in [0, 2^128) below the top chunk
-// and the top chunk signed.  For each chunk the residues modulo the N leading
-// moduli are formed directly from its four words; the products of chunk
-// pairs on one diagonal g = c + d run as one INT8 product over a K made of
-// the pairs (segments), and each diagonal's exact integer Y_g is rebuilt and
-// added at 2^(128 g) into the multiword result.
+// word planes (plane w: word w of every entry).  An entry is cut into chunks
+// of CW words (96, 128 or 160 bits), x = sum_c U_c 2^(32 CW c) with U_c in
+// [0, 2^(32 CW)) below the top chunk and the top chunk signed.  For each
+// chunk the residues modulo the N leading moduli are formed directly from its
+// words; chunk polynomials may first be combined by Karatsuba's splitting
+// (residue planes of chunk sums); the products of the leaf polynomials run
+// diagonal by diagonal as INT8 products over a K made of the chunk pairs
+// (segments), and each diagonal of the full product, a signed combination of
+// leaf diagonals, is rebuilt exactly and added at 2^(32 CW g) into the
+// multiword result.
 #include "crt_internal.hpp"
 #include "int_internal.hpp"
 
@@ -17,33 +20,34 @@ namespace {
 
 // 2^(32 j) mod p_z for the N moduli, built by the first threads of a block.
 struct WordWeights {
-  double c[kCrtMaxModuli][4];
+  double c[kCrtMaxModuli][kIntMaxChunkWords];
 };
 
 __device__ void word_weights(WordWeights& w, int N) {
   for (int z = threadIdx.x; z < N; z += blockDim.x) {
     const uint64_t p = (uint64_t)kCrtModuli[z];
     uint64_t v = 1;
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kIntMaxChunkWords; ++j) {
       w.c[z][j] = (double)v;
       v = (v << 32) % p;
     }
   }
 }
 
-// Chunk c of an entry (four words from word 4c; words past the entry's own
+// Chunk c of an entry (CW words from word CW c; words past the entry's own
 // are its sign extension; the top chunk's last word is signed).
+template <int CW>
 __device__ __forceinline__ void chunk_words(const uint32_t* X, int64_t pstride, int64_t off, int words,
-                                            int c, int chunks, bool ok, double (&v)[4]) {
+                                            int c, int chunks, bool ok, double (&v)[CW]) {
   const int64_t top_word = (int64_t)words - 1;
   uint32_t sign = 0;
   if (ok) sign = (int32_t)X[top_word * pstride + off] < 0 ? 0xFFFFFFFFu : 0u;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int w = 4 * c + j;
+  for (int j = 0; j < CW; ++j) {
+    const int w = CW * c + j;
     uint32_t u = 0;
     if (ok) u = w < words ? X[(int64_t)w * pstride + off] : sign;
-    v[j] = (c == chunks - 1 && j == 3) ? (double)(int32_t)u : (double)u;
+    v[j] = (c == chunks - 1 && j == CW - 1) ? (double)(int32_t)u : (double)u;
   }
 }
 
@@ -53,7 +57,7 @@ __device__ __forceinline__ void chunk_words(const uint32_t* X, int64_t pstride, 
 // Rows: a thread takes 8 consecutive k of one row.  Columns: a block takes
 // 32 columns x 64 k, a thread 8 consecutive k of one column (reads of one k
 // across the 32 columns are contiguous).
-template <bool COLS>
+template <bool COLS, int CW>
 __global__ __launch_bounds__(256) void int_residue_kernel(IntResidueArgs a) {
   __shared__ WordWeights ww;
   word_weights(ww, a.N);
@@ -72,26 +76,26 @@ __global__ __launch_bounds__(256) void int_residue_kernel(IntResidueArgs a) {
   }
   const int64_t plane = a.Rp * a.Kp;
   for (int c = 0; c < a.chunks; ++c) {
-    // the chunk's four words of 8 elements
-    double v[4][8];
+    // the chunk's CW words of 8 elements
+    double v[CW][8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int64_t k = k0 + q;
       const bool ok = r < a.R && k < a.K;
       const int64_t off = ok ? (COLS ? k * a.ld + r : r * a.ld + k) : 0;
-      double t[4];
-      chunk_words(a.X, a.pstride, off, a.words, c, a.chunks, ok, t);
+      double t[CW];
+      chunk_words<CW>(a.X, a.pstride, off, a.words, c, a.chunks, ok, t);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) v[j][q] = t[j];
+      for (int j = 0; j < CW; ++j) v[j][q] = t[j];
     }
     for (int z = 0; z < a.N; ++z) {
       const double pd = (double)kCrtModuli[z], inv = 1.0 / pd;
       uint64_t packed = 0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        double acc = 0.0;  // |acc| < 4 2^32 256: exact
+        double acc = 0.0;  // |acc| < CW 2^32 256 <= 2^43: exact
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc = __builtin_fma(v[j][q], ww.c[z][j], acc);
+        for (int j = 0; j < CW; ++j) acc = __builtin_fma(v[j][q], ww.c[z][j], acc);
         double res = __builtin_fma(-rint(acc * inv), pd, acc);
         if (2.0 * res >= pd) res -= pd;
         if (2.0 * res < -pd) res += pd;
@@ -105,6 +109,10 @@ __global__ __launch_bounds__(256) void int_residue_kernel(IntResidueArgs a) {
 
 // Rebuilds each entry's diagonal sum Y (W words) and adds it, signed, into
 // C's words from `word_off` up (carries and borrows run to the top word).
+// The residues of Y modulo p_z are the signed sum of the terms' residues
+// (each in [0, p_z)), brought back into [0, p_z): the sum is below
+// 64 x 256 in magnitude, so its FP32 quotient by p_z is within 2^-8 of the
+// exact one and one correction each way suffices.
 template <int W>
 __global__ __launch_bounds__(256) void int_accumulate_kernel(IntAccumArgs a) {
   const int64_t j0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
@@ -118,7 +126,28 @@ __global__ __launch_bounds__(256) void int_accumulate_kernel(IntAccumArgs a) {
       for (int w = 0; w < W; ++w) acc[b][w] = 0;
     const uint8_t* row = a.R + i * a.ldr + j0;
     for (int z = 0; z < a.N; ++z) {
-      const uint32_t r4 = *reinterpret_cast<const uint32_t*>(row + (int64_t)z * a.planeR);
+      uint32_t r4;
+      if (a.nterms == 1 && a.term_sign[0] == 1) {
+        r4 = *reinterpret_cast<const uint32_t*>(row + a.term_off[0] + (int64_t)z * a.planeR);
+      } else {
+        const int p = kCrtModuli[z];
+        const float inv_pf = 1.0f / (float)p;
+        int sum[4] = {0, 0, 0, 0};
+        for (int q = 0; q < a.nterms; ++q) {
+          const uint32_t v = *reinterpret_cast<const uint32_t*>(row + a.term_off[q] + (int64_t)z * a.planeR);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) sum[b] += a.term_sign[q] * (int)((v >> (8 * b)) & 0xffu);
+        }
+        r4 = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int qq = (int)floorf((float)sum[b] * inv_pf);
+          int r = sum[b] - qq * p;
+          if (r < 0) r += p;
+          if (r >= p) r -= p;
+          r4 |= (uint32_t)r << (8 * b);
+        }
+      }
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         const uint32_t tw = t.T[z][w];
@@ -146,6 +175,31 @@ __global__ __launch_bounds__(256) void int_accumulate_kernel(IntAccumArgs a) {
   }
 }
 
+// Residue planes of chunk sums: out (all N moduli) := the residues of the
+// sum of the `nin` input chunks, each input's residue a signed byte of its
+// class, the sum (|s| <= 8 128) brought into [-p/2, p/2] (256: -128 for
+// 128, the same class); N planes of `plane` bytes per chunk.
+__global__ __launch_bounds__(256) void int_sum_kernel(IntSumArgs a) {
+  const int z = blockIdx.y;
+  const int64_t e8 = (int64_t)blockIdx.x * 256 + threadIdx.x;  // 8 bytes per thread
+  if (e8 * 8 >= a.plane) return;
+  const int p = kCrtModuli[z];
+  const float inv_pf = 1.0f / (float)p;
+  int sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int q = 0; q < a.nin; ++q) {
+    const uint64_t v = *reinterpret_cast<const uint64_t*>(a.base + ((int64_t)a.in[q] * a.N + z) * a.plane + 8 * e8);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) sum[b] += (int)(int8_t)(uint8_t)(v >> (8 * b));
+  }
+  uint64_t packed = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int r = sum[b] - (int)rintf((float)sum[b] * inv_pf) * p;
+    packed |= (uint64_t)(uint8_t)(int8_t)r << (8 * b);
+  }
+  *reinterpret_cast<uint64_t*>(a.base + ((int64_t)a.out * a.N + z) * a.plane + 8 * e8) = packed;
+}
+
 __global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t* C, int words, int64_t pstride, int64_t m,
                                                        int64_t n, int64_t ldc) {
   const int64_t total = m * n;
@@ -159,21 +213,44 @@ __global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t* C, int words, i
 
 hipError_t launch_int_residues(const IntResidueArgs& a, bool cols, hipStream_t s) {
   if (a.chunks < 1 || a.N < 1 || a.N > kCrtMaxModuli || a.Kp % 64 || a.Rp % 32) return hipErrorInvalidValue;
+  if (a.chunk_words < 3 || a.chunk_words > kIntMaxChunkWords) return hipErrorInvalidValue;
   if (a.Rp <= 0 || a.Kp <= 0) return hipSuccess;
-  if (!cols) {
-    const int64_t work = a.Rp * (a.Kp / 8);
-    hipLaunchKernelGGL(int_residue_kernel<false>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, a);
-  } else {
-    if (a.Kp / 64 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(int_residue_kernel<true>, dim3((unsigned)(a.Rp / 32), (unsigned)(a.Kp / 64)), dim3(256),
-                       0, s, a);
+#define MPG_INT_RES(CW)                                                                                  \
+  case CW:                                                                                               \
+    if (!cols) {                                                                                         \
+      const int64_t work = a.Rp * (a.Kp / 8);                                                            \
+      hipLaunchKernelGGL((int_residue_kernel<false, CW>), dim3((unsigned)((work + 255) / 256)), dim3(256), \
+                         0, s, a);                                                                       \
+    } else {                                                                                             \
+      if (a.Kp / 64 > 65535) return hipErrorInvalidValue;                                                \
+      hipLaunchKernelGGL((int_residue_kernel<true, CW>), dim3((unsigned)(a.Rp / 32), (unsigned)(a.Kp / 64)), \
+                         dim3(256), 0, s, a);                                                            \
+    }                                                                                                    \
+    break;
+  switch (a.chunk_words) {
+    MPG_INT_RES(3)
+    MPG_INT_RES(4)
+    MPG_INT_RES(5)
+    default:
+      return hipErrorInvalidValue;
   }
+#undef MPG_INT_RES
+  return hipGetLastError();
+}
+
+hipError_t launch_int_sum(const IntSumArgs& a, hipStream_t s) {
+  if (a.nin < 1 || a.nin > kIntMaxSumInputs || a.N < 1 || a.N > kCrtMaxModuli || a.plane % 8)
+    return hipErrorInvalidValue;
+  if (a.plane <= 0) return hipSuccess;
+  const int64_t blocks = (a.plane / 8 + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(int_sum_kernel, dim3((unsigned)blocks, (unsigned)a.N), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_int_accumulate(const IntAccumArgs& a, hipStream_t s) {
   if (a.m <= 0 || a.n <= 0) return hipSuccess;
-  if (a.ldr % 4 || a.ldr < a.n) return hipErrorInvalidValue;
+  if (a.ldr % 4 || a.ldr < a.n || a.nterms < 1 || a.nterms > kIntMaxTerms) return hipErrorInvalidValue;
   const int64_t gx = ((a.n + 3) / 4 + 255) / 256;
   const dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(a.m, 65535));
   switch (crt_words(a.N)) {

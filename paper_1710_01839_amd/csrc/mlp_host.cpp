@@ -135,6 +135,18 @@ extern "C" int mpg_mlp_features(int precision, int64_t m, int64_t n, int64_t l, 
   if (tile) t = *tile;
   auto lg = [](double v) { return v > 0 ? std::log2(v) : 0.0; };
   float f[MPG_MLP_FEATURES] = {};
+  if (precision == 0) {  // long-integer product: operand words, chunk words, Karatsuba depth
+    f[0] = (float)(lg((double)m) / 12.0);
+    f[1] = (float)(lg((double)n) / 12.0);
+    f[2] = (float)(lg((double)l) / 12.0);
+    f[8] = (float)(lg(32.0 * t.bm) / 12.0);
+    f[9] = (float)(lg(32.0 * t.bn) / 12.0);
+    f[10] = (float)t.bk / 8.f;
+    f[12] = (float)t.depth / 3.f;
+    f[14] = 3.f;
+    std::memcpy(out, f, sizeof f);
+    return MPG_OK;
+  }
   f[0] = (float)(lg((double)m) / 12.0);
   f[1] = (float)(lg((double)n) / 12.0);
   f[2] = (float)(lg((double)l) / 12.0);

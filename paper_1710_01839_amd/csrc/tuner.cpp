@@ -696,3 +696,263 @@ bool mpg_table_lookup(mpg_ctx* c, int precision, int64_t m, int64_t n, int64_t l
 }
 
 void mpg_destroy_cached(mpg_ctx* c) { mpg_mlp_free(c); }
+
+// ---------------------------------------------------------------------------
+// Plans of the long-integer product: candidates, slab prediction (Section 3)
+// and the three tuning modes
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kIntDbAlgo = 16;  // DB rows of the long-integer product (precision 0)
+
+std::vector<mpg_int_algo> int_candidates(int wa, int wb, int64_t l) {
+  std::vector<mpg_int_algo> out;
+  for (int cw : {4, 3, 5})
+    for (int d = 0; d <= 2; ++d) {
+      const int ca = (wa + cw - 1) / cw, cb = (wb + cw - 1) / cw;
+      if (d > 0 && (1 << d) > std::max(ca, cb)) break;  // nothing left to split
+      if (mpg_int_plan_products(wa, wb, l, cw, d) > 0) out.push_back(mpg_int_algo{cw, d});
+    }
+  return out;
+}
+
+__global__ void fill_words_kernel(uint32_t* p, int64_t n, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint64_t z = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    p[i] = (uint32_t)(z ^ (z >> 31));
+  }
+}
+
+struct IntScratch {
+  int64_t m = 0, n = 0, l = 0;
+  int wa = 0, wb = 0, wc = 0;
+  uint32_t *A = nullptr, *B = nullptr, *C = nullptr;
+};
+
+void free_int_scratch(IntScratch& s) {
+  if (s.A) (void)hipFree(s.A);
+  if (s.B) (void)hipFree(s.B);
+  if (s.C) (void)hipFree(s.C);
+  s.A = s.B = s.C = nullptr;
+}
+
+int make_int_scratch(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int wa, int wb, IntScratch& s) {
+  s.m = m;
+  s.n = n;
+  s.l = l;
+  s.wa = wa;
+  s.wb = wb;
+  s.wc = mpg_int_words_needed(wa, wb, l);
+  hipError_t r = hipMalloc(&s.A, (size_t)(wa * m * l) * 4);
+  if (r == hipSuccess) r = hipMalloc(&s.B, (size_t)(wb * l * n) * 4);
+  if (r == hipSuccess) r = hipMalloc(&s.C, (size_t)(s.wc * m * n) * 4);
+  if (r != hipSuccess) {
+    free_int_scratch(s);
+    (void)hipGetLastError();
+    return mpg_fail(c, MPG_ERR_NOMEM, "tuner buffers of the long-integer product");
+  }
+  hipLaunchKernelGGL(fill_words_kernel, dim3(1024), dim3(256), 0, c->stream, s.A, (int64_t)wa * m * l, 31ull);
+  hipLaunchKernelGGL(fill_words_kernel, dim3(1024), dim3(256), 0, c->stream, s.B, (int64_t)wb * l * n, 37ull);
+  r = hipStreamSynchronize(c->stream);
+  if (r != hipSuccess) {
+    free_int_scratch(s);
+    return mpg_hip_fail(c, r, "tuner buffer fill");
+  }
+  return MPG_OK;
+}
+
+int run_int(mpg_ctx* c, IntScratch& s, int64_t rows, const mpg_int_algo& a) {
+  return mpg_int_run(c, rows, s.n, s.l, s.A, s.wa, s.l, s.m * s.l, s.B, s.wb, s.n, s.l * s.n, s.C, s.wc, s.n,
+                     s.m * s.n, a.chunk_words, a.karatsuba_depth);
+}
+
+void int_db_append(mpg_ctx* c, const IntScratch& s, const mpg_int_algo& a, double ms, const char* kind) {
+  if (c->db_path.empty()) return;
+  FILE* f = std::fopen(c->db_path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"prec\":0,\"m\":%lld,\"n\":%lld,\"l\":%lld,\"algo\":%d,\"bm\":%d,\"bn\":%d,\"bk\":%d,\"tm\":0,"
+               "\"tn\":0,\"depth\":%d,\"slices\":0,\"splits\":0,\"ms\":%.6f,\"kind\":\"%s\"}\n",
+               (long long)s.m, (long long)s.n, (long long)s.l, kIntDbAlgo, s.wa, s.wb, a.chunk_words,
+               a.karatsuba_depth, ms, kind);
+  std::fclose(f);
+}
+
+// Section 3 for the long-integer product, in the GPU form: a wave is
+// enough 256-row tile rows of the residue products for one workgroup on
+// every CU (each launch has tile rows x column tiles x moduli workgroups);
+// slabs of one and two waves, extrapolated linearly in tile rows (waves) to
+// the product's, without rounding; at most two waves: the product itself.
+int int_slab_plan(int64_t m, int64_t n, int64_t l, int wa, int wb, const mpg_int_algo& a, int num_cu, int64_t* r1,
+                  int64_t* r2, double* scale) {
+  const int N = mpg_int_plan_moduli(wa, wb, l, a.chunk_words, a.karatsuba_depth);
+  const int64_t tr = crt_tile_rows(), tiles_n = (n + crt_tile_cols() - 1) / crt_tile_cols();
+  const int64_t tiles_m = (m + tr - 1) / tr;
+  const int64_t per_row = std::max<int64_t>(1, tiles_n * std::max(N, 1));   // workgroups per tile row
+  const int64_t wave_rows = std::max<int64_t>(1, (num_cu + per_row - 1) / per_row);
+  if (tiles_m <= 2 * wave_rows) {
+    *r1 = m;
+    *r2 = 0;
+    *scale = 1.0;
+    return MPG_OK;
+  }
+  *r1 = wave_rows * tr;
+  *r2 = 2 * wave_rows * tr;
+  *scale = (double)tiles_m / (double)wave_rows;
+  return MPG_OK;
+}
+
+int int_predict(mpg_ctx* c, IntScratch& s, const mpg_int_algo& a, double* pred, double* slab_ms) {
+  int64_t r1 = 0, r2 = 0;
+  double scale = 1.0;
+  int_slab_plan(s.m, s.n, s.l, s.wa, s.wb, a, c->num_cu, &r1, &r2, &scale);
+  double t1 = 0.0, t2 = 0.0;
+  int st = time_median(c, 3, [&] { return run_int(c, s, r1, a); }, &t1);
+  if (st == MPG_OK && r2 > 0) st = time_median(c, 3, [&] { return run_int(c, s, r2, a); }, &t2);
+  if (st != MPG_OK) return st;
+  *slab_ms = t1 + t2;
+  *pred = r2 > 0 ? t1 + (t2 - t1) * (scale - 1.0) : t1;
+  return MPG_OK;
+}
+
+}  // namespace
+
+bool mpg_int_table_lookup(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int words_a, int words_b,
+                          mpg_int_algo* algo) {
+  auto it = c->int_table.find(std::make_tuple(m, n, l, words_a, words_b));
+  if (it == c->int_table.end()) return false;
+  *algo = it->second;
+  return true;
+}
+
+extern "C" int mpg_int_num_candidates(int words_a, int words_b, int64_t l) {
+  if (words_a < 1 || words_b < 1 || l < 1) return 0;
+  return (int)int_candidates(words_a, words_b, l).size();
+}
+
+extern "C" int mpg_int_candidate(int words_a, int words_b, int64_t l, int index, mpg_int_algo* algo) {
+  if (!algo || words_a < 1 || words_b < 1 || l < 1) return MPG_ERR_ARG;
+  const auto cs = int_candidates(words_a, words_b, l);
+  if (index < 0 || index >= (int)cs.size()) return MPG_ERR_ARG;
+  *algo = cs[index];
+  return MPG_OK;
+}
+
+extern "C" int64_t mpg_int_products(int words_a, int words_b, int64_t l, const mpg_int_algo* algo) {
+  if (!algo || words_a < 1 || words_b < 1 || l < 1) return 0;
+  return mpg_int_plan_products(words_a, words_b, l, algo->chunk_words, algo->karatsuba_depth);
+}
+
+extern "C" int mpg_int_time(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int words_a, int words_b,
+                            const mpg_int_algo* algo, int reps, double* ms) {
+  if (!c || !algo || !ms || m <= 0 || n <= 0 || l <= 0 || words_a < 1 || words_b < 1 || reps < 1)
+    return c ? mpg_fail(c, MPG_ERR_ARG, "bad timing request") : MPG_ERR_ARG;
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  IntScratch s;
+  if ((st = make_int_scratch(c, m, n, l, words_a, words_b, s)) != MPG_OK) return st;
+  st = time_median(c, reps, [&] { return run_int(c, s, m, *algo); }, ms);
+  if (st == MPG_OK) int_db_append(c, s, *algo, *ms, "trial");
+  free_int_scratch(s);
+  return st;
+}
+
+extern "C" int mpg_int_predict(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int words_a, int words_b,
+                               const mpg_int_algo* algo, double* predicted_ms, double* slab_ms) {
+  if (!c || !algo || !predicted_ms || m <= 0 || n <= 0 || l <= 0 || words_a < 1 || words_b < 1)
+    return c ? mpg_fail(c, MPG_ERR_ARG, "bad prediction request") : MPG_ERR_ARG;
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  IntScratch s;
+  if ((st = make_int_scratch(c, m, n, l, words_a, words_b, s)) != MPG_OK) return st;
+  double sm = 0.0;
+  st = int_predict(c, s, *algo, predicted_ms, &sm);
+  if (slab_ms) *slab_ms = sm;
+  free_int_scratch(s);
+  return st;
+}
+
+extern "C" int mpg_int_tune(mpg_ctx* c, int64_t m, int64_t n, int64_t l, int words_a, int words_b, int mode,
+                            int topk, mpg_int_algo* best_algo, double* best_ms, double* seconds, int* trials) {
+  if (!c) return MPG_ERR_ARG;
+  if (m <= 0 || n <= 0 || l <= 0 || words_a < 1 || words_b < 1 || mode < 0 || mode > 2)
+    return mpg_fail(c, MPG_ERR_ARG, "bad tuning request");
+  if (mode == MPG_TUNE_MLP && !mpg_mlp_ready(c))
+    return mpg_fail(c, MPG_ERR_STATE, "MLP mode needs a trained or loaded run-time model");
+  const auto cands = int_candidates(words_a, words_b, l);
+  if (cands.empty()) return mpg_fail(c, MPG_ERR_UNSUPPORTED, "no plan fits this product");
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  IntScratch s;
+  if ((st = make_int_scratch(c, m, n, l, words_a, words_b, s)) != MPG_OK) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  int ntrials = 0;
+  mpg_int_algo best{};
+  double bms = INFINITY;
+  auto trial = [&](const mpg_int_algo& a) -> int {
+    double ms = 0.0;
+    int r = time_median(c, 3, [&] { return run_int(c, s, m, a); }, &ms);
+    if (r == MPG_ERR_UNSUPPORTED || r == MPG_ERR_NOMEM) {
+      c->last_error.clear();
+      return MPG_OK;
+    }
+    if (r != MPG_OK) return r;
+    ++ntrials;
+    int_db_append(c, s, a, ms, "trial");
+    if (ms < bms) {
+      bms = ms;
+      best = a;
+    }
+    return MPG_OK;
+  };
+  if (mode == MPG_TUNE_EXHAUSTIVE) {
+    for (const auto& a : cands)
+      if ((st = trial(a)) != MPG_OK) break;
+  } else if (mode == MPG_TUNE_PAPER) {
+    // (1) the predicted time of every plan; (2) the best predicted and the
+    // default plan at full size; (3) the faster
+    double bp = INFINITY;
+    mpg_int_algo bpa = cands[0];
+    for (const auto& a : cands) {
+      double pred = 0.0, slab = 0.0;
+      if ((st = int_predict(c, s, a, &pred, &slab)) != MPG_OK) break;
+      int_db_append(c, s, a, pred, "predicted");
+      if (pred < bp) {
+        bp = pred;
+        bpa = a;
+      }
+    }
+    if (st == MPG_OK) st = trial(bpa);
+    if (st == MPG_OK && (bpa.chunk_words != cands[0].chunk_words || bpa.karatsuba_depth != cands[0].karatsuba_depth))
+      st = trial(cands[0]);
+  } else {
+    std::vector<float> X(cands.size() * MPG_MLP_FEATURES), y(cands.size());
+    for (size_t i = 0; i < cands.size(); ++i) {
+      mpg_tile t{words_a, words_b, cands[i].chunk_words, 0, 0, cands[i].karatsuba_depth, 0, 0};
+      mpg_mlp_features(0, m, n, l, kIntDbAlgo, &t, 1, &X[i * MPG_MLP_FEATURES]);
+    }
+    st = mpg_mlp_predict(c, X.data(), (int)cands.size(), y.data());
+    if (st == MPG_OK) {
+      std::vector<size_t> idx(cands.size());
+      for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+      std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return y[a] < y[b]; });
+      const int dflt = std::max(2, (int)((idx.size() + 3) / 4));
+      const int k = std::max(1, std::min<int>(topk > 0 ? topk : dflt, (int)idx.size()));
+      for (int i = 0; i < k; ++i)
+        if ((st = trial(cands[idx[i]])) != MPG_OK) break;
+    }
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  free_int_scratch(s);
+  if (st != MPG_OK) return st;
+  if (ntrials == 0) return mpg_fail(c, MPG_ERR_UNSUPPORTED, "no plan ran for this product");
+  if (best_algo) *best_algo = best;
+  if (best_ms) *best_ms = bms;
+  if (seconds) *seconds = secs;
+  if (trials) *trials = ntrials;
+  c->int_table[std::make_tuple(m, n, l, words_a, words_b)] = best;
+  return MPG_OK;
+}

@@ -41,6 +41,13 @@ class mpg_tile(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class mpg_int_algo(ctypes.Structure):
+    _fields_ = [("chunk_words", ctypes.c_int), ("karatsuba_depth", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"chunk_words": self.chunk_words, "karatsuba_depth": self.karatsuba_depth}
+
+
 class mpg_dd_problem(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("l", ctypes.c_int64),
                 ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldc", ctypes.c_int64),
@@ -101,6 +108,17 @@ _sig("mpg_zgemm_dd", [_vp, _ci, _ci, _i64, _i64, _i64, _pd, _pp, _i64, _pp, _i64
                       _ci, ctypes.POINTER(mpg_tile)])
 _sig("mpg_int_gemm", [_vp, _i64, _i64, _i64, _vp, _ci, _i64, _i64, _vp, _ci, _i64, _i64, _vp, _ci, _i64, _i64])
 _sig("mpg_int_words_needed", [_ci, _ci, _i64])
+_sig("mpg_int_gemm_ex", [_vp, _i64, _i64, _i64, _vp, _ci, _i64, _i64, _vp, _ci, _i64, _i64, _vp, _ci, _i64, _i64,
+                         ctypes.POINTER(mpg_int_algo)])
+_sig("mpg_int_num_candidates", [_ci, _ci, _i64])
+_sig("mpg_int_candidate", [_ci, _ci, _i64, _ci, ctypes.POINTER(mpg_int_algo)])
+_sig("mpg_int_products", [_ci, _ci, _i64, ctypes.POINTER(mpg_int_algo)], _i64)
+_sig("mpg_int_time", [_vp, _i64, _i64, _i64, _ci, _ci, ctypes.POINTER(mpg_int_algo), _ci,
+                      ctypes.POINTER(ctypes.c_double)])
+_sig("mpg_int_predict", [_vp, _i64, _i64, _i64, _ci, _ci, ctypes.POINTER(mpg_int_algo),
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)])
+_sig("mpg_int_tune", [_vp, _i64, _i64, _i64, _ci, _ci, _ci, _ci, ctypes.POINTER(mpg_int_algo),
+                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_ci)])
 _sig("mpgemm_dd_batched", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile)])
 _sig("mpgemm_dd_batched_noalloc", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile)])
 _sig("mpg_batch_plan_create", [_vp, _ci, ctypes.POINTER(mpg_dd_problem), ctypes.POINTER(mpg_tile),
@@ -367,20 +385,48 @@ def _words(t: torch.Tensor, name: str):
     return t.shape[0], t.shape[1], t.shape[2]
 
 
-def int_gemm(ctx: Context, A, B, C):
+def _int_algo(algo):
+    if algo is None:
+        return None
+    if isinstance(algo, mpg_int_algo):
+        return algo
+    a = mpg_int_algo()
+    a.chunk_words = int(algo.get("chunk_words", 4))
+    a.karatsuba_depth = int(algo.get("karatsuba_depth", 0))
+    return a
+
+
+def int_gemm(ctx: Context, A, B, C, algo=None):
     """C := A B exactly for long integers stored as word planes: int32 device
     tensors of shape (words, rows, cols), word 0 least significant, two's
-    complement over all words (the bits are read as unsigned words)."""
+    complement over all words (the bits are read as unsigned words).  algo:
+    {"chunk_words", "karatsuba_depth"} or None (tuning table, else 128-bit
+    chunks without splitting)."""
     wa, m, l = _words(A, "A")
     wb, l2, n = _words(B, "B")
     wc, m2, n2 = _words(C, "C")
     if l2 != l or (m2, n2) != (m, n):
         raise MpgemmError(MPG_ERR_ARG, "shape mismatch")
+    a = _int_algo(algo)
     ctx.bind_stream()
-    st = _lib.mpg_int_gemm(ctx.handle, m, n, l, _ptr(A), wa, l, m * l, _ptr(B), wb, n, l * n,
-                           _ptr(C), wc, n, m * n)
-    ctx.check(st, "mpg_int_gemm")
+    st = _lib.mpg_int_gemm_ex(ctx.handle, m, n, l, _ptr(A), wa, l, m * l, _ptr(B), wb, n, l * n,
+                              _ptr(C), wc, n, m * n, ctypes.byref(a) if a is not None else None)
+    ctx.check(st, "mpg_int_gemm_ex")
     return C
+
+
+def int_candidates(words_a: int, words_b: int, l: int):
+    out = []
+    for i in range(_lib.mpg_int_num_candidates(words_a, words_b, l)):
+        a = mpg_int_algo()
+        _lib.mpg_int_candidate(words_a, words_b, l, i, ctypes.byref(a))
+        out.append(a.as_dict())
+    return out
+
+
+def int_products(words_a: int, words_b: int, l: int, algo) -> int:
+    a = _int_algo(algo)
+    return int(_lib.mpg_int_products(words_a, words_b, l, ctypes.byref(a)))
 
 
 def mpgemm_ozaki_dd(ctx: Context, A, B, C, slices: int = 0, mode: str = "all"):
@@ -652,6 +698,31 @@ class Tuner:
                                               ctypes.byref(ms)), "mpg_select_method")
         return {"precision": p.value, "algo": a.value, "tile": t.as_dict(),
                 "pairs": ("all", "triangle", "crt")[pm.value], "bound_bits": bb.value, "ms": ms.value}
+
+    def int_time(self, m, n, l, words_a, words_b, algo, reps=3):
+        ms = ctypes.c_double()
+        a = _int_algo(algo)
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_int_time(self.ctx.handle, m, n, l, words_a, words_b, ctypes.byref(a), reps,
+                                         ctypes.byref(ms)), "mpg_int_time")
+        return ms.value
+
+    def int_predict(self, m, n, l, words_a, words_b, algo):
+        pred, slab = ctypes.c_double(), ctypes.c_double()
+        a = _int_algo(algo)
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_int_predict(self.ctx.handle, m, n, l, words_a, words_b, ctypes.byref(a),
+                                            ctypes.byref(pred), ctypes.byref(slab)), "mpg_int_predict")
+        return pred.value, slab.value
+
+    def int_tune(self, m, n, l, words_a, words_b, mode="exhaustive", topk=0):
+        a = mpg_int_algo()
+        ms, secs, trials = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        self.ctx.bind_stream()
+        self.ctx.check(_lib.mpg_int_tune(self.ctx.handle, m, n, l, words_a, words_b, TUNE_MODES.get(mode, mode),
+                                         topk, ctypes.byref(a), ctypes.byref(ms), ctypes.byref(secs),
+                                         ctypes.byref(trials)), "mpg_int_tune")
+        return {"algo": a.as_dict(), "ms": ms.value, "seconds": secs.value, "trials": trials.value}
 
     def table_set(self, precision, m, n, l, algo, tile=None):
         """Put a choice into the table MPG_AUTO follows."""

@@ -210,3 +210,28 @@ def test_splitk_plan_and_candidates(lib):
     assert f[6] == 1 and math.isclose(f[13], 1.0)
     f = M.mlp_features("dd", 64, 64, 1 << 20, "splitk", dict(M.variants(2)[7], splits=32))
     assert math.isclose(f[13], 0.5)
+
+
+def test_int_plans_host_only(lib):
+    """Plans of the long-integer product (host only): every chunk width and
+    Karatsuba depth that fits; a plan runs chunk pairs (3/4 per Karatsuba
+    level of the plain count for 2^d-divisible chunk counts) times the moduli
+    the oracle gives for its diagonal sums."""
+    from oracle import crt
+    from paper_1710_01839_amd import mpgemm as M
+    cs = M.int_candidates(64, 64, 1024)
+    assert {(c["chunk_words"], c["karatsuba_depth"]) for c in cs} == {
+        (4, 0), (4, 1), (4, 2), (3, 1), (3, 2), (5, 0), (5, 1), (5, 2)}
+    for cw, chunks in ((4, 16), (5, 13)):
+        bits = 64 * cw + (1024).bit_length() + chunks.bit_length() + 1
+        N = crt.moduli_for_bits(bits)
+        assert M.int_products(64, 64, 1024, {"chunk_words": cw, "karatsuba_depth": 0}) == chunks * chunks * N
+    N4 = crt.moduli_for_bits(256 + 11 + 5 + 1)
+    for d, pairs in ((1, 192), (2, 144), (3, 108)):
+        assert M.int_products(64, 64, 1024, {"chunk_words": 4, "karatsuba_depth": d}) == pairs * N4
+    # 96-bit chunks of 2048-bit operands: 22 chunk pairs per diagonal without a split
+    assert M.int_products(64, 64, 1024, {"chunk_words": 3, "karatsuba_depth": 0}) == 0
+    assert M.int_products(64, 64, 1024, {"chunk_words": 6, "karatsuba_depth": 0}) == 0
+    assert len(M.int_candidates(1, 1, 10)) == 3          # one chunk: no split
+    f = M.mlp_features(0, 256, 512, 1024, 16, {"bm": 64, "bn": 16, "bk": 5, "depth": 2})
+    assert f[3] == f[4] == 0 and f[14] == 3 and abs(f[10] - 5 / 8) < 1e-7 and abs(f[12] - 2 / 3) < 1e-7
