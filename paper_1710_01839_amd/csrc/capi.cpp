@@ -570,6 +570,15 @@ int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
       algo = MPG_BLOCK;
     }
   }
+  if (from_table && algo == MPG_OZAKI_CRT && limbs == 2 && chosen.slices == 0) {
+    // the tabled residue form with the exact slice count, decided on the
+    // device (no read-back): see mpg_dd_crt_auto
+    bool used = false;
+    st = mpg_dd_crt_auto(c, m, n, l, A[0], A[1], lda, B[0], B[1], ldb, C[0], C[1], ldc, &used);
+    if (st != MPG_OK || used) return st;
+    algo = MPG_BLOCK;
+    chosen = mpg_tile{};
+  }
   if (algo == MPG_OZAKI || algo == MPG_OZAKI_CRT) {
     if (algo == MPG_OZAKI && limbs != 2)
       return mpg_fail(c, MPG_ERR_UNSUPPORTED, "the digit form of the split product is DD only");

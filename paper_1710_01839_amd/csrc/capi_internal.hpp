@@ -90,6 +90,11 @@ void mpg_splitk_plan(int64_t m, int64_t n, int64_t l, int bm, int bn, int bk, in
 int mpg_splitk(mpg_ctx* c, int limbs, int splits, int variant, int64_t m, int64_t n, int64_t l,
                const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
                double* const* C, int64_t ldc);
+// MPG_AUTO's asynchronous double-double residue form (ozaki_host.cpp);
+// *used false: the shape admits no residue form, run the block kernel.
+int mpg_dd_crt_auto(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
+                    int64_t lda, const double* B, const double* B_lo, int64_t ldb, double* C_hi, double* C_lo,
+                    int64_t ldc, bool* used);
 // Quad-double product through the residue form (C := A B, four limbs).
 int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const* A, int64_t lda,
                const double* const* B, int64_t ldb, double* const* C, int64_t ldc);

@@ -39,7 +39,11 @@ __device__ void mul_small(uint32_t (&x)[kCrtMaxWords], uint32_t k) {
   }
 }
 
-__global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t) {
+__global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t, const CrtPlan* plan) {
+  if (plan) {
+    if (!plan->ok) return;
+    N = plan->N;
+  }
   const int j = threadIdx.x;
   if (j < N) {
     const int pj = kCrtModuli[j];
@@ -152,6 +156,7 @@ struct RecArgs {
   int64_t m, n;
   double* C[4];
   int64_t ldc;
+  const CrtPlan* plan;  // when set: N and S from it
 };
 
 // QD = false: C (hi, lo) := the value; QD = true: C (four limbs) += it.
@@ -159,6 +164,11 @@ template <int W, bool QD>
 __global__ __launch_bounds__(256) void crt_reconstruct_kernel(RecArgs a) {
   const int64_t j0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
   if (j0 >= a.n) return;
+  if (a.plan) {
+    if (!a.plan->ok) return;
+    a.N = a.plan->N;
+    a.base = 4 - 16 * a.plan->S;
+  }
   const CrtTable& t = *a.t;
   int fj[4];
 #pragma unroll
@@ -201,6 +211,15 @@ __global__ __launch_bounds__(256) void crt_reconstruct_kernel(RecArgs a) {
       }
     }
   }
+}
+
+__global__ void crt_plan_kernel(const int* need, CrtModuliTable t, CrtPlan* plan) {
+  if (threadIdx.x != 0) return;
+  const int S = max(*need, 1);
+  const int N = S <= kCrtMaxSlices ? t.N[S] : 0;
+  plan->S = S;
+  plan->N = N;
+  plan->ok = N > 0 ? 1 : 0;
 }
 
 __global__ void residue_consts_kernel(int N, CrtResidueConsts* rc) {
@@ -271,9 +290,14 @@ int crt_words(int N) {
   return W <= kCrtMaxWords ? W : 0;
 }
 
-hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s) {
+hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s, const CrtPlan* plan) {
   if (N < 1 || N > kCrtMaxModuli) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(crt_table_kernel, dim3(1), dim3(64), 0, s, N, t);
+  hipLaunchKernelGGL(crt_table_kernel, dim3(1), dim3(64), 0, s, N, t, plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_crt_plan(const int* need, const CrtModuliTable& t, CrtPlan* plan, hipStream_t s) {
+  hipLaunchKernelGGL(crt_plan_kernel, dim3(1), dim3(64), 0, s, need, t, plan);
   return hipGetLastError();
 }
 
@@ -285,10 +309,11 @@ hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s)
 
 hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR, int N,
                                   const CrtTable* t, const int* e, const int* f, int S, int64_t m,
-                                  int64_t n, double* const* C, int limbs, int64_t ldc, hipStream_t s) {
+                                  int64_t n, double* const* C, int limbs, int64_t ldc, hipStream_t s,
+                                  const CrtPlan* plan) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (ldr % 4 || ldr < n || (limbs != 2 && limbs != 4)) return hipErrorInvalidValue;
-  RecArgs a{R, ldr, planeR, N, t, e, f, 4 - 16 * S, m, n, {C[0], C[1], nullptr, nullptr}, ldc};
+  RecArgs a{R, ldr, planeR, N, t, e, f, 4 - 16 * S, m, n, {C[0], C[1], nullptr, nullptr}, ldc, plan};
   if (limbs == 4) {
     a.C[2] = C[2];
     a.C[3] = C[3];

@@ -34,6 +34,19 @@ struct CrtTable {
   int N;
 };
 
+// Slice and moduli counts of a residue-form product decided on the device
+// (from the exponent scan's exact slice count), so that the host need not
+// read them back: every kernel given a plan takes S and N from it, and
+// none does anything when ok is 0 (more than kCrtMaxSlices slices).
+struct CrtPlan {
+  int S, N, ok;
+};
+// Moduli for 1..kCrtMaxSlices slices at one l (index S; 0: does not fit).
+struct CrtModuliTable {
+  int N[kCrtMaxSlices + 1];
+};
+hipError_t launch_crt_plan(const int* need, const CrtModuliTable& t, CrtPlan* plan, hipStream_t s);
+
 // One INT8 product per modulus: residue planes z of A ([N] planes of
 // m_pad x l_pad) and of B ([N] planes of n_pad x l_pad, the columns of B as
 // rows), in the tiled layout of crt_plane_offset, padded as crt_tile_rows(),
@@ -54,6 +67,7 @@ struct CrtGemmArgs {
   int mods[kCrtMaxModuli];
   int nseg;
   int64_t segA[kCrtMaxSegments], segB[kCrtMaxSegments];
+  const CrtPlan* plan;  // when set: moduli z >= plan->N do nothing
 };
 
 // Bits the integer product can need: |(A' B')_ij| < l 2^(16 S - 4), and the
@@ -152,7 +166,8 @@ __device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const Cr
   return neg;
 }
 
-hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s);
+// plan (nullable): N from the plan (nothing when it is not ok).
+hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s, const CrtPlan* plan = nullptr);
 
 // Integer images are folded into words of five digits (40 bits, exact
 // doubles), least significant word first; kCrtImageWords of them hold 20
@@ -200,9 +215,11 @@ __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImag
 // A' = trunc(x 2^(8S - 2 - e)) and reduced modulo the N leading moduli:
 // plane z of out (Rp Kp bytes), element (r, k) at crt_plane_offset(r, k, Kp)
 // (r < Rp, k < Kp, zeros in the padding).  Columns of B go through a transposed copy.
+// plan (nullable): S and N from the plan (nothing when it is not ok; the
+// planes must hold the N given here, at least the plan's).
 hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
-                           const CrtResidueConsts* rc, hipStream_t s);
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan = nullptr);
 
 // Workgroup tile of the residue products: A's planes need rows padded to
 // crt_tile_rows(), B's to crt_tile_cols(), K to crt_k_multiple().
@@ -213,8 +230,11 @@ hipError_t launch_crt_gemm(const CrtGemmArgs& a, hipStream_t s);
 // V_ij = X_ij 2^(e_i + f_j + 4 - 16 S), X the CRT value of the N residues:
 // limbs 2: C (hi, lo) := V rounded to double-double; limbs 4: C (four
 // limbs) := C + V in quad-double.
+// plan (nullable): N and S from the plan (nothing when it is not ok; the
+// word count is that of the N given here, at least the plan's).
 hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR, int N,
                                   const CrtTable* t, const int* e, const int* f, int S, int64_t m,
-                                  int64_t n, double* const* C, int limbs, int64_t ldc, hipStream_t s);
+                                  int64_t n, double* const* C, int limbs, int64_t ldc, hipStream_t s,
+                                  const CrtPlan* plan = nullptr);
 
 }  // namespace mpg

@@ -139,6 +139,7 @@ __global__ __launch_bounds__(direct_threads<TM>(), MINW) void direct_kernel(Gemm
   constexpr int BM = 64, BN = 64, BK = kDirectBK, TN = 4, NT = direct_threads<TM>();
   static_assert(NT == 256 || NT == 512, "one or two chunks of 256 per operand");
   __shared__ DirectSmem<L> sm;
+  if (g.skip && *g.skip) return;
   const int per_problem = tiles_m * tiles_n;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const int p = w / per_problem;

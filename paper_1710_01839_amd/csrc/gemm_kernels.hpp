@@ -243,6 +243,7 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN), MINW) void block_kernel(Gemm
                                                                             int tiles_n) {
   constexpr int L = Arith::L;
   __shared__ BlockSmem<L, BM, BN, BK> sm;
+  if (g.skip && *g.skip) return;
   const int per_problem = tiles_m * tiles_n;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const int p = w / per_problem;

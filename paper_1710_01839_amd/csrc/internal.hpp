@@ -19,6 +19,9 @@ struct GemmBatch {
   double* C[4];
   int64_t ldc, sC;
   int count;
+  // when set, a kernel whose *skip is nonzero at run time does nothing (the
+  // fallback of a product decided on the device)
+  const int* skip;
 };
 
 // Block-kernel tile variant description.

@@ -280,7 +280,13 @@ template <bool DD>
 __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const double* Xlo, int64_t R,
                                                        int64_t K, int64_t ld, const int* e, int S, int N,
                                                        int8_t* __restrict__ out, int64_t Rp, int64_t Kp,
-                                                       const CrtResidueConsts* __restrict__ rc) {
+                                                       const CrtResidueConsts* __restrict__ rc,
+                                                       const CrtPlan* plan) {
+  if (plan) {
+    if (!plan->ok) return;
+    S = plan->S;
+    N = plan->N;
+  }
   const int64_t per_row = Kp / 8;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= Rp * per_row) return;
@@ -1026,6 +1032,7 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
     tm = first + in % gsize;
     tn = in / gsize;
   }
+  if (c.plan && z >= c.plan->N) return;  // a modulus the device-side plan does not use
   const int p = c.mods[z];
   const int c16 = 65536 % p;
   const float inv_pf = 1.0f / (float)p;
@@ -1241,7 +1248,7 @@ hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
 
 hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
-                           const CrtResidueConsts* rc, hipStream_t s) {
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan) {
   // the tiled plane layout (crt_plane_offset) needs whole 16-row x 64-k blocks
   if (S < 1 || S > kCrtMaxSlices || N < 1 || N > kCrtMaxModuli || Kp % 64 || Rp % 16)
     return hipErrorInvalidValue;
@@ -1250,10 +1257,10 @@ hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_
   const dim3 grid((unsigned)((work + 255) / 256));
   if (Xlo)
     hipLaunchKernelGGL(crt_rows_kernel<true>, grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out, Rp,
-                       Kp, rc);
+                       Kp, rc, plan);
   else
     hipLaunchKernelGGL(crt_rows_kernel<false>, grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out, Rp,
-                       Kp, rc);
+                       Kp, rc, plan);
   return hipGetLastError();
 }
 

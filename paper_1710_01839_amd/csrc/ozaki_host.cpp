@@ -6,6 +6,7 @@
 #include "capi_internal.hpp"
 #include "blas_internal.hpp"
 #include "crt_internal.hpp"
+#include "internal.hpp"
 #include "ozaki_internal.hpp"
 
 using namespace mpg;
@@ -115,15 +116,18 @@ namespace {
 // one INT8 product per modulus and the reconstruction of the exact integer
 // product, written to C as a double-double (limbs 2) or added to C as a
 // quad-double (limbs 4).
+// With a device-side plan, S and N are the largest the plan may hold
+// (buffers and the reconstruction's word count are sized for them) and the
+// kernels take the plan's own counts.
 int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
                 int64_t lda, const int* e, const double* BT, const double* BT_lo, const int* f, int S,
-                double* const* C, int limbs, int64_t ldc) {
+                double* const* C, int limbs, int64_t ldc, const CrtPlan* plan = nullptr) {
   const int N = crt_moduli_for_bits(crt_product_bits(S, l));
   if (N == 0 || crt_words(N) == 0)
     return mpg_fail(c, MPG_ERR_UNSUPPORTED, "product of %d slices at l = %lld is too wide for the moduli",
                     S, (long long)l);
-  c->last_slices = S;
-  c->last_moduli = N;
+  c->last_slices = plan ? 0 : S;
+  c->last_moduli = plan ? 0 : N;
   // planes padded to the residue products' tile (the rows kernel writes
   // zeros into the padding)
   const int64_t lp = round_up(l, crt_k_multiple()), mp = round_up(m, crt_tile_rows()),
@@ -141,13 +145,13 @@ int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, co
   uint8_t* R = (uint8_t*)out;
   CrtTable* table = (CrtTable*)((char*)out + ((size_t)N * (size_t)(m * n4) + 255) / 256 * 256);
   st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    hipError_t r = launch_crt_table(N, table, c->stream);
+    hipError_t r = launch_crt_table(N, table, c->stream, plan);
     if (r != hipSuccess) return r;
     r = launch_crt_residue_consts(N, consts, c->stream);
     if (r != hipSuccess) return r;
-    r = launch_crt_rows(A, A_lo, m, l, lda, e, S, N, Ares, mp, lp, consts, c->stream);
+    r = launch_crt_rows(A, A_lo, m, l, lda, e, S, N, Ares, mp, lp, consts, c->stream, plan);
     if (r != hipSuccess) return r;
-    return launch_crt_rows(BT, BT_lo, n, l, l, f, S, N, Bres, np, lp, consts, c->stream);
+    return launch_crt_rows(BT, BT_lo, n, l, l, f, S, N, Bres, np, lp, consts, c->stream, plan);
   }, "residue planes");
   if (st != MPG_OK) return st;
   CrtGemmArgs g{};
@@ -162,12 +166,13 @@ int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, co
   g.ldr = n4;
   g.planeR = m * n4;
   g.N = N;
+  g.plan = plan;
   for (int j = 0; j < N; ++j) g.mods[j] = kCrtModuli[j];
   st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_crt_gemm(g, c->stream); },
                   "INT8 MFMA residue products");
   if (st != MPG_OK) return st;
   return mpg_launch(c, MPG_KCLASS_AUX, [&] {
-    return launch_crt_reconstruct(R, n4, m * n4, N, table, e, f, S, m, n, C, limbs, ldc, c->stream);
+    return launch_crt_reconstruct(R, n4, m * n4, N, table, e, f, S, m, n, C, limbs, ldc, c->stream, plan);
   }, "residue reconstruction");
 }
 
@@ -295,6 +300,67 @@ int ozaki_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, 
 }
 
 }  // namespace
+
+// MPG_AUTO with a tabled residue form of the exact slice count, without a
+// host read-back: the exponent scan's count becomes a device-side plan
+// (slices, moduli, whether at most kCrtMaxSlices slices suffice); the
+// residue-form kernels are launched for the most moduli any count may need
+// and take the plan's counts, and the block kernel of the default tile is
+// launched after them and runs only when the plan rules the residue form out.
+// Same results as the explicit call (or the block kernel), bit for bit; the
+// stream is never synchronised and nothing is allocated once the workspace
+// has grown to the shape (so the calls can be captured in a HIP graph after
+// one eager call).
+int mpg_dd_crt_auto(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
+                    int64_t lda, const double* B, const double* B_lo, int64_t ldb, double* C_hi, double* C_lo,
+                    int64_t ldc, bool* used) {
+  *used = false;
+  const int Smax = kCrtMaxSlices;
+  const int Nmax = crt_moduli_for_bits(crt_product_bits(Smax, l));
+  if (Nmax == 0 || crt_words(Nmax) == 0) return MPG_OK;  // the caller runs the block kernel
+  CrtModuliTable tab{};
+  for (int S = 1; S <= Smax; ++S) {
+    const int N = crt_moduli_for_bits(crt_product_bits(S, l));
+    tab.N[S] = N > 0 && crt_words(N) > 0 ? N : 0;
+  }
+  int st;
+  int *e, *f, *counter;
+  if ((st = exponents(c, m, n, l, A, A_lo, lda, B, B_lo, ldb, true, &e, &f, &counter)) != MPG_OK) return st;
+  CrtPlan* plan = reinterpret_cast<CrtPlan*>(counter + 16);  // inside the small slot's 64-int tail
+  if ((st = mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_crt_plan(counter, tab, plan, c->stream); },
+                       "residue-form plan")) != MPG_OK)
+    return st;
+  const bool dd = B_lo != nullptr;
+  const double* Bp[2] = {B, B_lo};
+  double* BT[2] = {nullptr, nullptr};
+  if ((st = transpose_b(c, l, n, Bp, ldb, dd ? 2 : 1, BT)) != MPG_OK) return st;
+  double* Cp[4] = {C_hi, C_lo, nullptr, nullptr};
+  if ((st = crt_product(c, m, n, l, A, A_lo, lda, e, BT[0], BT[1], f, Smax, Cp, 2, ldc, plan)) != MPG_OK)
+    return st;
+  // the fallback, run only when the plan says the residue form does not fit
+  int variant = 0;
+  if ((st = mpg_resolve_variant(c, 2, nullptr, &variant)) != MPG_OK) return st;
+  GemmBatch g{};
+  g.m = m;
+  g.n = n;
+  g.l = l;
+  g.A[0] = A;
+  g.A[1] = A_lo;
+  g.B[0] = B;
+  g.B[1] = B_lo;
+  g.C[0] = C_hi;
+  g.C[1] = C_lo;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.count = 1;
+  g.skip = &plan->ok;
+  if ((st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_dd_block(variant, g, c->stream); },
+                       "block kernel (fallback)")) != MPG_OK)
+    return st;
+  *used = true;
+  return MPG_OK;
+}
 
 extern "C" int mpgemm_ozaki_dd(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A,
                                int64_t lda, const double* B, int64_t ldb, double* C_hi,

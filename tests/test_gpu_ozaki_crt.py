@@ -260,3 +260,52 @@ def test_auto_falls_back_when_the_split_is_ruled_out(gpu):
     torch.cuda.synchronize()
     for p, q in zip(Q1, Q2):
         assert torch.equal(p, q)
+
+
+def test_auto_residue_form_async_and_captured(gpu):
+    """MPG_AUTO with a tabled residue form (exact slice count) decides the
+    slice and moduli counts on the device: at 4096^3 its result equals the
+    explicit call's bit for bit, the call can be captured in a HIP graph (no
+    read-back, no allocation after one eager call) and replayed, and a replay
+    on data that needs more than 20 slices runs the block kernel instead (the
+    decision is taken again on the device at each replay).  The replayed
+    result is checked against the exact product on sampled rows, columns and
+    entries."""
+    from tests.helpers import ExactSample
+    M, ctx = gpu
+    T = M.Tuner(ctx)
+    nn = 4096
+    A, B = inputs.dd_uniform(nn, nn, 180), inputs.dd_uniform(nn, nn, 181)
+    Ad, Bd = M.to_device(A), M.to_device(B)
+    T.table_set("dd", nn, nn, nn, "ozaki_crt", {"slices": 0})
+    C_auto, C_exp = M.empty_like_limbs(nn, nn, 2), M.empty_like_limbs(nn, nn, 2)
+    M.mpgemm_dd(ctx, Ad, Bd, C_auto, algo="auto")          # eager: grows the workspace
+    M.mpgemm_dd_ozaki(ctx, Ad, Bd, C_exp, 0, "crt")
+    torch.cuda.synchronize()
+    assert torch.equal(C_auto[0], C_exp[0]) and torch.equal(C_auto[1], C_exp[1])
+    Cg = M.empty_like_limbs(nn, nn, 2)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        M.mpgemm_dd(ctx, Ad, Bd, Cg, algo="auto")
+    for _ in range(3):
+        for p in Cg:
+            p.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Cg[0], C_exp[0]) and torch.equal(Cg[1], C_exp[1])
+    r = ExactSample(A, B, nrand=64).ratios(M.to_host(Cg), -104)
+    assert r.max() <= 8.0
+    # data whose exact split needs more than 20 slices: the same graph runs
+    # the block kernel
+    Ab = (A[0].copy(), A[1].copy())
+    Ab[0][:, 3] = 2.0 ** -220
+    Ab[1][:, 3] = 0.0
+    for q in range(2):
+        Ad[q].copy_(torch.from_numpy(Ab[q]))
+    C_blk = M.empty_like_limbs(nn, nn, 2)
+    M.mpgemm_dd(ctx, Ad, Bd, C_blk, algo="block")
+    graph.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(Cg[0], C_blk[0]) and torch.equal(Cg[1], C_blk[1])
+    del graph
