@@ -95,7 +95,7 @@ def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
         ctx.prof_enable(False)
         return wall, gms / max(gn, 1)
 
-    out = {}
+    out = {"int8_mfma_sustained_tops": round(M.int8_mfma_rate(ctx), 1)}
     C = M.empty_like_limbs(n, n, 2)
     for name in ("fp64_wide", "fp64_uniform", "dd_uniform"):
         if name.startswith("fp64"):

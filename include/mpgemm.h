@@ -431,6 +431,13 @@ int mpg_ozaki_split(mpg_ctx* ctx, int side, int64_t rows, int64_t cols,
                     const double* X, int64_t ldx, int slices,
                     int8_t* out, int64_t ld_out, int64_t plane, int32_t* exps);
 
+/* Sustained INT8 matrix-core rate of the device, in TOP/s (1 multiply-add =
+ * 2 operations): back-to-back v_mfma_i32_16x16x64_i8 with no memory
+ * traffic, four workgroups of 8 wavefronts per CU, the best of three
+ * event-timed runs.  The ceiling the split products' kernels are compared
+ * with beside the datasheet peak.  Synchronises the stream. */
+int mpg_int8_mfma_rate(mpg_ctx* ctx, double* tops);
+
 /* Slice count used by the context's last mpgemm_ozaki_dd / mpgemm_dd_ozaki call. */
 int mpg_ozaki_last_slices(const mpg_ctx* ctx);
 

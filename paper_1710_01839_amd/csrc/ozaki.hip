@@ -1122,6 +1122,26 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
     }
 }
 
+// Sustained INT8 matrix-core rate: every wavefront issues back-to-back
+// v_mfma_i32_16x16x64_i8 into 32 independent accumulators (no memory
+// traffic), 8 wavefronts per workgroup, one workgroup per CU.  The sums are
+// folded into one word that is stored only if it takes an impossible value,
+// so the compiler keeps every product.
+__global__ __launch_bounds__(512, 1) void mfma_rate_kernel(int steps, int* sink) {
+  const int lane = threadIdx.x % 64;
+  const v4i a = v4i{lane, lane + 1, lane + 2, lane + 3}, b = v4i{3 * lane, 1, 2, lane};
+  v4i acc[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) acc[i] = v4i{0, 0, 0, 0};
+  for (int st = 0; st < steps; ++st)
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[i], 0, 0, 0);
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) t += acc[i][0] + acc[i][3];
+  if (t == 0x7fffffff) sink[0] = t;
+}
+
 struct OzKernels;
 
 template <int S>
@@ -1164,6 +1184,12 @@ void OzTable<S>::fill(OzKernels& k) {
 }
 
 }  // namespace
+
+hipError_t launch_mfma_rate(int blocks, int steps, int* sink, hipStream_t s) {
+  if (blocks < 1 || steps < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mfma_rate_kernel, dim3((unsigned)blocks), dim3(512), 0, s, steps, sink);
+  return hipGetLastError();
+}
 
 int ozaki_max_slices() { return kMaxSlices; }
 int ozaki_block_slices() { return 4; }

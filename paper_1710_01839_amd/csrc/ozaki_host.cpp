@@ -549,3 +549,32 @@ extern "C" int mpg_ozaki_slices_for_bits(int bits, int pairs_mode) {
     if (ozaki_unit_bound(S, pairs_mode) <= std::ldexp(1.0, -bits)) return S;
   return 0;
 }
+
+extern "C" int mpg_int8_mfma_rate(mpg_ctx* c, double* tops) {
+  if (!c || !tops) return MPG_ERR_ARG;
+  int st = mpg_device_guard(c);
+  if (st != MPG_OK) return st;
+  void* small = nullptr;
+  if ((st = mpg_workspace(c, 1, 256, &small)) != MPG_OK) return st;
+  const int blocks = 4 * c->num_cu, steps = 2000;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t r = hipEventCreate(&a);
+  if (r == hipSuccess) r = hipEventCreate(&b);
+  if (r == hipSuccess) r = launch_mfma_rate(blocks, steps, (int*)small, c->stream);  // warm-up
+  float best = 0.f;
+  for (int rep = 0; rep < 3 && r == hipSuccess; ++rep) {
+    r = hipEventRecord(a, c->stream);
+    if (r == hipSuccess) r = launch_mfma_rate(blocks, steps, (int*)small, c->stream);
+    if (r == hipSuccess) r = hipEventRecord(b, c->stream);
+    if (r == hipSuccess) r = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, a, b);
+    if (r == hipSuccess && (best == 0.f || ms < best)) best = ms;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (r != hipSuccess) return mpg_hip_fail(c, r, "INT8 MFMA rate");
+  // 16 x 16 x 64 multiply-adds = 32768 operations per MFMA
+  *tops = (double)blocks * 8 * steps * 32 * 32768.0 / (best * 1e-3) / 1e12;
+  return MPG_OK;
+}

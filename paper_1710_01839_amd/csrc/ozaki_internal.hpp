@@ -21,6 +21,10 @@ struct OzakiGemmArgs {
   int64_t ldc;
 };
 
+// blocks x 512 threads of back-to-back INT8 MFMAs (32 per wavefront and
+// step, `steps` steps); sink: one device int, written only in theory.
+hipError_t launch_mfma_rate(int blocks, int steps, int* sink, hipStream_t s);
+
 int ozaki_max_slices();
 // Slices per pair block of the general kernel, and the largest slice count
 // served by the kernels that split K into INT32-safe chunks.

@@ -151,6 +151,7 @@ _sig("mpg_mlp_load", [_vp, ctypes.c_char_p])
 _sig("mpg_prof_enable", [_vp, _ci])
 _sig("mpg_prof_read", [_vp, _ci, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
 _sig("mpg_test_inject", [_vp, _ci, _ci])
+_sig("mpg_int8_mfma_rate", [_vp, ctypes.POINTER(ctypes.c_double)])
 
 
 def lib():
@@ -461,6 +462,14 @@ def mpgemm_dd_ozaki(ctx: Context, A, B, C, slices: int = 0, mode: str = "all"):
                               ldb, _ptr(C[0]), _ptr(C[1]), ldc, int(slices), PAIR_MODES.get(mode, mode))
     ctx.check(st, "mpgemm_dd_ozaki")
     return C
+
+
+def int8_mfma_rate(ctx: Context) -> float:
+    """Sustained INT8 matrix-core rate of the device, TOP/s."""
+    t = ctypes.c_double()
+    ctx.bind_stream()
+    ctx.check(_lib.mpg_int8_mfma_rate(ctx.handle, ctypes.byref(t)), "mpg_int8_mfma_rate")
+    return t.value
 
 
 def ozaki_last_slices(ctx: Context) -> int:

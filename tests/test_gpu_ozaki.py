@@ -328,3 +328,13 @@ def test_k_beyond_headroom_refused(gpu):
     assert M.ozaki_slices_exact(ctx, A, B) > 24
     with pytest.raises(M.MpgemmError):
         M.mpgemm_ozaki_dd(ctx, A, B, C, 0)
+
+
+def test_int8_mfma_rate(gpu):
+    """The sustained INT8 matrix-core rate the split products are compared
+    with: positive and below the datasheet's dense peak (5.0 POP/s) with a
+    margin for clock boost."""
+    M, ctx = gpu
+    tops = M.int8_mfma_rate(ctx)
+    print("sustained INT8 MFMA rate", tops, "TOP/s")
+    assert 1000.0 < tops < 5600.0
