@@ -4,11 +4,11 @@ the paper's 128- to 2048-bit runs.
     python -m paper_1710_01839_amd.int_study [--n 1024] [--bits 128 256 512 1024 2048]
 
 For each operand size (uniformly random two's complement words, both
-operands the same size) at n x n x n: wall time per product, the INT8
-product launches' total time and the other launches' (residue planes,
-reconstruction), the count of INT8 products of n^3 (chunk pairs x moduli)
-and their rate, and exact multiply-adds per second (n^3 / t).  One JSON line
-per size.
+operands the same size) at n x n x n and each candidate plan (chunk width,
+Karatsuba depth): wall time per product, the INT8 product launches' total
+time and the other launches' (residue planes, chunk sums, reconstruction),
+the count of INT8 products of n^3 (chunk pairs x moduli) and their rate, and
+exact multiply-adds per second (n^3 / t).  One JSON line per size and plan.
 """
 from __future__ import annotations
 
@@ -42,27 +42,27 @@ def main():
                             .view(np.int32)).cuda()
         wc = M.int_words_needed(w, w, n)
         C = torch.empty((wc, n, n), dtype=torch.int32, device="cuda")
-        M.int_gemm(ctx, A, B, C)
-        torch.cuda.synchronize()
-        ctx.prof_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.reps):
-            M.int_gemm(ctx, A, B, C)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / args.reps * 1e3
-        gms, gn = ctx.prof_read(M.MPG_KCLASS_GEMM)
-        ams, _ = ctx.prof_read(M.MPG_KCLASS_AUX)
-        ctx.prof_enable(False)
-        chunks = (w + 3) // 4
-        moduli = int(M._lib.mpg_ozaki_last_moduli(ctx.handle))
-        products = chunks * chunks * moduli
-        gemm_ms = gms / args.reps
-        tops = products * 2.0 * n ** 3 / (gemm_ms * 1e-3) / 1e12
-        print(json.dumps({"bits": bits, "n": n, "words_out": wc, "chunks": chunks, "moduli": moduli,
-                          "int8_products": products, "wall_ms": round(wall, 3), "int8_ms": round(gemm_ms, 3),
-                          "other_ms": round(ams / args.reps, 3), "int8_tops": round(tops, 1),
-                          "frac_int8_peak": round(tops / INT8_PEAK_TOPS, 4),
-                          "exact_madds_per_s": float(f"{n ** 3 / (wall * 1e-3):.4g}")}), flush=True)
+        for plan in M.int_candidates(w, w, n):
+            M.int_gemm(ctx, A, B, C, plan)
+            torch.cuda.synchronize()
+            ctx.prof_enable(True)
+            t0 = time.perf_counter()
+            for _ in range(args.reps):
+                M.int_gemm(ctx, A, B, C, plan)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.reps * 1e3
+            gms, gn = ctx.prof_read(M.MPG_KCLASS_GEMM)
+            ams, _ = ctx.prof_read(M.MPG_KCLASS_AUX)
+            ctx.prof_enable(False)
+            moduli = int(M._lib.mpg_ozaki_last_moduli(ctx.handle))
+            products = M.int_products(w, w, n, plan)
+            gemm_ms = gms / args.reps
+            tops = products * 2.0 * n ** 3 / (gemm_ms * 1e-3) / 1e12
+            print(json.dumps({"bits": bits, "n": n, "plan": plan, "words_out": wc, "moduli": moduli,
+                              "int8_products": products, "wall_ms": round(wall, 3), "int8_ms": round(gemm_ms, 3),
+                              "other_ms": round(ams / args.reps, 3), "int8_tops": round(tops, 1),
+                              "frac_int8_peak": round(tops / INT8_PEAK_TOPS, 4),
+                              "exact_madds_per_s": float(f"{n ** 3 / (wall * 1e-3):.4g}")}), flush=True)
         del A, B, C
         torch.cuda.empty_cache()
     ctx.close()

@@ -6,8 +6,9 @@ the paper's procedure and over exhaustive search.
 
 1. Prediction accuracy: for DD n in {2048, 4096} and QD n = 1024 and the
    first four tile variants, the real full-size block time against the
-   prediction from a slab (GPU rule: one full wave of tiles scaled by wave
-   counts; printed rule: two block rows scaled linearly).
+   prediction from slabs (GPU rule: slabs of one and two waves of resident
+   workgroups, extrapolated linearly in waves; printed rule: two block rows
+   scaled linearly).
 2. Training data: exhaustive tuning of training shapes (every candidate
    timed) into a JSONL timing database; the MLP is trained on it on the GPU.
 3. Held-out shapes: exhaustive, paper and MLP-pruned (the default top-k) tuning; each
