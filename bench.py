@@ -75,6 +75,35 @@ def parse():
     return p.parse_args()
 
 
+
+def _library_int8_gemm(n):
+    """The platform's own INT8 GEMM (torch._int_mm: int8 x int8 -> int32, B
+    column-major) at n^3, as a reference for the INT8 product kernels' rate
+    on the same device: the median of 20 back-to-back calls.  A reported
+    context figure only; nothing here uses it."""
+    import torch
+    try:
+        g = torch.Generator(device="cuda").manual_seed(7)
+        A = torch.randint(-127, 128, (n, n), dtype=torch.int8, device="cuda", generator=g)
+        B = torch.randint(-127, 128, (n, n), dtype=torch.int8, device="cuda", generator=g).t().contiguous().t()
+        torch._int_mm(A, B)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch._int_mm(A, B)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[len(ts) // 2]
+        tops = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        return {"op": "torch._int_mm (int8 x int8 -> int32), n=%d" % n, "ms": round(ms, 4),
+                "tops": round(tops, 1), "frac_int8_peak": round(tops / INT8_PEAK_TOPS, 4)}
+    except Exception as ex:  # the reference is optional context
+        return {"op": "torch._int_mm", "error": str(ex)[:200]}
+
+
 def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
     """Split-precision product (exact slice count) against the plain DD
     algorithm `plain_step(A, B, C)` on the same operands: FP64 operands of the
@@ -95,7 +124,8 @@ def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
         ctx.prof_enable(False)
         return wall, gms / max(gn, 1)
 
-    out = {"int8_mfma_sustained_tops": round(M.int8_mfma_rate(ctx), 1)}
+    out = {"int8_mfma_sustained_tops": round(M.int8_mfma_rate(ctx), 1),
+           "int8_library_gemm": _library_int8_gemm(n)}
     C = M.empty_like_limbs(n, n, 2)
     for name in ("fp64_wide", "fp64_uniform", "dd_uniform"):
         if name.startswith("fp64"):
