@@ -222,15 +222,25 @@ __global__ void crt_plan_kernel(const int* need, CrtModuliTable t, CrtPlan* plan
   plan->ok = N > 0 ? 1 : 0;
 }
 
-__global__ void residue_consts_kernel(int N, CrtResidueConsts* rc) {
+__global__ void residue_consts_kernel(int N, int S, CrtResidueConsts* rc, const CrtPlan* plan) {
+  if (plan) {
+    if (!plan->ok) return;
+    N = plan->N;
+    S = plan->S;
+  }
   const int z = threadIdx.x;
   if (z >= N) return;
   const int p = kCrtModuli[z];
-  int c = 1;
-  for (int w = 0; w < kCrtImageWords; ++w) {
-    rc->c[z][w] = (double)c;
-    for (int k = 0; k < 8 * kCrtDigitsPerWord; ++k) c = (2 * c) % p;
+  for (int k = 0; k < kCrtImageWords; ++k) {
+    // 256^max(S - 5k - 5, 0) mod p; words past the last digit weigh nothing
+    int c = 0;
+    if (kCrtDigitsPerWord * k < S) {
+      c = 1 % p;
+      for (int b = 0; b < 8 * max(S - kCrtDigitsPerWord * (k + 1), 0); ++b) c = (2 * c) % p;
+    }
+    rc->c[z][k] = (double)c;
   }
+  rc->inv[z] = 1.0 / (double)p;
 }
 
 }  // namespace
@@ -301,9 +311,10 @@ hipError_t launch_crt_plan(const int* need, const CrtModuliTable& t, CrtPlan* pl
   return hipGetLastError();
 }
 
-hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s) {
-  if (N < 1 || N > kCrtMaxModuli) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(residue_consts_kernel, dim3(1), dim3(64), 0, s, N, rc);
+hipError_t launch_crt_residue_consts(int N, int S, CrtResidueConsts* rc, hipStream_t s,
+                                     const CrtPlan* plan) {
+  if (N < 1 || N > kCrtMaxModuli || S < 1 || S > kCrtMaxSlices) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(residue_consts_kernel, dim3(1), dim3(64), 0, s, N, S, rc, plan);
   return hipGetLastError();
 }
 

@@ -170,19 +170,25 @@ __device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const Cr
 hipError_t launch_crt_table(int N, CrtTable* t, hipStream_t s, const CrtPlan* plan = nullptr);
 
 // Integer images are folded into words of five digits (40 bits, exact
-// doubles), least significant word first; kCrtImageWords of them hold 20
-// digits.  Residue weights 2^(40 w) mod p_z per modulus.
+// doubles), most significant word first: word k holds digits 5k .. 5k + 4
+// (digit 0 the leading one), Horner-folded, so with S digits its weight is
+// 256^max(S - 5k - 5, 0); kCrtImageWords of them hold 20 digits.  The
+// residue constants of one slice count S: c[z][k] = that weight mod p_z
+// (0 for words past the last digit) and inv[z] = 1 / p_z rounded to double.
 constexpr int kCrtDigitsPerWord = 5;
 constexpr int kCrtImageWords = kCrtMaxSlices / kCrtDigitsPerWord;
 struct CrtResidueConsts {
   double c[kCrtMaxModuli][kCrtImageWords];
+  double inv[kCrtMaxModuli];
 };
-hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s);
+// plan (nullable): S from the plan (nothing when it is not ok).
+hipError_t launch_crt_residue_consts(int N, int S, CrtResidueConsts* rc, hipStream_t s,
+                                     const CrtPlan* plan = nullptr);
 
 // Residues of 8 elements' images (words[w][q], the first NW words nonzero;
 // |sum_w word c| < 2^51, so the sum, the rounded quotient's product and the
 // remainder are exact in FP64) modulo p, packed as signed bytes (element q
-// in byte q).  The computed quotient acc (1/p) is within 1/(2p) of the
+// in byte q); inv is 1/p rounded.  The computed quotient acc inv is within 1/(2p) of the
 // exact one (two roundings of relative 2^-53 on a value below 2^51 / p), so
 // the remainder of its nearest integer lies in [-(p+1)/2, (p+1)/2]: for the
 // odd moduli up to 253 that is inside [-127, 127] and already a signed
@@ -191,8 +197,8 @@ hipError_t launch_crt_residue_consts(int N, CrtResidueConsts* rc, hipStream_t s)
 // p at the end.
 template <int NW, bool CENTRE>
 __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImageWords][8],
-                                                  const double* c, int p) {
-  const double pd = (double)p, inv = 1.0 / pd;
+                                                  const double* c, int p, double inv) {
+  const double pd = (double)p;
   uint64_t packed = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {

@@ -197,18 +197,22 @@ __global__ __launch_bounds__(256) void col_finish_kernel(int* top_e, const int* 
 // part pulls toward zero (then one less in magnitude); the new remainder
 // is renormalised by an exact TwoSum.
 template <bool DD>
-__device__ __forceinline__ int digit_step(double& y, double& yl) {
+__device__ __forceinline__ double digit_value(double& y, double& yl) {
   const double sh = y * 256.0;
   if (!DD) {
     const double t = trunc(sh);
     y = sh - t;
-    return (int)t;
+    return t;
   }
   const double sl = yl * 256.0;
   double t = trunc(sh);
   if (t == sh && sh != 0.0 && sl != 0.0 && ((sl < 0.0) != (sh < 0.0))) t -= sh > 0.0 ? 1.0 : -1.0;
   two_sum(sh - t, sl, y, yl);
-  return (int)t;
+  return t;
+}
+template <bool DD>
+__device__ __forceinline__ int digit_step(double& y, double& yl) {
+  return (int)digit_value<DD>(y, yl);
 }
 
 // The carry that turns truncated digits into signed bytes, on one 8-byte
@@ -301,21 +305,20 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
     yl[q] = 0.0;
     if (DD) two_sum(y[q], ldexp(ok ? Xlo[r * ld + k] : 0.0, -(er + 2)), y[q], yl[q]);
   }
+  // word k gathers digits 5k .. 5k + 4 by Horner's rule (|word| < 2^40,
+  // every step exact); the word of a digit is known at compile time, so no
+  // register is selected at run time
   double words[kCrtImageWords][8];
 #pragma unroll
   for (int w = 0; w < kCrtImageWords; ++w)
 #pragma unroll
     for (int q = 0; q < 8; ++q) words[w][q] = 0.0;
-  for (int s = 0; s < S; ++s) {
-    const int pos = S - 1 - s;  // digit s + 1 weighs 256^pos in the image
-    const int w = pos / kCrtDigitsPerWord;
-    const double wt = (double)(1ull << (8 * (pos % kCrtDigitsPerWord)));
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double d = (double)digit_step<DD>(y[q], yl[q]);
+  for (int s = 0; s < kCrtMaxSlices; ++s) {
+    if (s < S) {  // uniform
+      const int k = s / kCrtDigitsPerWord;
 #pragma unroll
-      for (int ww = 0; ww < kCrtImageWords; ++ww)
-        if (ww == w) words[ww][q] = __builtin_fma(d, wt, words[ww][q]);
+      for (int q = 0; q < 8; ++q) words[k][q] = __builtin_fma(words[k][q], 256.0, digit_value<DD>(y[q], yl[q]));
     }
   }
   const int64_t plane = Rp * Kp;
@@ -325,13 +328,13 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
   if (S <= 2 * kCrtDigitsPerWord) {
     for (int z = 0; z < N; ++z)
       *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + crt_plane_offset(r, k0, Kp)) =
-          z < 2 ? crt_residues8<2, true>(words, rc->c[z], kCrtModuli[z])
-                : crt_residues8<2, false>(words, rc->c[z], kCrtModuli[z]);
+          z < 2 ? crt_residues8<2, true>(words, rc->c[z], kCrtModuli[z], rc->inv[z])
+                : crt_residues8<2, false>(words, rc->c[z], kCrtModuli[z], rc->inv[z]);
   } else {
     for (int z = 0; z < N; ++z)
       *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + crt_plane_offset(r, k0, Kp)) =
-          z < 2 ? crt_residues8<kCrtImageWords, true>(words, rc->c[z], kCrtModuli[z])
-                : crt_residues8<kCrtImageWords, false>(words, rc->c[z], kCrtModuli[z]);
+          z < 2 ? crt_residues8<kCrtImageWords, true>(words, rc->c[z], kCrtModuli[z], rc->inv[z])
+                : crt_residues8<kCrtImageWords, false>(words, rc->c[z], kCrtModuli[z], rc->inv[z]);
   }
 }
 

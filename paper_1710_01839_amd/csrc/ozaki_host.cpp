@@ -147,7 +147,7 @@ int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, co
   st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
     hipError_t r = launch_crt_table(N, table, c->stream, plan);
     if (r != hipSuccess) return r;
-    r = launch_crt_residue_consts(N, consts, c->stream);
+    r = launch_crt_residue_consts(N, S, consts, c->stream, plan);
     if (r != hipSuccess) return r;
     r = launch_crt_rows(A, A_lo, m, l, lda, e, S, N, Ares, mp, lp, consts, c->stream, plan);
     if (r != hipSuccess) return r;
@@ -468,7 +468,7 @@ int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const*
   st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
     hipError_t r = launch_crt_table(N, table, c->stream);
     if (r != hipSuccess) return r;
-    if ((r = launch_crt_residue_consts(N, consts, c->stream)) != hipSuccess) return r;
+    if ((r = launch_crt_residue_consts(N, Sc, consts, c->stream)) != hipSuccess) return r;
     for (int pa = 0; pa < 2; ++pa)
       if (useA[pa] && (r = launch_crt_rows(A[2 * pa], A[2 * pa + 1], m, l, lda, pa ? eL : eH, Sc, N, Ares[pa],
                                            mpad, lp, consts, c->stream)) != hipSuccess)
