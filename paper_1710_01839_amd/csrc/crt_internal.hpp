@@ -220,10 +220,15 @@ __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImag
 // truncated radix-256 digits of x 2^-(e + 2) are folded into the image
 // A' = trunc(x 2^(8S - 2 - e)) and reduced modulo the N leading moduli:
 // plane z of out (Rp Kp bytes), element (r, k) at crt_plane_offset(r, k, Kp)
-// (r < Rp, k < Kp, zeros in the padding).  Columns of B go through a transposed copy.
+// (r < Rp, k < Kp, zeros in the padding).
 // plan (nullable): S and N from the plan (nothing when it is not ok; the
 // planes must hold the N given here, at least the plan's).
 hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                           const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan = nullptr);
+// The same for the columns of X (K x R row-major, leading dimension ld):
+// plane row r is column r of X (B's columns, read in place).
+hipError_t launch_crt_cols(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
                            const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan = nullptr);
 

@@ -280,7 +280,13 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const double* X, const 
 // digits (before any carry: the carry does not change their weighted sum)
 // are folded into the image's 40-bit words in registers and only the
 // residues are written, one byte per element and modulus.
-template <bool DD>
+//
+// COLS: the rows of the plane are the columns of X (X is K x R, element
+// (r, k) at X[k ld + r]), read in place instead of through a transposed
+// copy.  A wavefront then takes 8 columns x 64 k: for each k its lanes read
+// 64 contiguous bytes of a row of X, and the 8 bytes each lane writes per
+// modulus fill half of a 16 x 64 block of the plane (512 contiguous bytes).
+template <bool DD, bool COLS>
 __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const double* Xlo, int64_t R,
                                                        int64_t K, int64_t ld, const int* e, int S, int N,
                                                        int8_t* __restrict__ out, int64_t Rp, int64_t Kp,
@@ -294,16 +300,26 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
   const int64_t per_row = Kp / 8;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= Rp * per_row) return;
-  const int64_t r = idx / per_row, k0 = (idx % per_row) * 8;
+  int64_t r, k0;
+  if (!COLS) {
+    r = idx / per_row;
+    k0 = (idx % per_row) * 8;
+  } else {
+    // Rp % 16 == 0 and Kp % 64 == 0: whole 8 x 64 groups
+    const int64_t t = idx / 64, lane = idx % 64, col_groups = Rp / 8;
+    r = (t % col_groups) * 8 + lane % 8;
+    k0 = ((t / col_groups) * 8 + lane / 8) * 8;
+  }
   double y[8], yl[8];
   const int er = r < R ? e[r] : 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int64_t k = k0 + q;
     const bool ok = r < R && k < K;
-    y[q] = ldexp(ok ? X[r * ld + k] : 0.0, -(er + 2));
+    const int64_t at = COLS ? k * ld + r : r * ld + k;
+    y[q] = ldexp(ok ? X[at] : 0.0, -(er + 2));
     yl[q] = 0.0;
-    if (DD) two_sum(y[q], ldexp(ok ? Xlo[r * ld + k] : 0.0, -(er + 2)), y[q], yl[q]);
+    if (DD) two_sum(y[q], ldexp(ok ? Xlo[at] : 0.0, -(er + 2)), y[q], yl[q]);
   }
   // word k gathers digits 5k .. 5k + 4 by Horner's rule (|word| < 2^40,
   // every step exact); the word of a digit is known at compile time, so no
@@ -1293,22 +1309,38 @@ hipError_t launch_ozaki_gemm(const OzakiGemmArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
-                           const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
-                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan) {
+namespace {
+template <bool COLS>
+hipError_t launch_crt_planes(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                             const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
+                             const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan) {
   // the tiled plane layout (crt_plane_offset) needs whole 16-row x 64-k blocks
   if (S < 1 || S > kCrtMaxSlices || N < 1 || N > kCrtMaxModuli || Kp % 64 || Rp % 16)
     return hipErrorInvalidValue;
   const int64_t work = Rp * (Kp / 8);
   if (work <= 0) return hipSuccess;
+  if ((work + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((work + 255) / 256));
   if (Xlo)
-    hipLaunchKernelGGL(crt_rows_kernel<true>, grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out, Rp,
-                       Kp, rc, plan);
+    hipLaunchKernelGGL((crt_rows_kernel<true, COLS>), grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out,
+                       Rp, Kp, rc, plan);
   else
-    hipLaunchKernelGGL(crt_rows_kernel<false>, grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out, Rp,
-                       Kp, rc, plan);
+    hipLaunchKernelGGL((crt_rows_kernel<false, COLS>), grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out,
+                       Rp, Kp, rc, plan);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                           const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan) {
+  return launch_crt_planes<false>(X, Xlo, R, K, ld, e, S, N, out, Rp, Kp, rc, s, plan);
+}
+
+hipError_t launch_crt_cols(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
+                           const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan) {
+  return launch_crt_planes<true>(X, Xlo, R, K, ld, e, S, N, out, Rp, Kp, rc, s, plan);
 }
 
 int crt_tile_rows() { return kCrtBM; }

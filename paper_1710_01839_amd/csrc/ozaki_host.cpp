@@ -120,8 +120,8 @@ namespace {
 // (buffers and the reconstruction's word count are sized for them) and the
 // kernels take the plan's own counts.
 int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
-                int64_t lda, const int* e, const double* BT, const double* BT_lo, const int* f, int S,
-                double* const* C, int limbs, int64_t ldc, const CrtPlan* plan = nullptr) {
+                int64_t lda, const int* e, const double* B, const double* B_lo, int64_t ldb, const int* f,
+                int S, double* const* C, int limbs, int64_t ldc, const CrtPlan* plan = nullptr) {
   const int N = crt_moduli_for_bits(crt_product_bits(S, l));
   if (N == 0 || crt_words(N) == 0)
     return mpg_fail(c, MPG_ERR_UNSUPPORTED, "product of %d slices at l = %lld is too wide for the moduli",
@@ -151,7 +151,7 @@ int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, co
     if (r != hipSuccess) return r;
     r = launch_crt_rows(A, A_lo, m, l, lda, e, S, N, Ares, mp, lp, consts, c->stream, plan);
     if (r != hipSuccess) return r;
-    return launch_crt_rows(BT, BT_lo, n, l, l, f, S, N, Bres, np, lp, consts, c->stream, plan);
+    return launch_crt_cols(B, B_lo, n, l, ldb, f, S, N, Bres, np, lp, consts, c->stream, plan);
   }, "residue planes");
   if (st != MPG_OK) return st;
   CrtGemmArgs g{};
@@ -176,33 +176,13 @@ int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, co
   }, "residue reconstruction");
 }
 
-// Copies `count` limb planes of B (l x n) transposed into workspace slot 0
-// (n x l each, leading dimension l).
-int transpose_b(mpg_ctx* c, int64_t l, int64_t n, const double* const* B, int64_t ldb, int count,
-                double** BT) {
-  void* w = nullptr;
-  int st = mpg_workspace(c, 0, (size_t)count * (size_t)(n * l) * sizeof(double), &w);
-  if (st != MPG_OK) return st;
-  PackArgs pk{};
-  for (int q = 0; q < count; ++q) {
-    BT[q] = (double*)w + (size_t)q * (size_t)(n * l);
-    pk.job[q] = PackJob{B[q], BT[q], n, l, ldb, l, 1, 1.0};
-  }
-  pk.count = count;
-  return mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_pack(pk, c->stream); }, "transposed copy of B");
-}
-
 // The double-double residue form after the scales.
 int crt_tail(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, const double* A_lo,
              int64_t lda, const double* B, const double* B_lo, int64_t ldb, double* C_hi,
              double* C_lo, int64_t ldc, int S, const int* e, const int* f) {
   const bool dd = B_lo != nullptr;
-  const double* Bp[2] = {B, B_lo};
-  double* BT[2] = {nullptr, nullptr};
-  int st = transpose_b(c, l, n, Bp, ldb, dd ? 2 : 1, BT);
-  if (st != MPG_OK) return st;
   double* Cp[4] = {C_hi, C_lo, nullptr, nullptr};
-  return crt_product(c, m, n, l, A, A_lo, lda, e, BT[0], BT[1], f, S, Cp, 2, ldc);
+  return crt_product(c, m, n, l, A, A_lo, lda, e, B, dd ? B_lo : nullptr, ldb, f, S, Cp, 2, ldc);
 }
 
 __global__ void zero_ints_kernel(int* p, int count) {
@@ -330,12 +310,8 @@ int mpg_dd_crt_auto(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A
   if ((st = mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_crt_plan(counter, tab, plan, c->stream); },
                        "residue-form plan")) != MPG_OK)
     return st;
-  const bool dd = B_lo != nullptr;
-  const double* Bp[2] = {B, B_lo};
-  double* BT[2] = {nullptr, nullptr};
-  if ((st = transpose_b(c, l, n, Bp, ldb, dd ? 2 : 1, BT)) != MPG_OK) return st;
   double* Cp[4] = {C_hi, C_lo, nullptr, nullptr};
-  if ((st = crt_product(c, m, n, l, A, A_lo, lda, e, BT[0], BT[1], f, Smax, Cp, 2, ldc, plan)) != MPG_OK)
+  if ((st = crt_product(c, m, n, l, A, A_lo, lda, e, B, B_lo, ldb, f, Smax, Cp, 2, ldc, plan)) != MPG_OK)
     return st;
   // the fallback, run only when the plan says the residue form does not fit
   int variant = 0;
@@ -427,8 +403,6 @@ int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const*
                       "an exact split of the quad-double operands needs %d slices per part (max %d)", S[k],
                       kCrtMaxSlices);
   }
-  double* BT[4] = {nullptr, nullptr, nullptr, nullptr};
-  if ((st = transpose_b(c, l, n, B, ldb, 4, BT)) != MPG_OK) return st;
   if ((st = mpg_launch(c, MPG_KCLASS_AUX, [&] { return launch_zero(C, 4, m, n, ldc, c->stream); },
                        "zero C")) != MPG_OK)
     return st;
@@ -474,7 +448,7 @@ int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const*
                                            mpad, lp, consts, c->stream)) != hipSuccess)
         return r;
     for (int pb = 0; pb < 2; ++pb)
-      if (useB[pb] && (r = launch_crt_rows(BT[2 * pb], BT[2 * pb + 1], n, l, l, pb ? fL : fH, Sc, N, Bres[pb],
+      if (useB[pb] && (r = launch_crt_cols(B[2 * pb], B[2 * pb + 1], n, l, ldb, pb ? fL : fH, Sc, N, Bres[pb],
                                            npad, lp, consts, c->stream)) != hipSuccess)
         return r;
     return hipSuccess;
