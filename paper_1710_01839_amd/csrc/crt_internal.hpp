@@ -185,10 +185,10 @@ struct CrtResidueConsts {
 hipError_t launch_crt_residue_consts(int N, int S, CrtResidueConsts* rc, hipStream_t s,
                                      const CrtPlan* plan = nullptr);
 
-// Residues of 8 elements' images (words[w][q], the first NW words nonzero;
-// |sum_w word c| < 2^51, so the sum, the rounded quotient's product and the
-// remainder are exact in FP64) modulo p, packed as signed bytes (element q
-// in byte q); inv is 1/p rounded.  The computed quotient acc inv is within 1/(2p) of the
+// Residues of 8 elements' images (sum_w words[w][q] c[w], the first NW
+// words nonzero, |word| < 2^41 + 2, c < 256: the sum stays below 2^51, so
+// it, the rounded quotient's product and the remainder are exact in FP64)
+// modulo p, packed as signed bytes (element q in byte q); inv is 1/p rounded.  The computed quotient acc inv is within 1/(2p) of the
 // exact one (two roundings of relative 2^-53 on a value below 2^51 / p), so
 // the remainder of its nearest integer lies in [-(p+1)/2, (p+1)/2]: for the
 // odd moduli up to 253 that is inside [-127, 127] and already a signed

@@ -310,20 +310,31 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
     r = (t % col_groups) * 8 + lane % 8;
     k0 = ((t / col_groups) * 8 + lane / 8) * 8;
   }
+  // y: the scaled leading part; yl: the scaled trailing part (DD), each cut
+  // into digits on its own (a pair is not renormalised)
   double y[8], yl[8];
+  unsigned neg = 0;  // bit q: the element hi + lo is negative (the sign of its rounded sum)
   const int er = r < R ? e[r] : 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int64_t k = k0 + q;
     const bool ok = r < R && k < K;
     const int64_t at = COLS ? k * ld + r : r * ld + k;
-    y[q] = ldexp(ok ? X[at] : 0.0, -(er + 2));
+    const double hi = ok ? X[at] : 0.0;
+    y[q] = ldexp(hi, -(er + 2));
     yl[q] = 0.0;
-    if (DD) two_sum(y[q], ldexp(ok ? Xlo[at] : 0.0, -(er + 2)), y[q], yl[q]);
+    if (DD) {
+      const double lo = ok ? Xlo[at] : 0.0;
+      yl[q] = ldexp(lo, -(er + 2));
+      neg |= (unsigned)(hi + lo < 0.0) << q;
+    }
   }
-  // word k gathers digits 5k .. 5k + 4 by Horner's rule (|word| < 2^40,
-  // every step exact); the word of a digit is known at compile time, so no
-  // register is selected at run time
+  // word k gathers digits 5k .. 5k + 4 by Horner's rule; the word of a
+  // digit is known at compile time, so no register is selected at run time.
+  // DD: the digit is the sum of the two parts' truncated digits (|d| <= 510,
+  // |word| < 2^41, every step exact; canonical pairs, |lo| <= ulp(hi) / 2,
+  // keep both parts below 1 after the row scale), so the words hold
+  // trunc(hi 2^s) + trunc(lo 2^s), s = 8S - 2 - e.
   double words[kCrtImageWords][8];
 #pragma unroll
   for (int w = 0; w < kCrtImageWords; ++w)
@@ -334,7 +345,33 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
     if (s < S) {  // uniform
       const int k = s / kCrtDigitsPerWord;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) words[k][q] = __builtin_fma(words[k][q], 256.0, digit_value<DD>(y[q], yl[q]));
+      for (int q = 0; q < 8; ++q) {
+        double dummy = 0.0;
+        double d = digit_value<false>(y[q], dummy);
+        if (DD) d += digit_value<false>(yl[q], dummy);
+        words[k][q] = __builtin_fma(words[k][q], 256.0, d);
+      }
+    }
+  }
+  // DD: with I = trunc(hi 2^s) + trunc(lo 2^s) (the words) and the two
+  // remainders rh, rl (|rh|, |rl| < 1), (hi + lo) 2^s = I + F, F = rh + rl,
+  // so trunc((hi + lo) 2^s) = I + delta, delta = floor(F) when hi + lo >= 0
+  // and ceil(F) when it is negative (|delta| <= 2), decided on the exact
+  // sum f + g = F
+  // delta goes into the word of the last digit, whose weight is 1 (|word|
+  // stays below 2^41 + 2); the word is chosen by a uniform branch
+  if (DD) {
+    const int klast = (S - 1) / kCrtDigitsPerWord;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double f, g;
+      two_sum(y[q], yl[q], f, g);
+      const bool nq = (neg >> q) & 1;
+      double t = nq ? ceil(f) : floor(f);
+      if (t == f) t += nq ? (g > 0.0 ? 1.0 : 0.0) : (g < 0.0 ? -1.0 : 0.0);
+#pragma unroll
+      for (int k = 0; k < kCrtImageWords; ++k)
+        if (k == klast) words[k][q] += t;
     }
   }
   const int64_t plane = Rp * Kp;

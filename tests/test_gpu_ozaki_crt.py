@@ -86,6 +86,35 @@ def test_matches_oracle(gpu, kind, S):
     assert r <= 1.0
 
 
+def _short_heads_long_tails(rows, cols, seed):
+    """Canonical double-double entries whose leading part has 11 bits and
+    whose trailing part, of either sign, lies far below it: truncating
+    such a value inside the gap must borrow from the leading part when the
+    two parts have opposite signs."""
+    rng = np.random.default_rng(seed)
+    hi = rng.integers(1 << 10, 1 << 11, size=(rows, cols)).astype(np.float64) * 2.0 ** -11
+    hi *= rng.choice([-1.0, 1.0], size=(rows, cols))
+    lo = rng.integers(1, 1 << 30, size=(rows, cols)).astype(np.float64) * 2.0 ** -60
+    lo *= rng.choice([-1.0, 1.0], size=(rows, cols))
+    lo[rng.random((rows, cols)) < 0.2] = 0.0
+    return hi, lo
+
+
+@pytest.mark.parametrize("S", [3, 4, 5])
+def test_truncation_across_opposite_signed_parts(gpu, S):
+    """Truncated slicing with the cut between the parts (S = 3: the whole
+    trailing part below it; 4, 5: part of it above): every entry against the
+    oracle's images, which truncate hi + lo as one exact value."""
+    M, ctx = gpu
+    m, n, l = 70, 60, 90
+    A, B = _short_heads_long_tails(m, l, 90), _short_heads_long_tails(l, n, 91)
+    C = run_crt(M, ctx, A, B, S)
+    assert M.ozaki_last_slices(ctx) == S
+    r = worst_relative(C, A, B, S)
+    print("short heads, long tails: S", S, "worst / 2^-104 |V|", r)
+    assert r <= 1.0
+
+
 def test_integer_data_exact_and_long_k(gpu):
     """Integer entries in [-63, 63] with l = 140000 (several reductions of
     the INT32 sums): the product is exact."""
