@@ -180,13 +180,22 @@ __global__ __launch_bounds__(256) void crt_reconstruct_kernel(RecArgs a) {
 #pragma unroll
       for (int w = 0; w < W; ++w) acc[b][w] = 0;
     const uint8_t* row = a.R + i * a.ldr + j0;
-    for (int z = 0; z < a.N; ++z) {
-      const uint32_t r4 = *reinterpret_cast<const uint32_t*>(row + (int64_t)z * a.planeR);
+    // the residues of eight moduli are loaded together, so a thread waits for
+    // one load latency per eight moduli instead of one per modulus
+    for (int z0 = 0; z0 < a.N; z0 += 8) {
+      uint32_t r4[8];
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const uint32_t tw = t.T[z][w];
+      for (int u = 0; u < 8; ++u)
+        r4[u] = z0 + u < a.N ? *reinterpret_cast<const uint32_t*>(row + (int64_t)(z0 + u) * a.planeR) : 0u;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[b][w] += (uint64_t)((r4 >> (8 * b)) & 0xffu) * tw;
+      for (int u = 0; u < 8; ++u) {
+        if (z0 + u >= a.N) break;  // uniform
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint32_t tw = t.T[z0 + u][w];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[b][w] += (uint64_t)((r4[u] >> (8 * b)) & 0xffu) * tw;
+        }
       }
     }
     const int ei = a.e[i];
