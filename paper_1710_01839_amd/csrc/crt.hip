@@ -57,6 +57,28 @@ __global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t, const
     mul_small(M, (uint32_t)inverse_mod(mmod, pj));
     for (int w = 0; w < kCrtMaxWords; ++w) t->T[j][w] = M[w];
   }
+  // signed radix-256 digits of T[j] into the MFMA fragment table (zeros for
+  // the moduli past N, up to the 64 the K range of one product holds)
+  {
+    int carry = 0;
+    for (int b = 0; b < 4 * kCrtMaxWords; ++b) {
+      int v = carry;
+      if (j < N) v += (int)((t->T[j][b / 4] >> (8 * (b % 4))) & 0xffu);
+      carry = v >= 128 ? 1 : 0;
+      t->frag[b / 16][16 * (j / 16) + b % 16][j % 16] = (int8_t)(v - 256 * carry);
+    }
+  }
+  __syncthreads();  // every T[j] written before thread 0 sums them
+  if (j == 0) {
+    // K0 = 128 sum_j T[j]: per-word sums below 2^45, then one carry pass
+    uint64_t c = 0;
+    for (int w = 0; w < kCrtMaxWords; ++w) {
+      uint64_t s = c;
+      for (int i = 0; i < N; ++i) s += (uint64_t)t->T[i][w] << 7;
+      t->K0[w] = (uint32_t)s;
+      c = s >> 32;
+    }
+  }
   if (j == 0) {
     uint32_t P[kCrtMaxWords] = {1};
     for (int i = 0; i < N; ++i) mul_small(P, (uint32_t)kCrtModuli[i]);
@@ -75,10 +97,9 @@ __global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t, const
 }
 
 // ---------------------------------------------------------------------
-// Reconstruction: a thread takes four consecutive columns of one row.
-//   1. per 32-bit word w, sum_j r_j T_j[w] in a 64-bit accumulator (each
-//      term < 2^40, N <= 49 terms: no carries needed until the end), then
-//      one carry pass gives X' = sum_j r_j T_j < N 255 P < 2^(32 W);
+// Reconstruction of one output:
+//   1. X' = sum_j r_j T_j < N 255 P < 2^(32 W) in W 32-bit words (formed by
+//      INT8 MFMAs over the T_j's digits, see the kernel below);
 //   2. q = floor(X' / P) from doubles (X' / P < 2^14, relative error far
 //      below 2^-14), then Y = X' - q P by words; a negative Y or Y >= P is
 //      corrected by one addition or subtraction of P;
@@ -159,66 +180,127 @@ struct RecArgs {
   const CrtPlan* plan;  // when set: N and S from it
 };
 
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
 // QD = false: C (hi, lo) := the value; QD = true: C (four limbs) += it.
+// A workgroup takes 256 consecutive columns of a row at a time:
+//   1. the residues of its 256 outputs for every modulus go into LDS as
+//      signed bytes u_j = r_j - 128, one row of moduli per output (a thread
+//      loads four moduli x four columns and transposes the 4 x 4 bytes);
+//   2. X_b = sum_j u_j d_jb for every digit position b of the T[j] is one
+//      INT8 MFMA per 16 positions and 16 outputs (|X_b| <= 49 128^2 < 2^20,
+//      exact in INT32), and the four positions of word w combine into
+//      V_w = sum_i X_{4w+i} 2^(8i) (exact in 64 bits);
+//   3. a thread per output adds K0 = 128 sum_j T[j] (sum_j r_j T[j] =
+//      sum_w V_w 2^(32 w) + K0) with a signed carry pass: the value is below
+//      2^(32 W), so the W low words hold it and the positions from 4W up
+//      cancel against the last carry; then as before (quotient by P,
+//      centring, double-double or quad-double).
 template <int W, bool QD>
-__global__ __launch_bounds__(256) void crt_reconstruct_kernel(RecArgs a) {
-  const int64_t j0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
-  if (j0 >= a.n) return;
+__global__ __launch_bounds__(256, 4) void crt_reconstruct_kernel(RecArgs a) {
+  constexpr int G = (4 * W + 15) / 16;  // MFMAs (groups of 16 digit positions) per 16 outputs
+  constexpr int LS = 68;                // bytes per output in the residue tile (17 dwords: no bank conflicts)
+  static_assert(G <= kCrtFragGroups, "digit groups");
+  // the residue tile and the word sums share one buffer: every tile read
+  // is done (a barrier) before the first word sum is written
+  constexpr int SMEM = 256 * LS > 256 * W * 8 ? 256 * LS : 256 * W * 8;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
+  uint8_t* const tile = smem;
+  int64_t* const vs = reinterpret_cast<int64_t*>(smem);
   if (a.plan) {
     if (!a.plan->ok) return;
     a.N = a.plan->N;
     a.base = 4 - 16 * a.plan->S;
   }
   const CrtTable& t = *a.t;
-  int fj[4];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  v4i_t fa[G];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) fj[b] = j0 + b < a.n ? a.f[j0 + b] : 0;
+  for (int g = 0; g < G; ++g) fa[g] = *reinterpret_cast<const v4i_t*>(&t.frag[g][lane][0]);
+  const int nzg = (a.N + 3) / 4;
+  const int c = threadIdx.x % 64, zq = threadIdx.x / 64;
+  const int64_t jc = j0 + 4 * c;       // this thread's four columns in step 1
+  const int64_t jt = j0 + threadIdx.x;  // its output in step 3
+  const int fjt = jt < a.n ? a.f[jt] : 0;
+  // all of a thread's loads for a row (up to four groups of four moduli) go
+  // out together, and those of its next row while this one is computed
+  uint32_t d[4][4];
+  auto load_row = [&](int64_t i) {
+    const uint8_t* row = a.R + i * a.ldr + jc;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int zg = zq + 4 * it;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int z = 4 * zg + q;
+        d[it][q] = z < a.N && jc < a.ldr ? *reinterpret_cast<const uint32_t*>(row + (int64_t)z * a.planeR) : 0u;
+      }
+    }
+  };
+  if (blockIdx.y < a.m) load_row(blockIdx.y);
   for (int64_t i = blockIdx.y; i < a.m; i += gridDim.y) {
-    uint64_t acc[4][W];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int it = 0; it < 4; ++it) {
+      const int zg = zq + 4 * it;
+      if (zg >= nzg) break;
 #pragma unroll
-      for (int w = 0; w < W; ++w) acc[b][w] = 0;
-    const uint8_t* row = a.R + i * a.ldr + j0;
-    // the residues of eight moduli are loaded together, so a thread waits for
-    // one load latency per eight moduli instead of one per modulus
-    for (int z0 = 0; z0 < a.N; z0 += 8) {
-      uint32_t r4[8];
+      for (int b = 0; b < 4; ++b) {
+        uint32_t x = 0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        r4[u] = z0 + u < a.N ? *reinterpret_cast<const uint32_t*>(row + (int64_t)(z0 + u) * a.planeR) : 0u;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (z0 + u >= a.N) break;  // uniform
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          const uint32_t tw = t.T[z0 + u][w];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b][w] += (uint64_t)((r4[u] >> (8 * b)) & 0xffu) * tw;
-        }
+        for (int q = 0; q < 4; ++q) x |= ((d[it][q] >> (8 * b)) & 0xffu) << (8 * q);
+        *reinterpret_cast<uint32_t*>(tile + (4 * c + b) * LS + 4 * zg) = x ^ 0x80808080u;
       }
     }
-    const int ei = a.e[i];
+    __syncthreads();
+    if (i + gridDim.y < a.m) load_row(i + gridDim.y);
+    v4i_t fb[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      if (j0 + b < a.n) {
-        uint32_t y[W];
-        const bool neg = crt_magnitude<W>(acc[b], t, y);
-        const int64_t o = i * a.ldc + j0 + b;
-        if constexpr (!QD) {
-          double hi, lo;
-          crt_to_dd<W>(y, neg, ei + fj[b] + a.base, hi, lo);
-          a.C[0][o] = hi;
-          a.C[1][o] = lo;
-        } else {
-          double v[4], c[4] = {a.C[0][o], a.C[1][o], a.C[2][o], a.C[3][o]}, r[4];
-          crt_to_qd<W>(y, neg, ei + fj[b] + a.base, v);
-          qd_add(c, v, r);
+    for (int og = 0; og < 4; ++og) {
+      const int o = 64 * wave + 16 * og + lane % 16;
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(tile + o * LS + 16 * (lane / 16));
 #pragma unroll
-          for (int q = 0; q < 4; ++q) a.C[q][o] = r[q];
-        }
+      for (int q = 0; q < 4; ++q) fb[og][q] = (int)src[q];
+    }
+    __syncthreads();  // the tile is read; its bytes take the word sums
+#pragma unroll
+    for (int og = 0; og < 4; ++og) {
+      const int o = 64 * wave + 16 * og + lane % 16;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const v4i_t x = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[g], fb[og], v4i_t{0, 0, 0, 0}, 0, 0, 0);
+        const int wd = 4 * g + lane / 16;  // lane holds positions 4 wd .. 4 wd + 3 of output o
+        if (wd < W)
+          vs[o * W + wd] = (int64_t)x[0] + ((int64_t)x[1] << 8) + ((int64_t)x[2] << 16) + ((int64_t)x[3] << 24);
       }
     }
+    __syncthreads();
+    if (jt < a.n) {
+      uint64_t acc[W];
+      int64_t carry = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int64_t v = vs[threadIdx.x * W + w] + (int64_t)t.K0[w] + carry;
+        acc[w] = (uint64_t)(uint32_t)v;
+        carry = v >> 32;
+      }
+      uint32_t y[W];
+      const bool neg = crt_magnitude<W>(acc, t, y);
+      const int64_t o = i * a.ldc + jt;
+      if constexpr (!QD) {
+        double hi, lo;
+        crt_to_dd<W>(y, neg, a.e[i] + fjt + a.base, hi, lo);
+        a.C[0][o] = hi;
+        a.C[1][o] = lo;
+      } else {
+        double v[4], cq[4] = {a.C[0][o], a.C[1][o], a.C[2][o], a.C[3][o]}, r[4];
+        crt_to_qd<W>(y, neg, a.e[i] + fjt + a.base, v);
+        qd_add(cq, v, r);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a.C[q][o] = r[q];
+      }
+    }
+    __syncthreads();  // the tile and the word sums are refilled for the next row
   }
 }
 
@@ -338,8 +420,12 @@ hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR,
     a.C[2] = C[2];
     a.C[3] = C[3];
   }
-  const int64_t gx = ((n + 3) / 4 + 255) / 256;
-  const dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(m, 65535));
+  const int64_t gx = (n + 255) / 256;
+  if (gx > 0x7fffffff) return hipErrorInvalidValue;
+  // about 4096 workgroups, each walking several rows (its next row's loads
+  // overlap the current row's arithmetic)
+  const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(m, 65535), (4096 + gx - 1) / gx));
+  const dim3 grid((unsigned)gx, (unsigned)gy);
 #define MPG_CRT_REC(WW)                                                                        \
   case WW:                                                                                     \
     if (limbs == 2)                                                                            \

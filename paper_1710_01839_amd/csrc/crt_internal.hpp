@@ -26,12 +26,22 @@ constexpr int kCrtMaxSlices = 20;
 //   T[j] = (P / p_j) * ((P / p_j)^-1 mod p_j) (so X = sum_j r_j T[j] mod P),
 //   P = prod p_j, half = P / 2 (P is even: 256 is the first modulus),
 //   Pd = P rounded to a double.
+//   frag: the T[j] in signed radix-256 digits d_jb in [-128, 127]
+//   (T[j] = sum_b d_jb 256^b, positions below 4 kCrtMaxWords kept) in the
+//   lane order of the A operand of v_mfma_i32_16x16x64_i8, rows = digit
+//   positions, k = moduli: frag[g][l][k] = d_{16 (l / 16) + k, 16 g + l % 16}
+//   (0 for moduli j >= N);
+//   K0 = 128 sum_j T[j] in words (the offset that turns sums over r_j - 128
+//   back into sums over r_j).
+constexpr int kCrtFragGroups = 4 * kCrtMaxWords / 16;
 struct CrtTable {
   uint32_t T[kCrtMaxModuli][kCrtMaxWords];
   uint32_t P[kCrtMaxWords];
   uint32_t half[kCrtMaxWords];
   double Pd;
   int N;
+  uint32_t K0[kCrtMaxWords];
+  alignas(16) int8_t frag[kCrtFragGroups][64][16];
 };
 
 // Slice and moduli counts of a residue-form product decided on the device
