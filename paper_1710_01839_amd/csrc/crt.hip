@@ -45,9 +45,11 @@ __global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t, const
     N = plan->N;
   }
   const int j = threadIdx.x;
+  __shared__ uint32_t Ms[64][kCrtMaxWords];
+  __shared__ uint64_t colsum[kCrtMaxWords];
+  uint32_t M[kCrtMaxWords] = {1};
   if (j < N) {
     const int pj = kCrtModuli[j];
-    uint32_t M[kCrtMaxWords] = {1};
     int mmod = 1;
     for (int i = 0; i < N; ++i)
       if (i != j) {
@@ -55,28 +57,38 @@ __global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t, const
         mmod = (int)((int64_t)mmod * (kCrtModuli[i] % pj) % pj);
       }
     mul_small(M, (uint32_t)inverse_mod(mmod, pj));
-    for (int w = 0; w < kCrtMaxWords; ++w) t->T[j][w] = M[w];
+  } else {
+    M[0] = 0;
+  }
+  for (int w = 0; w < kCrtMaxWords; ++w) {
+    if (j < N) t->T[j][w] = M[w];
+    Ms[j][w] = M[w];
   }
   // signed radix-256 digits of T[j] into the MFMA fragment table (zeros for
   // the moduli past N, up to the 64 the K range of one product holds)
   {
     int carry = 0;
     for (int b = 0; b < 4 * kCrtMaxWords; ++b) {
-      int v = carry;
-      if (j < N) v += (int)((t->T[j][b / 4] >> (8 * (b % 4))) & 0xffu);
+      const int v = carry + (int)((M[b / 4] >> (8 * (b % 4))) & 0xffu);
       carry = v >= 128 ? 1 : 0;
       t->frag[b / 16][16 * (j / 16) + b % 16][j % 16] = (int8_t)(v - 256 * carry);
     }
   }
-  __syncthreads();  // every T[j] written before thread 0 sums them
+  __syncthreads();
+  // K0 = 128 sum_j T[j]: per-word sums (below 2^45) by one thread per word,
+  // then one carry pass
+  if (j < kCrtMaxWords) {
+    uint64_t sw = 0;
+    for (int i = 0; i < N; ++i) sw += Ms[i][j];
+    colsum[j] = sw << 7;
+  }
+  __syncthreads();
   if (j == 0) {
-    // K0 = 128 sum_j T[j]: per-word sums below 2^45, then one carry pass
     uint64_t c = 0;
     for (int w = 0; w < kCrtMaxWords; ++w) {
-      uint64_t s = c;
-      for (int i = 0; i < N; ++i) s += (uint64_t)t->T[i][w] << 7;
-      t->K0[w] = (uint32_t)s;
-      c = s >> 32;
+      const uint64_t sw = colsum[w] + c;
+      t->K0[w] = (uint32_t)sw;
+      c = sw >> 32;
     }
   }
   if (j == 0) {
