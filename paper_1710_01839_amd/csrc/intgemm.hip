@@ -125,34 +125,50 @@ __global__ __launch_bounds__(256) void int_accumulate_kernel(IntAccumArgs a) {
 #pragma unroll
       for (int w = 0; w < W; ++w) acc[b][w] = 0;
     const uint8_t* row = a.R + i * a.ldr + j0;
-    for (int z = 0; z < a.N; ++z) {
-      uint32_t r4;
-      if (a.nterms == 1 && a.term_sign[0] == 1) {
-        r4 = *reinterpret_cast<const uint32_t*>(row + a.term_off[0] + (int64_t)z * a.planeR);
+    const bool plain = a.nterms == 1 && a.term_sign[0] == 1;  // uniform
+    // eight moduli at a time: their loads go out together (one load latency
+    // per eight moduli instead of one per modulus)
+    for (int z0 = 0; z0 < a.N; z0 += 8) {
+      uint32_t r4[8];
+      if (plain) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          r4[u] = z0 + u < a.N
+                      ? *reinterpret_cast<const uint32_t*>(row + a.term_off[0] + (int64_t)(z0 + u) * a.planeR)
+                      : 0u;
       } else {
-        const int p = kCrtModuli[z];
-        const float inv_pf = 1.0f / (float)p;
-        int sum[4] = {0, 0, 0, 0};
-        for (int q = 0; q < a.nterms; ++q) {
-          const uint32_t v = *reinterpret_cast<const uint32_t*>(row + a.term_off[q] + (int64_t)z * a.planeR);
 #pragma unroll
-          for (int b = 0; b < 4; ++b) sum[b] += a.term_sign[q] * (int)((v >> (8 * b)) & 0xffu);
-        }
-        r4 = 0;
+        for (int u = 0; u < 8; ++u) {
+          r4[u] = 0;
+          const int z = z0 + u;
+          if (z >= a.N) continue;
+          const int p = kCrtModuli[z];
+          const float inv_pf = 1.0f / (float)p;
+          int sum[4] = {0, 0, 0, 0};
+          for (int q = 0; q < a.nterms; ++q) {
+            const uint32_t v = *reinterpret_cast<const uint32_t*>(row + a.term_off[q] + (int64_t)z * a.planeR);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int qq = (int)floorf((float)sum[b] * inv_pf);
-          int r = sum[b] - qq * p;
-          if (r < 0) r += p;
-          if (r >= p) r -= p;
-          r4 |= (uint32_t)r << (8 * b);
+            for (int b = 0; b < 4; ++b) sum[b] += a.term_sign[q] * (int)((v >> (8 * b)) & 0xffu);
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int qq = (int)floorf((float)sum[b] * inv_pf);
+            int r = sum[b] - qq * p;
+            if (r < 0) r += p;
+            if (r >= p) r -= p;
+            r4[u] |= (uint32_t)r << (8 * b);
+          }
         }
       }
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const uint32_t tw = t.T[z][w];
+      for (int u = 0; u < 8; ++u) {
+        if (z0 + u >= a.N) break;  // uniform
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[b][w] += (uint64_t)((r4 >> (8 * b)) & 0xffu) * tw;
+        for (int w = 0; w < W; ++w) {
+          const uint32_t tw = t.T[z0 + u][w];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[b][w] += (uint64_t)((r4[u] >> (8 * b)) & 0xffu) * tw;
+        }
       }
     }
 #pragma unroll
