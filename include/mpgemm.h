@@ -53,17 +53,19 @@ typedef enum {
 typedef enum {
   MPG_AUTO = 0,     /* use the context's tuning table, else a default; a tabled split
                        product the data's exact slice count rules out falls back to
-                       MPG_BLOCK of the same precision.  A tabled DD residue form
-                       (MPG_OZAKI_CRT, slices 0) stays asynchronous: the slice and
-                       moduli counts are decided on the device, the residue-form
+                       MPG_BLOCK of the same precision.  A tabled DD or QD residue
+                       form (MPG_OZAKI_CRT, slices 0) stays asynchronous: the slice
+                       and moduli counts (for QD also the part products with an
+                       all-zero part) are decided on the device, the residue-form
                        kernels are launched for the most moduli 20 slices need and
                        take the device's counts, and the block kernel launched after
                        them runs only when more than 20 slices are needed; after one
                        eager call of a shape (which grows the workspace) the call
                        allocates nothing and can be captured in a HIP graph, whose
-                       replays decide again from the data.  The tabled digit form
-                       (MPG_OZAKI, slices 0) and the QD residue form read the counts
-                       back (one stream synchronisation). */
+                       replays decide again from the data (mpg_ozaki_last_slices and
+                       mpg_ozaki_last_moduli then read 0).  The tabled digit form
+                       (MPG_OZAKI, slices 0) reads its count back (one stream
+                       synchronisation). */
   MPG_SIMPLE = 1,   /* Eq. (1): one thread per c_ij, k in order */
   MPG_BLOCK = 2,    /* Eq. (2): LDS-staged tiles, register-blocked accumulators */
   MPG_STRASSEN = 3, /* Eq. (3), Winograd's form, `depth` levels over MPG_BLOCK */

@@ -570,11 +570,12 @@ int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
       algo = MPG_BLOCK;
     }
   }
-  if (from_table && algo == MPG_OZAKI_CRT && limbs == 2 && chosen.slices == 0) {
+  if (from_table && algo == MPG_OZAKI_CRT && chosen.slices == 0) {
     // the tabled residue form with the exact slice count, decided on the
-    // device (no read-back): see mpg_dd_crt_auto
+    // device (no read-back): see mpg_dd_crt_auto / mpg_qd_crt_auto
     bool used = false;
-    st = mpg_dd_crt_auto(c, m, n, l, A[0], A[1], lda, B[0], B[1], ldb, C[0], C[1], ldc, &used);
+    st = limbs == 2 ? mpg_dd_crt_auto(c, m, n, l, A[0], A[1], lda, B[0], B[1], ldb, C[0], C[1], ldc, &used)
+                    : mpg_qd_crt_auto(c, m, n, l, A, lda, B, ldb, C, ldc, &used);
     if (st != MPG_OK || used) return st;
     algo = MPG_BLOCK;
     chosen = mpg_tile{};

@@ -98,6 +98,9 @@ int mpg_dd_crt_auto(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A
 // Quad-double product through the residue form (C := A B, four limbs).
 int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const* A, int64_t lda,
                const double* const* B, int64_t ldb, double* const* C, int64_t ldc);
+// MPG_AUTO's asynchronous quad-double residue form; *used as for DD.
+int mpg_qd_crt_auto(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const* A, int64_t lda,
+                    const double* const* B, int64_t ldb, double* const* C, int64_t ldc, bool* used);
 int mpg_gemm_common(mpg_ctx* c, int limbs, int64_t m, int64_t n, int64_t l,
                     const double* const* A, int64_t lda, const double* const* B, int64_t ldb,
                     double* const* C, int64_t ldc, mpg_algo algo, const mpg_tile* tile);

@@ -190,6 +190,7 @@ struct RecArgs {
   double* C[4];
   int64_t ldc;
   const CrtPlan* plan;  // when set: N and S from it
+  int product;          // >= 0: nothing when plan->skip[product] is set
 };
 
 typedef int v4i_t __attribute__((ext_vector_type(4)));
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256, 4) void crt_reconstruct_kernel(RecArgs a) {
   uint8_t* const tile = smem;
   int64_t* const vs = reinterpret_cast<int64_t*>(smem);
   if (a.plan) {
-    if (!a.plan->ok) return;
+    if (!a.plan->ok || (a.product >= 0 && a.plan->skip[a.product])) return;
     a.N = a.plan->N;
     a.base = 4 - 16 * a.plan->S;
   }
@@ -323,6 +324,31 @@ __global__ void crt_plan_kernel(const int* need, CrtModuliTable t, CrtPlan* plan
   plan->S = S;
   plan->N = N;
   plan->ok = N > 0 ? 1 : 0;
+  for (int k = 0; k < 3; ++k) plan->skip[k] = 0;
+  for (int p = 0; p < 4; ++p) plan->unused[p] = 0;
+}
+
+// Products of the quad-double form: k = 0: A_H B_H, 1: A_H B_L, 2: A_L B_H;
+// one slice count, the largest exact count of the parts taking part.
+__global__ void crt_plan_qd_kernel(const int* need, CrtModuliTable t, CrtPlan* plan) {
+  if (threadIdx.x != 0) return;
+  const int pa[3] = {0, 0, 1}, pb[3] = {2, 3, 2};
+  int S = 0;
+  int used[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 3; ++k) {
+    const bool zero = need[pa[k]] == 0 || need[pb[k]] == 0;
+    plan->skip[k] = zero ? 1 : 0;
+    if (!zero) {
+      S = max(S, max(need[pa[k]], need[pb[k]]));
+      used[pa[k]] = used[pb[k]] = 1;
+    }
+  }
+  for (int p = 0; p < 4; ++p) plan->unused[p] = used[p] ? 0 : 1;
+  // nothing to multiply (C stays zero) counts as a plan that fits
+  const int N = S == 0 ? 1 : S <= kCrtMaxSlices ? t.N[S] : 0;
+  plan->S = max(S, 1);
+  plan->N = N;
+  plan->ok = N > 0 ? 1 : 0;
 }
 
 __global__ void residue_consts_kernel(int N, int S, CrtResidueConsts* rc, const CrtPlan* plan) {
@@ -414,6 +440,11 @@ hipError_t launch_crt_plan(const int* need, const CrtModuliTable& t, CrtPlan* pl
   return hipGetLastError();
 }
 
+hipError_t launch_crt_plan_qd(const int* need, const CrtModuliTable& t, CrtPlan* plan, hipStream_t s) {
+  hipLaunchKernelGGL(crt_plan_qd_kernel, dim3(1), dim3(64), 0, s, need, t, plan);
+  return hipGetLastError();
+}
+
 hipError_t launch_crt_residue_consts(int N, int S, CrtResidueConsts* rc, hipStream_t s,
                                      const CrtPlan* plan) {
   if (N < 1 || N > kCrtMaxModuli || S < 1 || S > kCrtMaxSlices) return hipErrorInvalidValue;
@@ -424,10 +455,10 @@ hipError_t launch_crt_residue_consts(int N, int S, CrtResidueConsts* rc, hipStre
 hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR, int N,
                                   const CrtTable* t, const int* e, const int* f, int S, int64_t m,
                                   int64_t n, double* const* C, int limbs, int64_t ldc, hipStream_t s,
-                                  const CrtPlan* plan) {
+                                  const CrtPlan* plan, int product) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (ldr % 4 || ldr < n || (limbs != 2 && limbs != 4)) return hipErrorInvalidValue;
-  RecArgs a{R, ldr, planeR, N, t, e, f, 4 - 16 * S, m, n, {C[0], C[1], nullptr, nullptr}, ldc, plan};
+  RecArgs a{R, ldr, planeR, N, t, e, f, 4 - 16 * S, m, n, {C[0], C[1], nullptr, nullptr}, ldc, plan, product};
   if (limbs == 4) {
     a.C[2] = C[2];
     a.C[3] = C[3];

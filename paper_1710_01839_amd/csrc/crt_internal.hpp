@@ -47,15 +47,24 @@ struct CrtTable {
 // Slice and moduli counts of a residue-form product decided on the device
 // (from the exponent scan's exact slice count), so that the host need not
 // read them back: every kernel given a plan takes S and N from it, and
-// none does anything when ok is 0 (more than kCrtMaxSlices slices).
+// none does anything when ok is 0 (more than kCrtMaxSlices slices).  For
+// the quad-double form (three products of double-double parts) skip[k]
+// marks a product with an all-zero part and unused[p] a part (A_H, A_L, B_H,
+// B_L) no remaining product takes; a kernel given its index does nothing
+// then.
 struct CrtPlan {
   int S, N, ok;
+  int skip[3];
+  int unused[4];
 };
 // Moduli for 1..kCrtMaxSlices slices at one l (index S; 0: does not fit).
 struct CrtModuliTable {
   int N[kCrtMaxSlices + 1];
 };
 hipError_t launch_crt_plan(const int* need, const CrtModuliTable& t, CrtPlan* plan, hipStream_t s);
+// The quad-double plan from the four parts' exact slice counts
+// (need[0..3]: A_H, A_L, B_H, B_L; 0 = an all-zero part).
+hipError_t launch_crt_plan_qd(const int* need, const CrtModuliTable& t, CrtPlan* plan, hipStream_t s);
 
 // One INT8 product per modulus: residue planes z of A ([N] planes of
 // m_pad x l_pad) and of B ([N] planes of n_pad x l_pad, the columns of B as
@@ -78,6 +87,7 @@ struct CrtGemmArgs {
   int nseg;
   int64_t segA[kCrtMaxSegments], segB[kCrtMaxSegments];
   const CrtPlan* plan;  // when set: moduli z >= plan->N do nothing
+  int product;          // >= 0: nothing when plan->skip[product] is set
 };
 
 // Bits the integer product can need: |(A' B')_ij| < l 2^(16 S - 4), and the
@@ -233,14 +243,17 @@ __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImag
 // (r < Rp, k < Kp, zeros in the padding).
 // plan (nullable): S and N from the plan (nothing when it is not ok; the
 // planes must hold the N given here, at least the plan's).
+// part >= 0 (with a plan): nothing when plan->unused[part] is set.
 hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
-                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan = nullptr);
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan = nullptr,
+                           int part = -1);
 // The same for the columns of X (K x R row-major, leading dimension ld):
 // plane row r is column r of X (B's columns, read in place).
 hipError_t launch_crt_cols(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
-                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan = nullptr);
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan = nullptr,
+                           int part = -1);
 
 // Workgroup tile of the residue products: A's planes need rows padded to
 // crt_tile_rows(), B's to crt_tile_cols(), K to crt_k_multiple().
@@ -253,9 +266,10 @@ hipError_t launch_crt_gemm(const CrtGemmArgs& a, hipStream_t s);
 // limbs) := C + V in quad-double.
 // plan (nullable): N and S from the plan (nothing when it is not ok; the
 // word count is that of the N given here, at least the plan's).
+// product >= 0 (with a plan): nothing when plan->skip[product] is set.
 hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR, int N,
                                   const CrtTable* t, const int* e, const int* f, int S, int64_t m,
                                   int64_t n, double* const* C, int limbs, int64_t ldc, hipStream_t s,
-                                  const CrtPlan* plan = nullptr);
+                                  const CrtPlan* plan = nullptr, int product = -1);
 
 }  // namespace mpg

@@ -293,6 +293,7 @@ int mpg_int_run(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const uint32_t* A, 
     const Leaf& lf = P.leaves[P.leafdiags[ld].first];
     const int g = P.leafdiags[ld].second;
     CrtGemmArgs ga{};
+    ga.product = -1;
     ga.m = m;
     ga.n = n;
     ga.l_pad = lp;

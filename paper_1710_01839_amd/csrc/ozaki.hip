@@ -291,9 +291,9 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
                                                        int64_t K, int64_t ld, const int* e, int S, int N,
                                                        int8_t* __restrict__ out, int64_t Rp, int64_t Kp,
                                                        const CrtResidueConsts* __restrict__ rc,
-                                                       const CrtPlan* plan) {
+                                                       const CrtPlan* plan, int part) {
   if (plan) {
-    if (!plan->ok) return;
+    if (!plan->ok || (part >= 0 && plan->unused[part])) return;
     S = plan->S;
     N = plan->N;
   }
@@ -1088,7 +1088,8 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
     tm = first + in % gsize;
     tn = in / gsize;
   }
-  if (c.plan && z >= c.plan->N) return;  // a modulus the device-side plan does not use
+  // a modulus or a product the device-side plan does not use
+  if (c.plan && (z >= c.plan->N || (c.product >= 0 && c.plan->skip[c.product]))) return;
   const int p = c.mods[z];
   const int c16 = 65536 % p;
   const float inv_pf = 1.0f / (float)p;
@@ -1350,7 +1351,7 @@ namespace {
 template <bool COLS>
 hipError_t launch_crt_planes(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                              const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
-                             const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan) {
+                             const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan, int part) {
   // the tiled plane layout (crt_plane_offset) needs whole 16-row x 64-k blocks
   if (S < 1 || S > kCrtMaxSlices || N < 1 || N > kCrtMaxModuli || Kp % 64 || Rp % 16)
     return hipErrorInvalidValue;
@@ -1360,24 +1361,24 @@ hipError_t launch_crt_planes(const double* X, const double* Xlo, int64_t R, int6
   const dim3 grid((unsigned)((work + 255) / 256));
   if (Xlo)
     hipLaunchKernelGGL((crt_rows_kernel<true, COLS>), grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out,
-                       Rp, Kp, rc, plan);
+                       Rp, Kp, rc, plan, part);
   else
     hipLaunchKernelGGL((crt_rows_kernel<false, COLS>), grid, dim3(256), 0, s, X, Xlo, R, K, ld, e, S, N, out,
-                       Rp, Kp, rc, plan);
+                       Rp, Kp, rc, plan, part);
   return hipGetLastError();
 }
 }  // namespace
 
 hipError_t launch_crt_rows(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
-                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan) {
-  return launch_crt_planes<false>(X, Xlo, R, K, ld, e, S, N, out, Rp, Kp, rc, s, plan);
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan, int part) {
+  return launch_crt_planes<false>(X, Xlo, R, K, ld, e, S, N, out, Rp, Kp, rc, s, plan, part);
 }
 
 hipError_t launch_crt_cols(const double* X, const double* Xlo, int64_t R, int64_t K, int64_t ld,
                            const int* e, int S, int N, int8_t* out, int64_t Rp, int64_t Kp,
-                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan) {
-  return launch_crt_planes<true>(X, Xlo, R, K, ld, e, S, N, out, Rp, Kp, rc, s, plan);
+                           const CrtResidueConsts* rc, hipStream_t s, const CrtPlan* plan, int part) {
+  return launch_crt_planes<true>(X, Xlo, R, K, ld, e, S, N, out, Rp, Kp, rc, s, plan, part);
 }
 
 int crt_tile_rows() { return kCrtBM; }

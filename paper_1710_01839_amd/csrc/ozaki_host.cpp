@@ -167,6 +167,7 @@ int crt_product(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A, co
   g.planeR = m * n4;
   g.N = N;
   g.plan = plan;
+  g.product = -1;
   for (int j = 0; j < N; ++j) g.mods[j] = kCrtModuli[j];
   st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_crt_gemm(g, c->stream); },
                   "INT8 MFMA residue products");
@@ -469,6 +470,7 @@ int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const*
     g.ldr = n4;
     g.planeR = m * n4;
     g.N = N;
+    g.product = -1;
     for (int j = 0; j < N; ++j) g.mods[j] = kCrtModuli[j];
     if ((st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_crt_gemm(g, c->stream); },
                          "INT8 MFMA residue products")) != MPG_OK)
@@ -484,6 +486,129 @@ int mpg_qd_crt(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const*
   for (int k = 0; k < 3; ++k) moduli += S[k] > 0 ? N : 0;
   c->last_slices = slices;
   c->last_moduli = moduli;
+  return MPG_OK;
+}
+
+// MPG_AUTO's quad-double residue form without a read-back: the four parts'
+// slice counts become a device-side plan (one slice count, the products
+// with an all-zero part and the parts no product takes), the residue-form
+// kernels are launched for the most moduli 20 slices need and take the
+// plan's counts and gates, and the quad-double block kernel launched after
+// them runs only when more than 20 slices are needed (C is zeroed first, so
+// either path leaves the product in C).
+int mpg_qd_crt_auto(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* const* A, int64_t lda,
+                    const double* const* B, int64_t ldb, double* const* C, int64_t ldc, bool* used) {
+  *used = false;
+  const int Smax = kCrtMaxSlices;
+  const int Nmax = crt_moduli_for_bits(crt_product_bits(Smax, l));
+  if (Nmax == 0 || crt_words(Nmax) == 0) return MPG_OK;  // the caller runs the block kernel
+  CrtModuliTable tab{};
+  for (int S = 1; S <= Smax; ++S) {
+    const int N = crt_moduli_for_bits(crt_product_bits(S, l));
+    tab.N[S] = N > 0 && crt_words(N) > 0 ? N : 0;
+  }
+  const int64_t mp = round_up(std::max<int64_t>(m, 1), 64), np = round_up(std::max<int64_t>(n, 1), 64);
+  void* small = nullptr;
+  int st = mpg_workspace(c, 1, (size_t)(2 * mp + 3 * np + 64) * sizeof(int), &small);
+  if (st != MPG_OK) return st;
+  int* eH = (int*)small;
+  int* eL = eH + mp;
+  int* fH = eL + mp;
+  int* fL = fH + np;
+  int* low = fL + np;
+  int* cnt = low + np;  // digits needed by A_H, A_L, B_H, B_L
+  CrtPlan* plan = reinterpret_cast<CrtPlan*>(cnt + 16);  // inside the slot's 64-int tail
+  st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, c->stream, cnt, 4);
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    if ((r = launch_ozaki_scan(A[0], A[1], m, l, lda, 0, eH, nullptr, cnt + 0, c->stream)) != hipSuccess) return r;
+    if ((r = launch_ozaki_scan(A[2], A[3], m, l, lda, 0, eL, nullptr, cnt + 1, c->stream)) != hipSuccess) return r;
+    if ((r = launch_ozaki_scan(B[0], B[1], l, n, ldb, 1, fH, low, cnt + 2, c->stream)) != hipSuccess) return r;
+    if ((r = launch_ozaki_scan(B[2], B[3], l, n, ldb, 1, fL, low, cnt + 3, c->stream)) != hipSuccess) return r;
+    if ((r = launch_crt_plan_qd(cnt, tab, plan, c->stream)) != hipSuccess) return r;
+    return launch_zero(C, 4, m, n, ldc, c->stream);
+  }, "exponent scans and residue-form plan");
+  if (st != MPG_OK) return st;
+  const int N = Nmax;
+  const int64_t lp = round_up(l, crt_k_multiple()), mpad = round_up(m, crt_tile_rows()),
+                npad = round_up(n, crt_tile_cols()), n4 = round_up(n, 4);
+  const int64_t planeA = mpad * lp, planeB = npad * lp;
+  const size_t cb = (sizeof(CrtResidueConsts) + 255) / 256 * 256;
+  void *res = nullptr, *out = nullptr;
+  if ((st = mpg_workspace(c, 7, (size_t)N * (size_t)(2 * planeA + 2 * planeB) + cb, &res)) != MPG_OK ||
+      (st = mpg_workspace(c, 8, (size_t)N * (size_t)(m * n4) + 256 + sizeof(CrtTable), &out)) != MPG_OK)
+    return st;
+  int8_t* Ares[2] = {(int8_t*)res, (int8_t*)res + (size_t)N * planeA};
+  int8_t* Bres[2] = {Ares[1] + (size_t)N * planeA, Ares[1] + (size_t)N * (planeA + planeB)};
+  CrtResidueConsts* consts = (CrtResidueConsts*)(Bres[1] + (size_t)N * planeB);
+  uint8_t* R = (uint8_t*)out;
+  CrtTable* table = (CrtTable*)((char*)out + ((size_t)N * (size_t)(m * n4) + 255) / 256 * 256);
+  st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+    hipError_t r = launch_crt_table(N, table, c->stream, plan);
+    if (r != hipSuccess) return r;
+    if ((r = launch_crt_residue_consts(N, Smax, consts, c->stream, plan)) != hipSuccess) return r;
+    for (int pa = 0; pa < 2; ++pa)
+      if ((r = launch_crt_rows(A[2 * pa], A[2 * pa + 1], m, l, lda, pa ? eL : eH, Smax, N, Ares[pa], mpad, lp,
+                               consts, c->stream, plan, pa)) != hipSuccess)
+        return r;
+    for (int pb = 0; pb < 2; ++pb)
+      if ((r = launch_crt_cols(B[2 * pb], B[2 * pb + 1], n, l, ldb, pb ? fL : fH, Smax, N, Bres[pb], npad, lp,
+                               consts, c->stream, plan, 2 + pb)) != hipSuccess)
+        return r;
+    return hipSuccess;
+  }, "residue planes");
+  if (st != MPG_OK) return st;
+  const int pa_of[3] = {0, 0, 1}, pb_of[3] = {0, 1, 0};
+  for (int k = 0; k < 3; ++k) {
+    const int pa = pa_of[k], pb = pb_of[k];
+    CrtGemmArgs g{};
+    g.m = m;
+    g.n = n;
+    g.l_pad = lp;
+    g.A = Ares[pa];
+    g.B = Bres[pb];
+    g.planeA = planeA;
+    g.planeB = planeB;
+    g.R = R;
+    g.ldr = n4;
+    g.planeR = m * n4;
+    g.N = N;
+    g.plan = plan;
+    g.product = k;
+    for (int j = 0; j < N; ++j) g.mods[j] = kCrtModuli[j];
+    if ((st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_crt_gemm(g, c->stream); },
+                         "INT8 MFMA residue products")) != MPG_OK)
+      return st;
+    if ((st = mpg_launch(c, MPG_KCLASS_AUX, [&] {
+           return launch_crt_reconstruct(R, n4, m * n4, N, table, pa ? eL : eH, pb ? fL : fH, Smax, m, n, C, 4,
+                                         ldc, c->stream, plan, k);
+         }, "residue reconstruction")) != MPG_OK)
+      return st;
+  }
+  // the fallback, run only when the plan says the residue form does not fit
+  int variant = 0;
+  if ((st = mpg_resolve_variant(c, 4, nullptr, &variant)) != MPG_OK) return st;
+  GemmBatch g{};
+  g.m = m;
+  g.n = n;
+  g.l = l;
+  for (int q = 0; q < 4; ++q) {
+    g.A[q] = A[q];
+    g.B[q] = B[q];
+    g.C[q] = C[q];
+  }
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.count = 1;
+  g.skip = &plan->ok;
+  if ((st = mpg_launch(c, MPG_KCLASS_GEMM, [&] { return launch_qd_block(variant, g, c->stream); },
+                       "block kernel (fallback)")) != MPG_OK)
+    return st;
+  c->last_slices = 0;
+  c->last_moduli = 0;
+  *used = true;
   return MPG_OK;
 }
 

@@ -338,3 +338,65 @@ def test_auto_residue_form_async_and_captured(gpu):
     torch.cuda.synchronize()
     assert torch.equal(Cg[0], C_blk[0]) and torch.equal(Cg[1], C_blk[1])
     del graph
+
+
+def test_qd_auto_residue_form_async_and_captured(gpu):
+    """MPG_AUTO with a tabled quad-double residue form decides the slice
+    count, the products with an all-zero part and the fallback on the
+    device: its result equals the explicit call's bit for bit, the call is
+    captured in a HIP graph and replayed, and the same graph then takes
+    double-double data carried as quad-double (one product), an all-zero A
+    (C = 0) and data needing more than 20 slices (the quad-double block
+    kernel), each equal to the explicit call of that case."""
+    M, ctx = gpu
+    T = M.Tuner(ctx)
+    nn = 384
+    A, B = inputs.qd_uniform(nn, nn, 190), inputs.qd_uniform(nn, nn, 191)
+    Ad, Bd = M.to_device(A), M.to_device(B)
+    T.table_set("qd", nn, nn, nn, "ozaki_crt", {"slices": 0})
+
+    def explicit(algo):
+        C = M.empty_like_limbs(nn, nn, 4)
+        M.mpgemm_qd(ctx, Ad, Bd, C, algo=algo)
+        torch.cuda.synchronize()
+        return C
+
+    def same(X, Y):
+        return all(torch.equal(x, y) for x, y in zip(X, Y))
+
+    C_auto = M.empty_like_limbs(nn, nn, 4)
+    M.mpgemm_qd(ctx, Ad, Bd, C_auto, algo="auto")      # eager: grows the workspace
+    torch.cuda.synchronize()
+    assert same(C_auto, explicit("ozaki_crt"))
+    Cg = M.empty_like_limbs(nn, nn, 4)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        M.mpgemm_qd(ctx, Ad, Bd, Cg, algo="auto")
+
+    def replay_equals(want):
+        for _ in range(2):
+            for p in Cg:
+                p.fill_(float("nan"))
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert same(Cg, want)
+
+    replay_equals(explicit("ozaki_crt"))
+    # double-double data carried as quad-double: the trailing parts are zero
+    for q in (2, 3):
+        Ad[q].zero_()
+        Bd[q].zero_()
+    replay_equals(explicit("ozaki_crt"))
+    # an all-zero A: nothing to multiply
+    for q in range(4):
+        Ad[q].zero_()
+    replay_equals(explicit("ozaki_crt"))
+    # data whose exact split needs more than 20 slices: the block kernel
+    for q in range(4):
+        Ad[q].copy_(torch.from_numpy(A[q]))
+    Ad[0][:, 3] = 2.0 ** -230
+    for q in (1, 2, 3):
+        Ad[q][:, 3] = 0.0
+    replay_equals(explicit("block"))
+    del graph
