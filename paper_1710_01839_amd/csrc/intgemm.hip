@@ -113,81 +113,125 @@ __global__ __launch_bounds__(256) void int_residue_kernel(IntResidueArgs a) {
 // (each in [0, p_z)), brought back into [0, p_z): the sum is below
 // 64 x 256 in magnitude, so its FP32 quotient by p_z is within 2^-8 of the
 // exact one and one correction each way suffices.
+//
+// X' = sum_z r_z T_z is formed on INT8 MFMA as in the residue form's
+// reconstruction: a workgroup stages the residues of 256 outputs of a row
+// as signed bytes r_z - 128 in LDS (four moduli x four columns per thread,
+// transposed in registers), one MFMA per 16 digit positions of the T_z
+// (signed radix-256 digits from the table) and 16 outputs gives the
+// position sums, each word's four positions combine into a 64-bit sum, and
+// a thread per output adds 128 sum_z T_z with a signed carry pass (X' is
+// below 2^(32 W)); a workgroup walks several rows.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
 template <int W>
 __global__ __launch_bounds__(256) void int_accumulate_kernel(IntAccumArgs a) {
-  const int64_t j0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
-  if (j0 >= a.n) return;
+  constexpr int G = (4 * W + 15) / 16;
+  constexpr int LS = 68;  // bytes per output in the residue tile (17 dwords: no bank conflicts)
+  static_assert(G <= kCrtFragGroups, "digit groups");
+  constexpr int SMEM = 256 * LS > 256 * W * 8 ? 256 * LS : 256 * W * 8;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
+  uint8_t* const tile = smem;
+  int64_t* const vs = reinterpret_cast<int64_t*>(smem);
   const CrtTable& t = *a.t;
-  for (int64_t i = blockIdx.y; i < a.m; i += gridDim.y) {
-    uint64_t acc[4][W];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  v4i_t fa[G];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+  for (int g = 0; g < G; ++g) fa[g] = *reinterpret_cast<const v4i_t*>(&t.frag[g][lane][0]);
+  const int nzg = (a.N + 3) / 4;
+  const int c = threadIdx.x % 64, zq = threadIdx.x / 64;
+  const int64_t jc = j0 + 4 * c;        // this thread's four columns when staging
+  const int64_t jt = j0 + threadIdx.x;  // its output in the tail
+  const bool plain = a.nterms == 1 && a.term_sign[0] == 1;  // uniform
+  // residues of four consecutive columns for modulus z (0 past the planes)
+  auto residues4 = [&](const uint8_t* row, int z) -> uint32_t {
+    if (z >= a.N || jc >= a.ldr) return 0u;
+    if (plain) return *reinterpret_cast<const uint32_t*>(row + a.term_off[0] + (int64_t)z * a.planeR);
+    const int p = kCrtModuli[z];
+    const float inv_pf = 1.0f / (float)p;
+    int sum[4] = {0, 0, 0, 0};
+    for (int q = 0; q < a.nterms; ++q) {
+      const uint32_t v = *reinterpret_cast<const uint32_t*>(row + a.term_off[q] + (int64_t)z * a.planeR);
 #pragma unroll
-      for (int w = 0; w < W; ++w) acc[b][w] = 0;
-    const uint8_t* row = a.R + i * a.ldr + j0;
-    const bool plain = a.nterms == 1 && a.term_sign[0] == 1;  // uniform
-    // eight moduli at a time: their loads go out together (one load latency
-    // per eight moduli instead of one per modulus)
-    for (int z0 = 0; z0 < a.N; z0 += 8) {
-      uint32_t r4[8];
-      if (plain) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          r4[u] = z0 + u < a.N
-                      ? *reinterpret_cast<const uint32_t*>(row + a.term_off[0] + (int64_t)(z0 + u) * a.planeR)
-                      : 0u;
-      } else {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          r4[u] = 0;
-          const int z = z0 + u;
-          if (z >= a.N) continue;
-          const int p = kCrtModuli[z];
-          const float inv_pf = 1.0f / (float)p;
-          int sum[4] = {0, 0, 0, 0};
-          for (int q = 0; q < a.nterms; ++q) {
-            const uint32_t v = *reinterpret_cast<const uint32_t*>(row + a.term_off[q] + (int64_t)z * a.planeR);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) sum[b] += a.term_sign[q] * (int)((v >> (8 * b)) & 0xffu);
-          }
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int qq = (int)floorf((float)sum[b] * inv_pf);
-            int r = sum[b] - qq * p;
-            if (r < 0) r += p;
-            if (r >= p) r -= p;
-            r4[u] |= (uint32_t)r << (8 * b);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (z0 + u >= a.N) break;  // uniform
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          const uint32_t tw = t.T[z0 + u][w];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b][w] += (uint64_t)((r4[u] >> (8 * b)) & 0xffu) * tw;
-        }
-      }
+      for (int b = 0; b < 4; ++b) sum[b] += a.term_sign[q] * (int)((v >> (8 * b)) & 0xffu);
     }
+    uint32_t r4 = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      if (j0 + b >= a.n) continue;
-      uint32_t y[W];
-      const bool neg = crt_magnitude<W>(acc[b], t, y);
-      uint32_t* cw = a.C + i * a.ldc + j0 + b;
-      // C += (neg ? -Y : Y) at word_off, in two's complement over words_c words
-      int64_t carry = 0;
-      for (int w = a.word_off; w < a.words_c; ++w) {
-        const int64_t yw = w - a.word_off < W ? (int64_t)y[w - a.word_off] : 0;
-        if (yw == 0 && carry == 0 && w - a.word_off >= W) break;
-        const int64_t cur = (int64_t)cw[(int64_t)w * a.pstride];
-        const int64_t s = neg ? cur - yw + carry : cur + yw + carry;
-        cw[(int64_t)w * a.pstride] = (uint32_t)s;
-        carry = s >> 32;  // -1, 0 or 1
+      const int qq = (int)floorf((float)sum[b] * inv_pf);
+      int r = sum[b] - qq * p;
+      if (r < 0) r += p;
+      if (r >= p) r -= p;
+      r4 |= (uint32_t)r << (8 * b);
+    }
+    return r4;
+  };
+  for (int64_t i = blockIdx.y; i < a.m; i += gridDim.y) {
+    const uint8_t* row = a.R + i * a.ldr + jc;
+    uint32_t d[4][4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[it][q] = residues4(row, 4 * (zq + 4 * it) + q);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int zg = zq + 4 * it;
+      if (zg >= nzg) break;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x |= ((d[it][q] >> (8 * b)) & 0xffu) << (8 * q);
+        *reinterpret_cast<uint32_t*>(tile + (4 * c + b) * LS + 4 * zg) = x ^ 0x80808080u;
       }
     }
+    __syncthreads();
+    v4i_t fb[4];
+#pragma unroll
+    for (int og = 0; og < 4; ++og) {
+      const int o = 64 * wave + 16 * og + lane % 16;
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(tile + o * LS + 16 * (lane / 16));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fb[og][q] = (int)src[q];
+    }
+    __syncthreads();  // the tile is read; its bytes take the word sums
+#pragma unroll
+    for (int og = 0; og < 4; ++og) {
+      const int o = 64 * wave + 16 * og + lane % 16;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const v4i_t x = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[g], fb[og], v4i_t{0, 0, 0, 0}, 0, 0, 0);
+        const int wd = 4 * g + lane / 16;
+        if (wd < W)
+          vs[o * W + wd] = (int64_t)x[0] + ((int64_t)x[1] << 8) + ((int64_t)x[2] << 16) + ((int64_t)x[3] << 24);
+      }
+    }
+    __syncthreads();
+    if (jt < a.n) {
+      uint64_t acc[W];
+      int64_t carry = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int64_t v = vs[threadIdx.x * W + w] + (int64_t)t.K0[w] + carry;
+        acc[w] = (uint64_t)(uint32_t)v;
+        carry = v >> 32;
+      }
+      uint32_t y[W];
+      const bool neg = crt_magnitude<W>(acc, t, y);
+      uint32_t* cw = a.C + i * a.ldc + jt;
+      // C += (neg ? -Y : Y) at word_off, in two's complement over words_c words
+      int64_t cy = 0;
+      for (int w = a.word_off; w < a.words_c; ++w) {
+        const int64_t yw = w - a.word_off < W ? (int64_t)y[w - a.word_off] : 0;
+        if (yw == 0 && cy == 0 && w - a.word_off >= W) break;
+        const int64_t cur = (int64_t)cw[(int64_t)w * a.pstride];
+        const int64_t sres = neg ? cur - yw + cy : cur + yw + cy;
+        cw[(int64_t)w * a.pstride] = (uint32_t)sres;
+        cy = sres >> 32;  // -1, 0 or 1
+      }
+    }
+    __syncthreads();  // the tile and the word sums are refilled for the next row
   }
 }
 
@@ -267,8 +311,11 @@ hipError_t launch_int_sum(const IntSumArgs& a, hipStream_t s) {
 hipError_t launch_int_accumulate(const IntAccumArgs& a, hipStream_t s) {
   if (a.m <= 0 || a.n <= 0) return hipSuccess;
   if (a.ldr % 4 || a.ldr < a.n || a.nterms < 1 || a.nterms > kIntMaxTerms) return hipErrorInvalidValue;
-  const int64_t gx = ((a.n + 3) / 4 + 255) / 256;
-  const dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(a.m, 65535));
+  const int64_t gx = (a.n + 255) / 256;
+  if (gx > 0x7fffffff) return hipErrorInvalidValue;
+  // about 4096 workgroups, each walking several rows
+  const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(a.m, 65535), (4096 + gx - 1) / gx));
+  const dim3 grid((unsigned)gx, (unsigned)gy);
   switch (crt_words(a.N)) {
     case 4: hipLaunchKernelGGL(int_accumulate_kernel<4>, grid, dim3(256), 0, s, a); break;
     case 6: hipLaunchKernelGGL(int_accumulate_kernel<6>, grid, dim3(256), 0, s, a); break;
