@@ -18,9 +18,11 @@
 namespace mpg {
 namespace {
 
-// 2^(32 j) mod p_z for the N moduli, built by the first threads of a block.
+// 2^(32 j) mod p_z and 1 / p_z (rounded) for the N moduli, built by the
+// first threads of a block.
 struct WordWeights {
   double c[kCrtMaxModuli][kIntMaxChunkWords];
+  double inv[kCrtMaxModuli];
 };
 
 __device__ void word_weights(WordWeights& w, int N) {
@@ -31,6 +33,7 @@ __device__ void word_weights(WordWeights& w, int N) {
       w.c[z][j] = (double)v;
       v = (v << 32) % p;
     }
+    w.inv[z] = 1.0 / (double)p;
   }
 }
 
@@ -89,7 +92,11 @@ __global__ __launch_bounds__(256) void int_residue_kernel(IntResidueArgs a) {
       for (int j = 0; j < CW; ++j) v[j][q] = t[j];
     }
     for (int z = 0; z < a.N; ++z) {
-      const double pd = (double)kCrtModuli[z], inv = 1.0 / pd;
+      const double pd = (double)kCrtModuli[z], inv = ww.inv[z];
+      // the remainder of the rounded quotient lies in [-(p+1)/2, (p+1)/2]
+      // (the quotient is within 1/(2p) of the exact one): a signed byte for
+      // every odd modulus up to 253; only 256 and 255 are centred
+      const bool centre = z < 2;  // uniform
       uint64_t packed = 0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -97,8 +104,10 @@ __global__ __launch_bounds__(256) void int_residue_kernel(IntResidueArgs a) {
 #pragma unroll
         for (int j = 0; j < CW; ++j) acc = __builtin_fma(v[j][q], ww.c[z][j], acc);
         double res = __builtin_fma(-rint(acc * inv), pd, acc);
-        if (2.0 * res >= pd) res -= pd;
-        if (2.0 * res < -pd) res += pd;
+        if (centre) {
+          if (2.0 * res >= pd) res -= pd;
+          if (2.0 * res < -pd) res += pd;
+        }
         packed |= (uint64_t)(uint8_t)(int8_t)(int)res << (8 * q);
       }
       *reinterpret_cast<uint64_t*>(a.out + ((int64_t)c * a.N + z) * plane + crt_plane_offset(r, k0, a.Kp)) =
