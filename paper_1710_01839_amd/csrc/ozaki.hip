@@ -78,22 +78,27 @@ __global__ __launch_bounds__(256) void row_scan_kernel(const double* X, const do
                                                        int64_t ld, int* e, int* need) {
   __shared__ int s_top[4], s_low[4];
   const int64_t r = blockIdx.x;
-  const double* row = X + r * ld;
   int top = INT_MIN, low = INT_MAX;
-  for (int64_t k = threadIdx.x; k < K; k += 256) {
-    const double x = row[k];
-    if (x != 0.0) {
-      int t, lo;
-      bit_range(x, t, lo);
-      top = max(top, t);
-      low = min(low, lo);
-    }
-    if (Xlo) {
-      const double xl = Xlo[r * ld + k];
-      if (xl != 0.0) {
-        int t, lo;
-        bit_range(xl, t, lo);
-        low = min(low, lo);
+  // pass 0 reads X (scale and lowest bit), pass 1 Xlo (lowest bit); four
+  // loads of a thread are issued before any is used (clamped indices, the
+  // values past K masked to zero)
+  for (int pass = 0; pass < (Xlo ? 2 : 1); ++pass) {
+    const double* row = (pass ? Xlo : X) + r * ld;
+    for (int64_t k0 = threadIdx.x; k0 < K; k0 += 4 * 256) {
+      double v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t k = k0 + 256 * j;
+        v[j] = row[k < K ? k : K - 1];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (k0 + 256 * j < K && v[j] != 0.0) {
+          int t, lo;
+          bit_range(v[j], t, lo);
+          if (pass == 0) top = max(top, t);
+          low = min(low, lo);
+        }
       }
     }
   }
@@ -131,23 +136,25 @@ __global__ __launch_bounds__(256) void col_scan_kernel(const double* X, const do
   const int64_t c = (int64_t)blockIdx.x * 64 + tc;
   const int64_t r0 = (int64_t)blockIdx.y * kColScanRows;
   int t = INT_MIN, lo = INT_MAX;
+  // pass 0 reads X (scale and lowest bit), pass 1 Xlo (lowest bit); the
+  // thread's rows are loaded eight at a time before any is used (clamped
+  // row indices, rows past R masked)
   if (c < K) {
-#pragma unroll 4
-    for (int i = tg; i < kColScanRows; i += 4) {
-      const int64_t r = r0 + i;
-      if (r < R) {
-        const double x = X[r * ld + c];
-        if (x != 0.0) {
-          int a, b;
-          bit_range(x, a, b);
-          t = max(t, a);
-          lo = min(lo, b);
+    for (int pass = 0; pass < (Xlo ? 2 : 1); ++pass) {
+      const double* col = (pass ? Xlo : X) + c;
+      for (int i0 = tg; i0 < kColScanRows; i0 += 8 * 4) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int64_t r = r0 + i0 + 4 * j;
+          v[j] = col[(r < R ? r : R - 1) * ld];
         }
-        if (Xlo) {
-          const double xl = Xlo[r * ld + c];
-          if (xl != 0.0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (r0 + i0 + 4 * j < R && v[j] != 0.0) {
             int a, b;
-            bit_range(xl, a, b);
+            bit_range(v[j], a, b);
+            if (pass == 0) t = max(t, a);
             lo = min(lo, b);
           }
         }
@@ -275,11 +282,44 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const double* X, const 
   for (int s = S - 1; s >= 0; --s) w[s * plane / 8] = carry_word(w[s * plane / 8], neg, c, s == 0);
 }
 
+// Residues of the 8 images in `words` (the first NW words nonzero) modulo
+// the N leading moduli, one 8-byte store per plane (planes `plane` bytes
+// apart).  The first two moduli (256, 255) need their residues centred to
+// fit a signed byte; the odd ones after them do not.  The odd moduli go in
+// groups of four whose constants are read together, so one wait on the
+// uniform loads serves four moduli.
+template <int NW>
+__device__ __forceinline__ void crt_store_residues(const double (&words)[kCrtImageWords][8],
+                                                   const CrtResidueConsts* __restrict__ rc, int N,
+                                                   int8_t* __restrict__ out, int64_t plane) {
+  for (int z = 0; z < min(N, 2); ++z)
+    *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane) =
+        crt_residues8<NW, true>(words, rc->c[z], kCrtModuli[z], rc->inv[z]);
+  constexpr int G = 4;
+  for (int z = 2; z < N; z += G) {
+    double c[G][NW], inv[G];
+    int p[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int zj = min(z + j, N - 1);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) c[j][w] = rc->c[zj][w];
+      inv[j] = rc->inv[zj];
+      p[j] = kCrtModuli[zj];
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (z + j < N)  // uniform
+        *reinterpret_cast<uint64_t*>(out + (int64_t)(z + j) * plane) =
+            crt_residues8<NW, false>(words, c[j], p[j], inv[j]);
+  }
+}
+
 // Residue planes of the residue form straight from the operand: one thread
-// per 8 consecutive k of a row, as in split_rows_kernel, but the truncated
-// digits (before any carry: the carry does not change their weighted sum)
-// are folded into the image's 40-bit words in registers and only the
-// residues are written, one byte per element and modulus.
+// per 8 consecutive k of a row, as in split_rows_kernel, but the image (the
+// truncated digits before any carry: the carry does not change their
+// weighted sum) is cut into 40-bit words of five digits in registers and
+// only the residues are written, one byte per element and modulus.
 //
 // COLS: the rows of the plane are the columns of X (X is K x R, element
 // (r, k) at X[k ld + r]), read in place instead of through a transposed
@@ -329,27 +369,34 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
       neg |= (unsigned)(hi + lo < 0.0) << q;
     }
   }
-  // word k gathers digits 5k .. 5k + 4 by Horner's rule; the word of a
-  // digit is known at compile time, so no register is selected at run time.
-  // DD: the digit is the sum of the two parts' truncated digits (|d| <= 510,
-  // |word| < 2^41, every step exact; canonical pairs, |lo| <= ulp(hi) / 2,
-  // keep both parts below 1 after the row scale), so the words hold
-  // trunc(hi 2^s) + trunc(lo 2^s), s = 8S - 2 - e.
+  // word k holds digits 5k .. 5k + n - 1 (n = min(5, S - 5k)) folded by
+  // Horner's rule, which is trunc(y 2^(8n)) of the remainder left by the
+  // words before it: truncations toward zero of a same-signed remainder
+  // compose, and scaling by 2^(8n), the integer part and the new remainder
+  // are all exact, so a word costs one step instead of n digit steps.
+  // DD: the two parts are cut on their own (|word| < 2^41; canonical pairs,
+  // |lo| <= ulp(hi) / 2, keep both parts below 1 after the row scale), so the
+  // words hold trunc(hi 2^s) + trunc(lo 2^s), s = 8S - 2 - e.
   double words[kCrtImageWords][8];
 #pragma unroll
-  for (int w = 0; w < kCrtImageWords; ++w)
+  for (int k = 0; k < kCrtImageWords; ++k) {
+    const int n = min(kCrtDigitsPerWord, S - kCrtDigitsPerWord * k);
+    const double scale = n > 0 ? __builtin_amdgcn_ldexp(1.0, 8 * n) : 0.0;  // uniform
 #pragma unroll
-    for (int q = 0; q < 8; ++q) words[w][q] = 0.0;
-#pragma unroll
-  for (int s = 0; s < kCrtMaxSlices; ++s) {
-    if (s < S) {  // uniform
-      const int k = s / kCrtDigitsPerWord;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        double dummy = 0.0;
-        double d = digit_value<false>(y[q], dummy);
-        if (DD) d += digit_value<false>(yl[q], dummy);
-        words[k][q] = __builtin_fma(words[k][q], 256.0, d);
+    for (int q = 0; q < 8; ++q) {
+      if (n > 0) {  // uniform
+        const double a = y[q] * scale;
+        const double t = trunc(a);
+        y[q] = a - t;
+        words[k][q] = t;
+        if (DD) {
+          const double al = yl[q] * scale;
+          const double tl = trunc(al);
+          yl[q] = al - tl;
+          words[k][q] += tl;
+        }
+      } else {
+        words[k][q] = 0.0;
       }
     }
   }
@@ -374,21 +421,14 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
         if (k == klast) words[k][q] += t;
     }
   }
-  const int64_t plane = Rp * Kp;
-  // images of up to 10 digits fill two words (uniform branch)
-  // the first two moduli (256, 255) need their residues centred to fit a
-  // signed byte; the odd ones below do not
-  if (S <= 2 * kCrtDigitsPerWord) {
-    for (int z = 0; z < N; ++z)
-      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + crt_plane_offset(r, k0, Kp)) =
-          z < 2 ? crt_residues8<2, true>(words, rc->c[z], kCrtModuli[z], rc->inv[z])
-                : crt_residues8<2, false>(words, rc->c[z], kCrtModuli[z], rc->inv[z]);
-  } else {
-    for (int z = 0; z < N; ++z)
-      *reinterpret_cast<uint64_t*>(out + (int64_t)z * plane + crt_plane_offset(r, k0, Kp)) =
-          z < 2 ? crt_residues8<kCrtImageWords, true>(words, rc->c[z], kCrtModuli[z], rc->inv[z])
-                : crt_residues8<kCrtImageWords, false>(words, rc->c[z], kCrtModuli[z], rc->inv[z]);
-  }
+  // images of up to 10 (15) digits fill two (three) words: uniform branch
+  int8_t* const o = out + crt_plane_offset(r, k0, Kp);
+  if (S <= 2 * kCrtDigitsPerWord)
+    crt_store_residues<2>(words, rc, N, o, Rp * Kp);
+  else if (S <= 3 * kCrtDigitsPerWord)
+    crt_store_residues<3>(words, rc, N, o, Rp * Kp);
+  else
+    crt_store_residues<kCrtImageWords>(words, rc, N, o, Rp * Kp);
 }
 
 // Columns of X (K x C, row-major) -> planes out[s][c][k] (transposed, c < Cp,
