@@ -113,36 +113,32 @@ __global__ __launch_bounds__(64) void crt_table_kernel(int N, CrtTable* t, const
 //   1. X' = sum_j r_j T_j < N 255 P < 2^(32 W) in W 32-bit words (formed by
 //      INT8 MFMAs over the T_j's digits, see the kernel below);
 //   2. q = floor(X' / P) from doubles (X' / P < 2^14, relative error far
-//      below 2^-14), then Y = X' - q P by words; a negative Y or Y >= P is
+//      below 2^-14; X' times the rounded 1 / P), then Y = X' - q P by words; a negative Y or Y >= P is
 //      corrected by one addition or subtraction of P;
 //   3. centre: Y >= P / 2 stands for Y - P (negative, magnitude P - Y);
-//   4. the top words of the magnitude, each scaled exactly by
+//   4. the words of the magnitude, each scaled exactly by
 //      2^(32 w + e_i + f_j + 4 - 16 S), are summed into a double-double
-//      (five words; the dropped ones are below 2^-96 of the top one) or
-//      added to a quad-double result (eight words, below 2^-192).
+//      (all of them, from the top) or added to a quad-double result (the
+//      top eight words; the dropped ones are below 2^-192 of the top one).
 // ---------------------------------------------------------------------
 // The signed value (magnitude words y, sign neg) times 2^scale as a
-// double-double: the top five words, each scaled exactly, summed by TwoSum.
+// double-double: every word from the top, each scaled exactly, summed by
+// Fast2Sum (once hi is nonzero it is at least the leading word's value,
+// above any later word, so each error term is exact).  No word is chosen
+// at run time: a per-lane top word would need selects over all W words for
+// each word taken.  From the fifth word on they lie below 2^-96 of the
+// leading one.
 template <int W>
 __device__ __forceinline__ void crt_to_dd(const uint32_t (&y)[W], bool neg, int scale, double& hi,
                                           double& lo) {
-  int top = -1;
-#pragma unroll
-  for (int w = 0; w < W; ++w)
-    if (y[w] != 0) top = w;
   hi = 0.0;
   lo = 0.0;
-  if (top < 0) return;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const int w = top - k;
-    if (w >= 0) {
-      const double v = ldexp((double)y[w], 32 * w + scale);
-      double s, e;
-      two_sum(hi, v, s, e);
-      hi = s;
-      lo += e;
-    }
+  for (int w = W - 1; w >= 0; --w) {
+    const double v = ldexp((double)y[w], 32 * w + scale);
+    const double s = hi + v;
+    lo += v - (s - hi);
+    hi = s;
   }
   dd_renorm(hi, lo);
   if (neg) {
@@ -219,13 +215,14 @@ __global__ __launch_bounds__(256, 4) void crt_reconstruct_kernel(RecArgs a) {
   constexpr int SMEM = 256 * LS > 256 * W * 8 ? 256 * LS : 256 * W * 8;
   __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
   uint8_t* const tile = smem;
-  int64_t* const vs = reinterpret_cast<int64_t*>(smem);
+  uint64_t* const vs = reinterpret_cast<uint64_t*>(smem);  // per output: W pairs of half sums
   if (a.plan) {
     if (!a.plan->ok || (a.product >= 0 && a.plan->skip[a.product])) return;
     a.N = a.plan->N;
     a.base = 4 - 16 * a.plan->S;
   }
   const CrtTable& t = *a.t;
+  const double rP = 1.0 / t.Pd;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   v4i_t fa[G];
@@ -283,22 +280,15 @@ __global__ __launch_bounds__(256, 4) void crt_reconstruct_kernel(RecArgs a) {
       for (int g = 0; g < G; ++g) {
         const v4i_t x = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[g], fb[og], v4i_t{0, 0, 0, 0}, 0, 0, 0);
         const int wd = 4 * g + lane / 16;  // lane holds positions 4 wd .. 4 wd + 3 of output o
-        if (wd < W)
-          vs[o * W + wd] = (int64_t)x[0] + ((int64_t)x[1] << 8) + ((int64_t)x[2] << 16) + ((int64_t)x[3] << 24);
+        if (wd < W) vs[o * W + wd] = crt_half_sums(x[0], x[1], x[2], x[3]);
       }
     }
     __syncthreads();
     if (jt < a.n) {
       uint64_t acc[W];
-      int64_t carry = 0;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int64_t v = vs[threadIdx.x * W + w] + (int64_t)t.K0[w] + carry;
-        acc[w] = (uint64_t)(uint32_t)v;
-        carry = v >> 32;
-      }
+      crt_carry_halves<W>(reinterpret_cast<const int32_t*>(vs + threadIdx.x * W), t, acc);
       uint32_t y[W];
-      const bool neg = crt_magnitude<W>(acc, t, y);
+      const bool neg = crt_magnitude<W>(acc, t, rP, y);
       const int64_t o = i * a.ldc + jt;
       if constexpr (!QD) {
         double hi, lo;

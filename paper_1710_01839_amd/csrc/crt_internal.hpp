@@ -106,13 +106,45 @@ __host__ __device__ __forceinline__ int64_t crt_plane_offset(int64_t r, int64_t 
   return ((r >> 4) * (Kp >> 6) + (k >> 6)) * 1024 + (r & 15) * 64 + (k & 63);
 }
 
+// The MFMA digit sums of an output, four consecutive radix-256 positions
+// 4wd .. 4wd + 3 (|x| < 2^20 each), as two int32 sums of 16-bit halves:
+// x0 + 2^8 x1 and x2 + 2^8 x3 (each below 2^29 in magnitude), so that the
+// word sum V_wd = sum_i x_i 2^(8i) is half0 + 2^16 half1 with no 64-bit
+// arithmetic; packed low half first.
+__device__ __forceinline__ uint64_t crt_half_sums(int x0, int x1, int x2, int x3) {
+  const uint32_t h0 = (uint32_t)(x0 + (x1 << 8)), h1 = (uint32_t)(x2 + (x3 << 8));
+  return (uint64_t)h0 | ((uint64_t)h1 << 32);
+}
+
+// The W 32-bit words of sum_h vh[h] 2^(16h) + K0 (2W half sums vh from
+// crt_half_sums, K0 the table's constant) by a signed carry pass over 16-bit
+// steps in int32: each step holds |vh| < 2^29, a 16-bit piece of K0 and a
+// carry below 2^14.  The value is below 2^(32W), so the positions from 32W
+// up cancel against the last carry, which is dropped.
+template <int W>
+__device__ __forceinline__ void crt_carry_halves(const int32_t* vh, const CrtTable& t, uint64_t (&acc)[W]) {
+  int32_t carry = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t k0 = t.K0[w];
+    const int32_t s0 = vh[2 * w] + (int32_t)(k0 & 0xFFFFu) + carry;
+    carry = s0 >> 16;
+    const int32_t s1 = vh[2 * w + 1] + (int32_t)(k0 >> 16) + carry;
+    carry = s1 >> 16;
+    acc[w] = ((uint32_t)s0 & 0xFFFFu) | ((uint32_t)s1 << 16);
+  }
+}
+
 // Reduces X' = sum_j r_j T_j (per 32-bit word in 64-bit accumulators, W
 // words) to the centred CRT value: returns its sign and writes its magnitude
 // words to y.  The quotient by P comes from doubles (off by at most one,
 // corrected by one addition or subtraction of P); Y >= P / 2 stands for
 // Y - P.
+// rP = 1 / Pd (rounded): the quotient estimate is a product, within one of
+// the true quotient as a division's would be (X' < N 256 P, so the quotient
+// is below 2^14, and the two estimates differ by a relative 2^-52).
 template <int W>
-__device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const CrtTable& t,
+__device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const CrtTable& t, double rP,
                                               uint32_t (&y)[W]) {
   uint32_t x[W];
   uint64_t carry = 0;
@@ -125,7 +157,7 @@ __device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const Cr
   double xd = 0.0;
 #pragma unroll
   for (int w = W - 1; w >= 0; --w) xd += ldexp((double)x[w], 32 * w);
-  const uint32_t q = (uint32_t)floor(xd / t.Pd);
+  const uint32_t q = (uint32_t)floor(xd * rP);
   // Y = X' - q P
   uint64_t mc = 0;
   int64_t br = 0;

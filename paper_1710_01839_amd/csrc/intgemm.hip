@@ -141,8 +141,9 @@ __global__ __launch_bounds__(256) void int_accumulate_kernel(IntAccumArgs a) {
   constexpr int SMEM = 256 * LS > 256 * W * 8 ? 256 * LS : 256 * W * 8;
   __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
   uint8_t* const tile = smem;
-  int64_t* const vs = reinterpret_cast<int64_t*>(smem);
+  uint64_t* const vs = reinterpret_cast<uint64_t*>(smem);  // per output: W pairs of half sums
   const CrtTable& t = *a.t;
+  const double rP = 1.0 / t.Pd;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   v4i_t fa[G];
@@ -212,22 +213,15 @@ __global__ __launch_bounds__(256) void int_accumulate_kernel(IntAccumArgs a) {
       for (int g = 0; g < G; ++g) {
         const v4i_t x = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[g], fb[og], v4i_t{0, 0, 0, 0}, 0, 0, 0);
         const int wd = 4 * g + lane / 16;
-        if (wd < W)
-          vs[o * W + wd] = (int64_t)x[0] + ((int64_t)x[1] << 8) + ((int64_t)x[2] << 16) + ((int64_t)x[3] << 24);
+        if (wd < W) vs[o * W + wd] = crt_half_sums(x[0], x[1], x[2], x[3]);
       }
     }
     __syncthreads();
     if (jt < a.n) {
       uint64_t acc[W];
-      int64_t carry = 0;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int64_t v = vs[threadIdx.x * W + w] + (int64_t)t.K0[w] + carry;
-        acc[w] = (uint64_t)(uint32_t)v;
-        carry = v >> 32;
-      }
+      crt_carry_halves<W>(reinterpret_cast<const int32_t*>(vs + threadIdx.x * W), t, acc);
       uint32_t y[W];
-      const bool neg = crt_magnitude<W>(acc, t, y);
+      const bool neg = crt_magnitude<W>(acc, t, rP, y);
       uint32_t* cw = a.C + i * a.ldc + jt;
       // C += (neg ? -Y : Y) at word_off, in two's complement over words_c words
       int64_t cy = 0;
