@@ -136,13 +136,16 @@ __device__ __forceinline__ void crt_carry_halves(const int32_t* vh, const CrtTab
 }
 
 // Reduces X' = sum_j r_j T_j (per 32-bit word in 64-bit accumulators, W
-// words) to the centred CRT value: returns its sign and writes its magnitude
-// words to y.  The quotient by P comes from doubles (off by at most one,
-// corrected by one addition or subtraction of P); Y >= P / 2 stands for
-// Y - P.
-// rP = 1 / Pd (rounded): the quotient estimate is a product, within one of
-// the true quotient as a division's would be (X' < N 256 P, so the quotient
-// is below 2^14, and the two estimates differ by a relative 2^-52).
+// words; X' < N 256 P < 2^(32 W)) to the centred CRT value: returns its sign
+// and writes its magnitude words to y.  Branch-free, by borrow chains:
+//   q: the quotient estimate, X' summed in doubles times rP = 1 / Pd
+//      (rounded), scaled by 1 - 2^-45 so that it never exceeds
+//      floor(X' / P) (the estimate's relative error is below 2^-48: W + 1
+//      roundings in the sum and Pd, two more in 1 / Pd and the product) and
+//      is at most one below it (X' / P < 2^14);
+//   Y = X' - q P lies in [0, 2 P): P is subtracted where that leaves no
+//      borrow;
+//   Y >= P / 2 (no borrow in Y - P / 2) stands for Y - P: magnitude P - Y.
 template <int W>
 __device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const CrtTable& t, double rP,
                                               uint32_t (&y)[W]) {
@@ -157,64 +160,31 @@ __device__ __forceinline__ bool crt_magnitude(const uint64_t (&acc)[W], const Cr
   double xd = 0.0;
 #pragma unroll
   for (int w = W - 1; w >= 0; --w) xd += ldexp((double)x[w], 32 * w);
-  const uint32_t q = (uint32_t)floor(xd * rP);
-  // Y = X' - q P
-  uint64_t mc = 0;
-  int64_t br = 0;
+  const uint32_t q = (uint32_t)floor(xd * rP * (1.0 - 0x1p-45));
+  uint32_t mc = 0;
+  unsigned b = 0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const uint64_t qp = (uint64_t)q * t.P[w] + mc;
-    mc = qp >> 32;
-    const int64_t d = (int64_t)x[w] - (int64_t)(uint32_t)qp + br;
-    y[w] = (uint32_t)d;
-    br = d >> 32;  // 0 or -1
+    mc = (uint32_t)(qp >> 32);
+    y[w] = __builtin_subc(x[w], (uint32_t)qp, b, &b);
   }
-  if (br < 0) {  // q one too large: add P back
-    uint64_t c = 0;
+  uint32_t z[W];
+  b = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const uint64_t s = (uint64_t)y[w] + t.P[w] + c;
-      y[w] = (uint32_t)s;
-      c = s >> 32;
-    }
-  } else {
-    // Y >= P (q one too small): subtract P
-    bool ge = true;
+  for (int w = 0; w < W; ++w) z[w] = __builtin_subc(y[w], t.P[w], b, &b);
+  const bool ge = b == 0;
 #pragma unroll
-    for (int w = W - 1; w >= 0; --w) {
-      if (y[w] != t.P[w]) {
-        ge = y[w] > t.P[w];
-        break;
-      }
-    }
-    if (ge) {
-      int64_t b2 = 0;
+  for (int w = 0; w < W; ++w) y[w] = ge ? z[w] : y[w];
+  b = 0;
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int64_t d = (int64_t)y[w] - (int64_t)t.P[w] + b2;
-        y[w] = (uint32_t)d;
-        b2 = d >> 32;
-      }
-    }
-  }
-  // centre
-  bool neg = true;  // Y >= P / 2
+  for (int w = 0; w < W; ++w) (void)__builtin_subc(y[w], t.half[w], b, &b);
+  const bool neg = b == 0;
+  b = 0;
 #pragma unroll
-  for (int w = W - 1; w >= 0; --w) {
-    if (y[w] != t.half[w]) {
-      neg = y[w] > t.half[w];
-      break;
-    }
-  }
-  if (neg) {  // magnitude P - Y
-    int64_t b2 = 0;
+  for (int w = 0; w < W; ++w) z[w] = __builtin_subc(t.P[w], y[w], b, &b);
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int64_t d = (int64_t)t.P[w] - (int64_t)y[w] + b2;
-      y[w] = (uint32_t)d;
-      b2 = d >> 32;
-    }
-  }
+  for (int w = 0; w < W; ++w) y[w] = neg ? z[w] : y[w];
   return neg;
 }
 
