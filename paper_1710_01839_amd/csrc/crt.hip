@@ -230,37 +230,48 @@ __global__ __launch_bounds__(256, 4) void crt_reconstruct_kernel(RecArgs a) {
   for (int g = 0; g < G; ++g) fa[g] = *reinterpret_cast<const v4i_t*>(&t.frag[g][lane][0]);
   const int nzg = (a.N + 3) / 4;
   const int c = threadIdx.x % 64, zq = threadIdx.x / 64;
-  const int64_t jc = j0 + 4 * c;       // this thread's four columns in step 1
   const int64_t jt = j0 + threadIdx.x;  // its output in step 3
   const int fjt = jt < a.n ? a.f[jt] : 0;
   // all of a thread's loads for a row (up to four groups of four moduli) go
-  // out together, and those of its next row while this one is computed
+  // out together, and those of its next row while this one is computed.
+  // The address is a uniform base (row, plane, column block) plus a 32-bit
+  // lane offset; lanes past the row's end (the last column block; ldr and
+  // j0 are multiples of 4) read its last four columns instead, whose values
+  // reach only outputs that are not stored.  Moduli past N read nothing.
+  const uint32_t lane_off = (uint32_t)(4 * c < a.ldr - j0 - 4 ? 4 * c : a.ldr - j0 - 4);
   uint32_t d[4][4];
   auto load_row = [&](int64_t i) {
-    const uint8_t* row = a.R + i * a.ldr + jc;
+    const uint8_t* row = a.R + i * a.ldr + j0;
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int zg = zq + 4 * it;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int z = 4 * zg + q;
-        d[it][q] = z < a.N && jc < a.ldr ? *reinterpret_cast<const uint32_t*>(row + (int64_t)z * a.planeR) : 0u;
+        d[it][q] = z < a.N ? *reinterpret_cast<const uint32_t*>(row + (int64_t)z * a.planeR + lane_off) : 0u;
       }
     }
   };
   if (blockIdx.y < a.m) load_row(blockIdx.y);
   for (int64_t i = blockIdx.y; i < a.m; i += gridDim.y) {
+    // 4 x 4 byte transpose (element q of word b: byte b of d[q]) by byte
+    // permutes: pairs of rows interleaved, then pairs of those
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int zg = zq + 4 * it;
       if (zg >= nzg) break;
+      const uint32_t d0 = d[it][0] ^ 0x80808080u, d1 = d[it][1] ^ 0x80808080u;
+      const uint32_t d2 = d[it][2] ^ 0x80808080u, d3 = d[it][3] ^ 0x80808080u;
+      const uint32_t lo01 = __builtin_amdgcn_perm(d1, d0, 0x05010400u);  // d0.0 d1.0 d0.1 d1.1
+      const uint32_t hi01 = __builtin_amdgcn_perm(d1, d0, 0x07030602u);  // d0.2 d1.2 d0.3 d1.3
+      const uint32_t lo23 = __builtin_amdgcn_perm(d3, d2, 0x05010400u);
+      const uint32_t hi23 = __builtin_amdgcn_perm(d3, d2, 0x07030602u);
+      const uint32_t x[4] = {__builtin_amdgcn_perm(lo23, lo01, 0x05040100u),
+                             __builtin_amdgcn_perm(lo23, lo01, 0x07060302u),
+                             __builtin_amdgcn_perm(hi23, hi01, 0x05040100u),
+                             __builtin_amdgcn_perm(hi23, hi01, 0x07060302u)};
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        uint32_t x = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) x |= ((d[it][q] >> (8 * b)) & 0xffu) << (8 * q);
-        *reinterpret_cast<uint32_t*>(tile + (4 * c + b) * LS + 4 * zg) = x ^ 0x80808080u;
-      }
+      for (int b = 0; b < 4; ++b) *reinterpret_cast<uint32_t*>(tile + (4 * c + b) * LS + 4 * zg) = x[b];
     }
     __syncthreads();
     if (i + gridDim.y < a.m) load_row(i + gridDim.y);
