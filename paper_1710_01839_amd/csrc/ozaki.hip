@@ -1141,20 +1141,38 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
   // within a 1 KiB block of the tiled plane layout: row lane % 16, k chunk lane / 16
   const uint32_t lane_off = (uint32_t)((lane % 16) * 64 + 16 * (lane / 16));
 
-  // K steps per segment; the segments' products add up in one accumulation
+  // K steps per segment; the segments' products add up in one accumulation.
+  // The loads are issued in step order by a running state: the segment's
+  // per-load buffer resources (base of the load's row block) are made once
+  // per segment, and the step within the segment is the scalar offset, so a
+  // step's issue costs a few scalar instructions (no division by the step
+  // count, no reload of the segment offsets).
   const int kps = (int)(lp / 64);
-  // K step `st` into its ring slot: blocks round-robin over the waves
-  auto issue = [&](int st) {
-    int8_t* dst = lds + (st % NBUF) * STAGE;
-    const int seg = st / kps, kk = st - seg * kps;
+  __amdgpu_buffer_rsrc_t rs[LOADS];
+  const auto set_segment = [&](int seg) {
     const int8_t* As = A + c.segA[seg];
     const int8_t* Bs = B + c.segB[seg];
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       const int b = wave + 8 * i;
       const int64_t rb = b < kCrtNBA ? m0 / 16 + b : n0 / 16 + (b - kCrtNBA);  // row block
-      const int8_t* src = (b < kCrtNBA ? As : Bs) + (rb * kps + kk) * 1024;
-      oz_dma(src, lane_off, dst + b * 1024);
+      const int8_t* base = (b < kCrtNBA ? As : Bs) + rb * kps * 1024;
+      // raw buffer: num_records only has to exceed every offset used
+      rs[i] = __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(base), (short)0, 0x7ffffff0, 0x00020000);
+    }
+  };
+  int next_seg = 0, next_kk = 0, next_slot = 0;
+  set_segment(0);
+  const auto issue_next = [&]() {
+    int8_t* dst = lds + next_slot * STAGE;
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs[i], (lds_ptr)(dst + (wave + 8 * i) * 1024), 16, (int)lane_off,
+                                               next_kk * 1024, 0, 0);
+    next_slot = next_slot + 1 == NBUF ? 0 : next_slot + 1;
+    if (++next_kk == kps) {
+      next_kk = 0;
+      if (++next_seg < c.nseg) set_segment(next_seg);
     }
   };
 
@@ -1167,7 +1185,8 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
   const int numK = kps * c.nseg;
 #pragma unroll
   for (int s = 0; s < NBUF - 1; ++s)
-    if (s < numK) issue(s);
+    if (s < numK) issue_next();
+  int until_reduce = kchunk;
   for (int st = 0; st < numK; ++st) {
     // this wave's loads of step st are done once at most the later steps'
     // (up to NBUF - 2 of them) are outstanding; near the end fewer are
@@ -1198,9 +1217,10 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
     // since the barrier); issued ahead of them they held up the MFMA issue
     // while the load unit queued them (1-2% slower as measured)
     __builtin_amdgcn_sched_barrier(0);
-    if (st + NBUF - 1 < numK) issue(st + NBUF - 1);
+    if (st + NBUF - 1 < numK) issue_next();
     __builtin_amdgcn_sched_barrier(0);
-    if ((st + 1) % kchunk == 0) {
+    if (--until_reduce == 0) {
+      until_reduce = kchunk;
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
