@@ -323,9 +323,9 @@ __device__ __forceinline__ void crt_store_residues(const double (&words)[kCrtIma
 //
 // COLS: the rows of the plane are the columns of X (X is K x R, element
 // (r, k) at X[k ld + r]), read in place instead of through a transposed
-// copy.  A wavefront then takes 8 columns x 64 k: for each k its lanes read
-// 64 contiguous bytes of a row of X, and the 8 bytes each lane writes per
-// modulus fill half of a 16 x 64 block of the plane (512 contiguous bytes).
+// copy: for each k a wavefront's lanes read 64 contiguous bytes of a row of
+// X.
+constexpr int kCrtRowsTiledModuli = 24;
 template <bool DD, bool COLS>
 __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const double* Xlo, int64_t R,
                                                        int64_t K, int64_t ld, const int* e, int S, int N,
@@ -341,14 +341,25 @@ __global__ __launch_bounds__(256) void crt_rows_kernel(const double* X, const do
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= Rp * per_row) return;
   int64_t r, k0;
-  if (!COLS) {
+  // a wavefront takes 8 rows x 64 k of the plane (Rp % 16 == 0 and
+  // Kp % 64 == 0: whole groups), so its 8-byte stores of one plane fill 512
+  // contiguous bytes, half of a 16 x 64 block.  Rows of X with few moduli
+  // (few stores per load) keep one row x 512 k per wavefront, whose loads
+  // span fewer rows: the 8 x 64 form was 12% faster with 44 moduli and 39%
+  // slower with 16.
+  const int64_t t = idx / 64, lane = idx % 64, row_groups = Rp / 8;
+  if (!COLS && N < kCrtRowsTiledModuli) {
     r = idx / per_row;
     k0 = (idx % per_row) * 8;
+  } else if (!COLS) {
+    // lanes 8i .. 8i + 7: one row, 64 consecutive k
+    r = (t % row_groups) * 8 + lane / 8;
+    k0 = ((t / row_groups) * 8 + lane % 8) * 8;
   } else {
-    // Rp % 16 == 0 and Kp % 64 == 0: whole 8 x 64 groups
-    const int64_t t = idx / 64, lane = idx % 64, col_groups = Rp / 8;
-    r = (t % col_groups) * 8 + lane % 8;
-    k0 = ((t / col_groups) * 8 + lane / 8) * 8;
+    // lanes i, i + 8, ..: 8 consecutive columns of X, one 64-byte segment of
+    // a row of X for each k
+    r = (t % row_groups) * 8 + lane % 8;
+    k0 = ((t / row_groups) * 8 + lane / 8) * 8;
   }
   // y: the scaled leading part; yl: the scaled trailing part (DD), each cut
   // into digits on its own (a pair is not renormalised)
