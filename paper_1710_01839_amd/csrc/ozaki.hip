@@ -904,7 +904,7 @@ __global__ __launch_bounds__(64 * NW, 1) void ozaki_lds_kernel(OzakiGemmArgs a, 
 // (4 + WN) S KiB for 4 WN S^2 MFMAs; a wave loading both operands itself
 // would move 2S KiB for S^2.
 // ---------------------------------------------------------------------
-constexpr int kOzBandMinS = kOzLdsMaxS + 1, kOzBandMaxS = 24;
+constexpr int kOzBandMaxS = 24;  // the band form takes kOzLdsMaxS + 1 .. kOzBandMaxS slices
 // column blocks per wavefront: two while the 2S - 1 accumulators of both fit
 template <int S>
 constexpr int oz_band_wn() {
