@@ -79,20 +79,21 @@ __global__ __launch_bounds__(256) void row_scan_kernel(const double* X, const do
   __shared__ int s_top[4], s_low[4];
   const int64_t r = blockIdx.x;
   int top = INT_MIN, low = INT_MAX;
-  // pass 0 reads X (scale and lowest bit), pass 1 Xlo (lowest bit); four
+  // pass 0 reads X (scale and lowest bit), pass 1 Xlo (lowest bit); eight
   // loads of a thread are issued before any is used (clamped indices, the
   // values past K masked to zero)
+  constexpr int V = 8;
   for (int pass = 0; pass < (Xlo ? 2 : 1); ++pass) {
     const double* row = (pass ? Xlo : X) + r * ld;
-    for (int64_t k0 = threadIdx.x; k0 < K; k0 += 4 * 256) {
-      double v[4];
+    for (int64_t k0 = threadIdx.x; k0 < K; k0 += V * 256) {
+      double v[V];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < V; ++j) {
         const int64_t k = k0 + 256 * j;
         v[j] = row[k < K ? k : K - 1];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < V; ++j) {
         if (k0 + 256 * j < K && v[j] != 0.0) {
           int t, lo;
           bit_range(v[j], t, lo);
