@@ -51,3 +51,50 @@ def test_product_residue_reduction_in_32_bits():
         assert np.all((r >= -p) & (r < 2 * p)), p
         got = (np.stack([r, r + p, r - p]) & 0xffffffff).min(axis=0)
         assert np.array_equal(got, np.mod(v.astype(np.int64), p)), p
+
+
+def _crt_words(n_mod, mods):
+    """Words of the reconstruction for n_mod moduli: the bit length of
+    n_mod 255 P in 32-bit words, at least 4 and even (the built sizes)."""
+    P = 1
+    for p in mods[:n_mod]:
+        P *= p
+    words = ((n_mod * 255 * P).bit_length() + 31) // 32
+    return max(4, (words + 1) // 2 * 2), P
+
+
+def test_reconstruction_quotient_estimate():
+    """The reconstruction's quotient: X' (< N 255 P, in W 32-bit words) summed
+    in doubles from the top word, times the rounded 1 / Pd (Pd: P's words
+    summed the same way), scaled by 1 - 2^-45 and floored, is floor(X' / P)
+    or one less, never more, so X' - q P lies in [0, 2P) and one
+    conditional subtraction of P finishes the reduction.  Every moduli count,
+    random X' and X' next to every multiple of P up to a few hundred,
+    IEEE binary64 steps in Python floats (each add and product rounded once,
+    in the kernel's order)."""
+    import math
+    import random
+    mods = crt.moduli()
+    rnd = random.Random(17)
+    for n_mod in range(1, len(mods) + 1):
+        W, P = _crt_words(n_mod, mods)
+        if W > 12:
+            continue
+        pd = 0.0
+        for w in range(12 - 1, -1, -1):
+            pd += math.ldexp(float((P >> (32 * w)) & 0xFFFFFFFF), 32 * w)
+        rp = 1.0 / pd
+        top = n_mod * 255 * P
+        xs = [0, top - 1] + [rnd.randrange(top) for _ in range(400)]
+        for k in list(range(1, 300)) + [rnd.randrange(1, n_mod * 255) for _ in range(100)]:
+            xs += [k * P - 1, k * P, k * P + 1]
+        for x in xs:
+            if not 0 <= x < top:
+                continue
+            xd = 0.0
+            for w in range(W - 1, -1, -1):
+                xd += math.ldexp(float((x >> (32 * w)) & 0xFFFFFFFF), 32 * w)
+            q = math.floor(xd * rp * (1.0 - 2.0 ** -45))
+            exact = x // P
+            assert q in (exact - 1, exact), (n_mod, x)
+            assert 0 <= x - q * P < 2 * P
