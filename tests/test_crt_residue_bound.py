@@ -98,3 +98,66 @@ def test_reconstruction_quotient_estimate():
             exact = x // P
             assert q in (exact - 1, exact), (n_mod, x)
             assert 0 <= x - q * P < 2 * P
+
+
+def _two_sum(a, b):
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def test_image_words_by_one_truncation_each():
+    """The residue planes cut an element's image into 40-bit words, one
+    truncation per word (trunc(y 2^(8n)) of the remainder the words before
+    it left, n = min(5, S - 5k) digits), a double-double's two parts on their
+    own, and restore the truncation of hi + lo as one value from the two
+    remainders (floor or ceil of their exact sum by the sign of the rounded
+    sum).  The words, weighted 256^max(S - 5k - 5, 0), must give
+    trunc((hi + lo) 2^(8S - 2 - e)) exactly: host steps in IEEE binary64
+    (Python floats) against the exact value in rationals, for canonical pairs
+    of both sign patterns, tiny trailing parts and every slice count."""
+    import math
+    import random
+    from fractions import Fraction
+    rnd = random.Random(23)
+    cases = []
+    for _ in range(3000):
+        hi = rnd.uniform(-1.0, 1.0) * 2.0 ** rnd.randint(-30, 30)
+        if hi == 0.0:
+            continue
+        ulp = math.ulp(hi)
+        lo = rnd.choice([0.0, rnd.uniform(-0.5, 0.5) * ulp, rnd.uniform(-0.5, 0.5) * ulp * 2.0 ** -40])
+        cases.append((hi, lo))
+    # trailing parts of the opposite sign and leading parts with few bits
+    for _ in range(1000):
+        hi = rnd.randrange(1 << 10, 1 << 11) * 2.0 ** -11 * rnd.choice([-1.0, 1.0])
+        lo = rnd.randrange(1, 1 << 30) * 2.0 ** -60 * rnd.choice([-1.0, 1.0])
+        cases.append((hi, lo))
+    for hi, lo in cases:
+        # the row scale: |x| < 2^e from the leading part's exponent
+        e = math.frexp(hi)[1]
+        for S in range(1, 21):
+            y, yl = math.ldexp(hi, -(e + 2)), math.ldexp(lo, -(e + 2))
+            words = []
+            for k in range(4):
+                n = min(5, S - 5 * k)
+                if n <= 0:
+                    break
+                sc = math.ldexp(1.0, 8 * n)
+                a, al = y * sc, yl * sc
+                t, tl = float(math.trunc(a)), float(math.trunc(al))
+                y, yl = a - t, al - tl
+                words.append(t + tl)
+            f, g = _two_sum(y, yl)
+            neg = hi + lo < 0.0
+            t = float(math.ceil(f)) if neg else float(math.floor(f))
+            if t == f:
+                t += (1.0 if g > 0.0 else 0.0) if neg else (-1.0 if g < 0.0 else 0.0)
+            words[-1] += t
+            image = 0
+            for k, wv in enumerate(words):
+                assert wv == math.floor(wv) and abs(wv) < 2.0 ** 41 + 2
+                image += int(wv) * 256 ** max(S - 5 * k - 5, 0)
+            exact = (Fraction(hi) + Fraction(lo)) * Fraction(2) ** (8 * S - 2 - e)
+            want = math.floor(exact) if exact >= 0 else -math.floor(-exact)
+            assert image == want, (hi, lo, S)
