@@ -161,3 +161,59 @@ def test_image_words_by_one_truncation_each():
             exact = (Fraction(hi) + Fraction(lo)) * Fraction(2) ** (8 * S - 2 - e)
             want = math.floor(exact) if exact >= 0 else -math.floor(-exact)
             assert image == want, (hi, lo, S)
+
+
+def test_reconstruction_integer_steps():
+    """The reconstruction's integer steps on the host: T_j in balanced
+    radix-256 digits (4W positions), residues staged as u_j = r_j - 128, the
+    digit sums X_b = sum_j u_j d_jb (below 2^20), their pairs as int32 half
+    sums x0 + 2^8 x1 (below 2^29), and the signed carry pass over 16-bit
+    steps with K0 = 128 sum_j T_j (carries below 2^14) give the W low words
+    of X' = sum_j r_j T_j, which is below 2^(32W).  Python integers with the
+    kernel's arithmetic shifts, several moduli counts, random residues and
+    the extremes 0 and p - 1."""
+    import random
+    mods = crt.moduli()
+    rnd = random.Random(5)
+    for n_mod in (1, 4, 5, 16, 17, 39, 44, 49):
+        W, P = _crt_words(n_mod, mods)
+        ps = mods[:n_mod]
+        T = [(P // p) * pow(P // p, -1, p) % P for p in ps]
+        assert all(T[j] % ps[k] == (1 if j == k else 0) for j in range(n_mod) for k in range(n_mod))
+
+        def balanced(t):
+            ds = []
+            for _ in range(4 * W):
+                d = t % 256
+                t //= 256
+                if d >= 128:
+                    d -= 256
+                    t += 1
+                ds.append(d)
+            assert t == 0
+            return ds
+
+        D = [balanced(t) for t in T]
+        K0 = 128 * sum(T)
+        trials = [[0] * n_mod, [p - 1 for p in ps]] + [[rnd.randrange(p) for p in ps] for _ in range(150)]
+        for r in trials:
+            u = [x - 128 for x in r]
+            X = [sum(u[j] * D[j][b] for j in range(n_mod)) for b in range(4 * W)]
+            assert all(abs(x) < 2 ** 20 for x in X)
+            carry, words = 0, []
+            for w in range(W):
+                h0 = X[4 * w] + (X[4 * w + 1] << 8)
+                h1 = X[4 * w + 2] + (X[4 * w + 3] << 8)
+                assert abs(h0) < 2 ** 29 and abs(h1) < 2 ** 29
+                k0 = (K0 >> (32 * w)) & 0xFFFFFFFF
+                s0 = h0 + (k0 & 0xFFFF) + carry
+                carry = s0 >> 16
+                assert abs(carry) < 2 ** 14
+                s1 = h1 + (k0 >> 16) + carry
+                carry = s1 >> 16
+                assert abs(carry) < 2 ** 14
+                words.append((s0 & 0xFFFF) | ((s1 & 0xFFFF) << 16))
+            xp = sum(rj * tj for rj, tj in zip(r, T))
+            assert xp < 2 ** (32 * W)
+            assert words == [(xp >> (32 * w)) & 0xFFFFFFFF for w in range(W)], n_mod
+            assert all(xp % p == rj for p, rj in zip(ps, r))
