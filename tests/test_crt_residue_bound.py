@@ -217,3 +217,67 @@ def test_reconstruction_integer_steps():
             assert xp < 2 ** (32 * W)
             assert words == [(xp >> (32 * w)) & 0xFFFFFFFF for w in range(W)], n_mod
             assert all(xp % p == rj for p, rj in zip(ps, r))
+
+
+def test_reconstruction_magnitude_and_double_double():
+    """The reconstruction's tail on the host: from X' (W words) the
+    branch-free magnitude (quotient estimate, borrow chains, one conditional
+    subtraction of P, centring at P/2) must give the centred value of X' mod
+    P, and every word of its magnitude summed from the top by Fast2Sum then
+    renormalised must be within 2^-104 of it, relative (the result's stated
+    rounding).  Python integers for the words, Python floats (IEEE binary64)
+    for the doubles, in the kernel's order."""
+    import math
+    import random
+    from fractions import Fraction
+    mods = crt.moduli()
+    rnd = random.Random(29)
+    worst = 0.0
+    for n_mod in (4, 16, 39, 44, 49):
+        W, P = _crt_words(n_mod, mods)
+        pd = 0.0
+        for w in range(11, -1, -1):
+            pd += math.ldexp(float((P >> (32 * w)) & 0xFFFFFFFF), 32 * w)
+        rp = 1.0 / pd
+        half = P >> 1
+        top = n_mod * 255 * P
+        xs = [rnd.randrange(top) for _ in range(300)]
+        # small values of either sign and values next to P/2
+        for k in (rnd.randrange(1, 50) for _ in range(20)):
+            for v in (rnd.randrange(1, 1 << 60), half - rnd.randrange(1, 1 << 40)):
+                xs += [k * P + v, k * P + P - v]
+        for x in xs:
+            if not 0 <= x < top:
+                continue
+            xw = [(x >> (32 * w)) & 0xFFFFFFFF for w in range(W)]
+            xd = 0.0
+            for w in range(W - 1, -1, -1):
+                xd += math.ldexp(float(xw[w]), 32 * w)
+            q = math.floor(xd * rp * (1.0 - 2.0 ** -45))
+            y = x - q * P                       # the borrow chain's result
+            assert 0 <= y < 2 * P
+            if y >= P:                          # no borrow in Y - P
+                y -= P
+            neg = y >= half                     # no borrow in Y - P/2
+            mag = P - y if neg else y
+            want = x % P
+            if want > P // 2 or (want == half and P % 2 == 0):
+                want -= P
+            assert (-mag if neg else mag) == want
+            scale = rnd.randint(-300, 300) - 32 * W
+            hi = lo = 0.0
+            for w in range(W - 1, -1, -1):
+                v = math.ldexp(float((mag >> (32 * w)) & 0xFFFFFFFF), 32 * w + scale)
+                s = hi + v
+                lo += v - (s - hi)
+                hi = s
+            s = hi + lo                         # renormalise (TwoSum)
+            bb = s - hi
+            lo = (hi - (s - bb)) + (lo - bb)
+            hi = s
+            if mag:
+                exact = Fraction(mag) * Fraction(2) ** scale
+                err = abs(Fraction(hi) + Fraction(lo) - exact) / exact
+                worst = max(worst, float(err) * 2.0 ** 104)
+    print("worst double-double error / 2^-104:", worst)
+    assert worst <= 1.0
