@@ -151,6 +151,22 @@ def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
             crt = lambda: M.mpgemm_dd_ozaki(ctx, Ad, Bd, C, 0, "crt")
         crt_ms, crt_launch = timed(crt)
         N = M.ozaki_last_moduli(ctx)
+        auto_ms = None
+        if not name.startswith("fp64"):
+            # the same product through MPG_AUTO with the residue form in the
+            # tuning table: slice and moduli counts decided on the device, no
+            # read-back (its own context, so the table stays local to it)
+            actx = M.Context(0)
+            M.Tuner(actx).table_set("dd", n, n, n, "ozaki_crt", {"slices": 0})
+            auto = lambda: M.mpgemm_dd(actx, Ad, Bd, C, algo="auto")
+            auto()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                auto()
+            torch.cuda.synchronize()
+            auto_ms = (time.perf_counter() - t0) / reps * 1e3
+            actx.close()
         dd_ms, _ = timed(lambda: plain_step(Ad, Bd, C))
         tops = S * S * 2.0 * n ** 3 / (oz_launch * 1e-3) / 1e12
         crt_tops = N * 2.0 * n ** 3 / (crt_launch * 1e-3) / 1e12
@@ -172,6 +188,8 @@ def ozaki_vs_plain(M, ctx, n, plain_step, reps=3):
                                                    "frac": round(crt_tops / INT8_PEAK_TOPS, 4),
                                                    "kernel": "INT8 MFMA residue products",
                                                    "launch_ms": round(crt_launch, 3)}}}
+        if auto_ms is not None:
+            out[name]["residue_form"]["auto_device_plan_ms"] = round(auto_ms, 3)
         del Ad, Bd
     return out
 

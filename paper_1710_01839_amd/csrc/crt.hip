@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256, 4) void crt_reconstruct_kernel(RecArgs a) {
   uint8_t* const tile = smem;
   uint64_t* const vs = reinterpret_cast<uint64_t*>(smem);  // per output: W pairs of half sums
   if (a.plan) {
-    if (!a.plan->ok || (a.product >= 0 && a.plan->skip[a.product])) return;
+    if (!a.plan->ok || a.plan->W != W || (a.product >= 0 && a.plan->skip[a.product])) return;
     a.N = a.plan->N;
     a.base = 4 - 16 * a.plan->S;
   }
@@ -324,6 +324,7 @@ __global__ void crt_plan_kernel(const int* need, CrtModuliTable t, CrtPlan* plan
   const int N = S <= kCrtMaxSlices ? t.N[S] : 0;
   plan->S = S;
   plan->N = N;
+  plan->W = N > 0 ? t.W[S] : 0;
   plan->ok = N > 0 ? 1 : 0;
   for (int k = 0; k < 3; ++k) plan->skip[k] = 0;
   for (int p = 0; p < 4; ++p) plan->unused[p] = 0;
@@ -349,6 +350,7 @@ __global__ void crt_plan_qd_kernel(const int* need, CrtModuliTable t, CrtPlan* p
   const int N = S == 0 ? 1 : S <= kCrtMaxSlices ? t.N[S] : 0;
   plan->S = max(S, 1);
   plan->N = N;
+  plan->W = N == 0 ? 0 : S == 0 ? t.W[0] : t.W[S];
   plan->ok = N > 0 ? 1 : 0;
 }
 
@@ -477,17 +479,26 @@ hipError_t launch_crt_reconstruct(const uint8_t* R, int64_t ldr, int64_t planeR,
     else                                                                                       \
       hipLaunchKernelGGL((crt_reconstruct_kernel<WW, true>), grid, dim3(256), 0, s, a);        \
     break;
-  switch (crt_words(N)) {
-    MPG_CRT_REC(4)
-    MPG_CRT_REC(6)
-    MPG_CRT_REC(8)
-    MPG_CRT_REC(10)
-    MPG_CRT_REC(12)
-    default:
-      return hipErrorInvalidValue;
+  const int Wmax = crt_words(N);
+  if (Wmax == 0) return hipErrorInvalidValue;
+  // with a plan: one launch per built word count up to Wmax (the plan's N
+  // is at most N, so its W is one of them); all but the plan's return at
+  // once
+  for (int W = plan ? 4 : Wmax; W <= Wmax; W += 2) {
+    switch (W) {
+      MPG_CRT_REC(4)
+      MPG_CRT_REC(6)
+      MPG_CRT_REC(8)
+      MPG_CRT_REC(10)
+      MPG_CRT_REC(12)
+      default:
+        return hipErrorInvalidValue;
+    }
+    const hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
   }
 #undef MPG_CRT_REC
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace mpg

@@ -51,15 +51,20 @@ struct CrtTable {
 // the quad-double form (three products of double-double parts) skip[k]
 // marks a product with an all-zero part and unused[p] a part (A_H, A_L, B_H,
 // B_L) no remaining product takes; a kernel given its index does nothing
-// then.
+// then.  W is crt_words(N): the reconstruction is launched once per built
+// word count up to that of the most moduli, and only the launch of the
+// plan's W works.
 struct CrtPlan {
   int S, N, ok;
   int skip[3];
   int unused[4];
+  int W;
 };
-// Moduli for 1..kCrtMaxSlices slices at one l (index S; 0: does not fit).
+// Moduli for 1..kCrtMaxSlices slices at one l (index S; 0: does not fit)
+// and their reconstruction word counts (W[0]: that of one modulus).
 struct CrtModuliTable {
   int N[kCrtMaxSlices + 1];
+  int W[kCrtMaxSlices + 1];
 };
 hipError_t launch_crt_plan(const int* need, const CrtModuliTable& t, CrtPlan* plan, hipStream_t s);
 // The quad-double plan from the four parts' exact slice counts

@@ -1126,9 +1126,21 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
   __shared__ __attribute__((aligned(16))) int8_t lds[NBUF * STAGE];
   const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int tiles = tiles_m * tiles_n;
+  // With a device-side plan the grid holds the most moduli any plan may
+  // use, and only its first plan->N x tiles workgroups work.  The remap is
+  // taken over those: the hardware deals workgroup b to XCD b % 8, so a
+  // prefix of the grid is spread evenly, and the idle workgroups at the end
+  // return at once (a remap over the whole grid put the unused moduli's
+  // tiles on whole XCDs, which then sat idle).
+  int total = gridDim.x;
+  if (c.plan) {
+    if (c.product >= 0 && c.plan->skip[c.product]) return;
+    total = min(c.plan->N, c.N) * tiles;  // 0 when the plan does not fit
+    if ((int)blockIdx.x >= total) return;
+  }
   int tm, tn, z;
   {
-    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int w = xcd_remap(blockIdx.x, total);
     z = w / tiles;
     const int t = w - z * tiles;
     constexpr int GR = 8;
@@ -1140,8 +1152,6 @@ __global__ __launch_bounds__(512, 1) void crt_tile_kernel(CrtGemmArgs c, int til
     tm = first + in % gsize;
     tn = in / gsize;
   }
-  // a modulus or a product the device-side plan does not use
-  if (c.plan && (z >= c.plan->N || (c.product >= 0 && c.plan->skip[c.product]))) return;
   const int p = c.mods[z];
   const int c16 = 65536 % p;
   const float inv_pf = 1.0f / (float)p;

@@ -303,7 +303,9 @@ int mpg_dd_crt_auto(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* A
   for (int S = 1; S <= Smax; ++S) {
     const int N = crt_moduli_for_bits(crt_product_bits(S, l));
     tab.N[S] = N > 0 && crt_words(N) > 0 ? N : 0;
+    tab.W[S] = crt_words(tab.N[S]);
   }
+  tab.W[0] = crt_words(1);
   int st;
   int *e, *f, *counter;
   if ((st = exponents(c, m, n, l, A, A_lo, lda, B, B_lo, ldb, true, &e, &f, &counter)) != MPG_OK) return st;
@@ -506,7 +508,9 @@ int mpg_qd_crt_auto(mpg_ctx* c, int64_t m, int64_t n, int64_t l, const double* c
   for (int S = 1; S <= Smax; ++S) {
     const int N = crt_moduli_for_bits(crt_product_bits(S, l));
     tab.N[S] = N > 0 && crt_words(N) > 0 ? N : 0;
+    tab.W[S] = crt_words(tab.N[S]);
   }
+  tab.W[0] = crt_words(1);
   const int64_t mp = round_up(std::max<int64_t>(m, 1), 64), np = round_up(std::max<int64_t>(n, 1), 64);
   void* small = nullptr;
   int st = mpg_workspace(c, 1, (size_t)(2 * mp + 3 * np + 64) * sizeof(int), &small);
