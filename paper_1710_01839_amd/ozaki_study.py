@@ -35,6 +35,9 @@ def main():
     ap.add_argument("--crt", action="store_true",
                     help="also time the residue (CRT) form at each slice count up to 20 (one INT8 "
                          "product per modulus)")
+    ap.add_argument("--auto", action="store_true",
+                    help="with --dist dd: also time MPG_AUTO with the residue form (exact slice count) in the "
+                         "tuning table, whose slice and moduli counts are decided on the device")
     args = ap.parse_args()
 
     import torch
@@ -95,6 +98,11 @@ def main():
                               "aux_ms": round(aux, 3), "int8_tops": round(tops, 1),
                               "frac_int8_peak": round(tops / INT8_PEAK_TOPS, 4),
                               "dd_equiv_gflops": round(2.0 * n ** 3 / wall / 1e6, 1)}), flush=True)
+        if dd and args.auto:
+            M.Tuner(ctx).table_set("dd", n, n, n, "ozaki_crt", {"slices": 0})
+            wall, kms, aux = timed(lambda: M.mpgemm_dd(ctx, Ad, Bd, C, algo="auto"))
+            print(json.dumps({"kind": "ozaki_auto", "n": n, "dist": args.dist, "pairs": "crt",
+                              "wall_ms": round(wall, 3), "aux_ms": round(aux, 3)}), flush=True)
         if not dd:
             Ad, Bd = (A, torch.zeros_like(A)), (B, torch.zeros_like(B))
         for algo, tile in (("block", None), ("strassen", {"depth": 2})):
