@@ -126,6 +126,34 @@ def test_crt_moduli_match_oracle(lib):
     assert M.crt_moduli_for(21, 64) == 0 and M.crt_moduli_for(0, 64) == 0
 
 
+def test_device_plan_counts_within_the_launch_sizes(lib):
+    """MPG_AUTO's device-side plan launches the residue form for the moduli
+    20 slices need and the reconstruction once per built word count up to
+    theirs; that covers every plan only if the moduli count never falls as
+    the slice count grows and every count's reconstruction words (the bit
+    length of N 255 P, rounded up to an even count of 32-bit words, at least
+    4) are a built size no larger than those of 20 slices."""
+    from oracle import crt
+    from paper_1710_01839_amd import mpgemm as M
+
+    def words(N):
+        P = 1
+        for p in crt.moduli()[:N]:
+            P *= p
+        w = ((N * 255 * P).bit_length() + 31) // 32
+        return max(4, (w + 1) // 2 * 2)
+
+    for l in (1, 64, 100, 4096, 8192, 1 << 20):
+        Ns = [M.crt_moduli_for(S, l) for S in range(1, 21)]
+        fit = [N for N in Ns if N > 0]
+        assert Ns[:len(fit)] == fit and fit == sorted(fit), l
+        if not fit:
+            continue
+        Wmax = words(fit[-1])
+        for N in fit:
+            assert words(N) in (4, 6, 8, 10, 12) and words(N) <= Wmax, (l, N)
+
+
 def test_int_words_needed_matches_oracle(lib):
     """Output word count of the exact long-integer product (host only) equals
     the oracle's bound for every operand size pair and a range of l."""
