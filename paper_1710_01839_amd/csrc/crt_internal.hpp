@@ -226,7 +226,7 @@ template <int NW, bool CENTRE>
 __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImageWords][8],
                                                   const double* c, int p, double inv) {
   const double pd = (double)p;
-  uint64_t packed = 0;
+  uint32_t v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     double acc = 0.0;
@@ -237,9 +237,18 @@ __device__ __forceinline__ uint64_t crt_residues8(const double (&words)[kCrtImag
       if (2.0 * r >= pd) r -= pd;
       if (2.0 * r < -pd) r += pd;
     }
-    packed |= (uint64_t)(uint8_t)(int8_t)(int)r << (8 * q);
+    v[q] = (uint32_t)(int)r;
   }
-  return packed;
+  // the low bytes (two's complement) four at a time: two byte pairs, then
+  // the pairs (three byte permutes per four elements)
+  uint32_t half[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t p01 = __builtin_amdgcn_perm(v[4 * h + 1], v[4 * h], 0x0c0c0400u);      // e0 e1 0 0
+    const uint32_t p23 = __builtin_amdgcn_perm(v[4 * h + 3], v[4 * h + 2], 0x0c0c0400u);  // e2 e3 0 0
+    half[h] = __builtin_amdgcn_perm(p23, p01, 0x05040100u);                                // e0 e1 e2 e3
+  }
+  return (uint64_t)half[0] | (uint64_t)half[1] << 32;
 }
 
 // Residue planes straight from the operand rows: for each row r of X (R x K,
