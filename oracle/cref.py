@@ -35,8 +35,9 @@ def build(force: bool = False) -> str:
 def lib():
     global _lib
     if _lib is None:
-        build()
-        _lib = ctypes.CDLL(_LIB)
+        # MPREF_LIB: another build of the same source (the sanitizer test's)
+        path = os.environ.get("MPREF_LIB") or build()
+        _lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(dp)
         i64 = ctypes.c_int64
